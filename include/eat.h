@@ -1,0 +1,231 @@
+/*
+ * eat.h -- C ABI of libeat: earliest-arrival-time (EAT) queries on public-
+ * transport timetables, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Haryan, Ramakrishna, Nasre, Reddy, "GPU Algorithm for Earliest
+ * Arrival Time Problem in Public Transport Networks", arXiv 1912.00966.
+ *   - the problem and its answer: Section I and Section I-A (a connection
+ *     (u, v, t, lam) leaves u at t and reaches v at t + lam; a query (s, ts)
+ *     asks for the earliest arrival at every stop over time-respecting paths
+ *     leaving s at or after ts);
+ *   - connection types (same u, v, lam) and the next departure at or after the
+ *     arrival at u: Section II-B;
+ *   - arithmetic-progression tuples and their closed form: Section II-C,
+ *     Algorithm 6;
+ *   - hourly clusters and the "next non-empty cluster" rule: Section II-D;
+ *   - edge grouping and (virtual) warps per edge: Sections II-E, II-F, IV-B;
+ *   - Relax and atomic minimum: Algorithm 3, Section III-C;
+ *   - double-buffered activity: Section III-B; convergence without per-
+ *     iteration host round trips: Section IV-C.
+ *
+ * General rules
+ *   - Every function returns an eat_status and never throws or aborts.  On
+ *     failure eat_last_error() returns a thread-local message.
+ *   - Host arrays passed in are only read during the call and may be freed on
+ *     return.  "device" pointers are HIP device allocations on the device that
+ *     was current when the graph was built.
+ *   - Times are int32 seconds, t >= 0, lam >= 1, t + lam <= EAT_INF - 1.
+ *     Unreached stops get EAT_INF.  The answer is unique, so results are
+ *     bit-identical whatever the layout, launch shape or batching.
+ *   - Streams are hipStream_t passed as void* (NULL = the null stream).
+ */
+#ifndef EAT_H
+#define EAT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EAT_INF INT32_MAX
+
+typedef enum {
+  EAT_OK = 0,
+  EAT_ERR_INVALID_ARGUMENT = 1, /* bad pointer, size, id or connection value */
+  EAT_ERR_OUT_OF_MEMORY = 2,    /* host or device allocation failed */
+  EAT_ERR_DEVICE = 3,           /* a HIP call failed, or no usable GPU */
+  EAT_ERR_NOT_CONVERGED = 4,    /* a query hit its round limit */
+  EAT_ERR_BUSY = 5,             /* no free result slot (serving sessions) */
+  EAT_ERR_UNSUPPORTED = 6       /* valid input outside this build's limits */
+} eat_status;
+
+typedef enum {
+  /* types -> clusters of cluster_seconds -> one arithmetic-progression
+   * descriptor per cluster, or a sorted departure array when the cluster's
+   * departures are not a single progression (Sections II-B..II-D) */
+  EAT_LAYOUT_HYBRID = 0,
+  /* types -> one sorted departure array per type, searched by bisection */
+  EAT_LAYOUT_FLAT = 1
+} eat_layout_kind;
+
+typedef struct {
+  int32_t layout;          /* eat_layout_kind; default EAT_LAYOUT_HYBRID */
+  int32_t cluster_seconds; /* cluster width in seconds, 1..32767; 0 = 3600 (one hour) */
+  int32_t n_threads;       /* host threads for preprocessing; 0 = all cores */
+  int32_t reserved[5];     /* must be zero */
+} eat_build_options;
+
+typedef struct {
+  int32_t n_vertices;
+  int32_t layout;
+  int32_t cluster_seconds;
+  int32_t n_clusters;        /* clusters per type: max departure / width + 1 (hybrid: <= 64) */
+  int32_t max_departure;
+  int32_t max_types_per_vertex;
+  int64_t n_conn_input;      /* connections passed in */
+  int64_t n_self_loops;      /* dropped: u == v can never improve an arrival */
+  int64_t n_duplicates;      /* dropped: identical (u, v, t, lam) */
+  int64_t n_conn;            /* connections kept */
+  int64_t n_edges;           /* distinct (u, v) */
+  int64_t n_types;           /* distinct (u, v, lam) */
+  int64_t n_headers;         /* non-empty (type, cluster) pairs (hybrid) */
+  int64_t n_ap_clusters;     /* ... stored as one progression */
+  int64_t n_array_clusters;  /* ... stored as a sorted array */
+  int64_t n_pool;            /* int32 words of the departure pool */
+  int64_t device_bytes;      /* device memory held by the graph */
+} eat_graph_info_t;
+
+/* ---------------------------------------------------------------------------
+ * Host layout (CPU only; needs no GPU).  The preprocessing of Section III-A:
+ * connections are grouped by tail u, then by (v, lam) into connection types,
+ * then each type's departures into clusters of cluster_seconds.
+ * ------------------------------------------------------------------------- */
+typedef struct eat_layout eat_layout;
+
+/* Read-only view of a host layout; pointers stay valid until eat_layout_free.
+ *   vt_off[n_vertices + 1]: the types leaving u are vt_off[u] .. vt_off[u+1]-1,
+ *     ordered by (v, lam).
+ *   ty[4 * n_types]: per type {v, lam, a, b}.  Hybrid: a = index of the type's
+ *     first cluster header, b = bits 0..31 of its cluster-occupancy mask (bit k
+ *     set when cluster k holds a departure).  Flat: a = offset of its
+ *     departures in pool, b = their count.
+ *   ty_mask_hi[n_types]: hybrid, bits 32..63 of the occupancy mask.
+ *   hdr[2 * n_headers]: hybrid, per non-empty cluster in (type, cluster) order
+ *     {t0, c}: t0 = first departure of the cluster; c >= 0 encodes the
+ *     progression t0 + i*h, i = 0..n-1 as c = (n << 16) | h; c < 0 encodes a
+ *     sorted array at pool[~c]: pool[~c] = n, pool[~c + 1 ..] = departures.
+ *   pool[n_pool]: hybrid array clusters, or flat departures. */
+typedef struct {
+  int32_t layout;
+  int32_t n_vertices;
+  int32_t cluster_seconds;
+  int32_t n_clusters;
+  int64_t n_types;
+  int64_t n_headers;
+  int64_t n_pool;
+  const int32_t *vt_off;
+  const int32_t *ty;
+  const uint32_t *ty_mask_hi;
+  const int32_t *hdr;
+  const int32_t *pool;
+} eat_layout_view;
+
+/* Validates and preprocesses n_conn connections (u, v, t, lam host arrays).
+ * Self-loops and exact duplicates are dropped.  opt may be NULL (defaults).
+ * EAT_ERR_INVALID_ARGUMENT for out-of-range ids or times, lam < 1 or
+ * t + lam > EAT_INF - 1; EAT_ERR_UNSUPPORTED when the hybrid layout would need
+ * more than 64 clusters per type, or more than 2^31-1 types or pool words. */
+eat_status eat_layout_build(const int32_t *u, const int32_t *v, const int32_t *t,
+                            const int32_t *lam, int64_t n_conn, int32_t n_vertices,
+                            const eat_build_options *opt, eat_layout **out);
+void eat_layout_free(eat_layout *layout); /* NULL-safe */
+eat_status eat_layout_info(const eat_layout *layout, eat_graph_info_t *out);
+eat_status eat_layout_view_get(const eat_layout *layout, eat_layout_view *out);
+
+/* ---------------------------------------------------------------------------
+ * Device-resident graph
+ * ------------------------------------------------------------------------- */
+typedef struct eat_graph eat_graph;
+
+/* Preprocesses (as eat_layout_build) and uploads to the current HIP device.
+ * The graph is immutable afterwards; queries on several streams may share it. */
+eat_status eat_graph_build(const int32_t *u, const int32_t *v, const int32_t *t,
+                           const int32_t *lam, int64_t n_conn, int32_t n_vertices,
+                           const eat_build_options *opt, eat_graph **out);
+/* Uploads an existing host layout (the layout may be freed afterwards). */
+eat_status eat_graph_upload(const eat_layout *layout, eat_graph **out);
+void eat_graph_free(eat_graph *g); /* NULL-safe; waits for the device */
+eat_status eat_graph_info(const eat_graph *g, eat_graph_info_t *out);
+
+/* ---------------------------------------------------------------------------
+ * Queries
+ * ------------------------------------------------------------------------- */
+typedef enum {
+  EAT_MODE_AUTO = 0,     /* frontier-driven; topology sweep when a frontier overflows */
+  EAT_MODE_FRONTIER = 1, /* same as AUTO */
+  EAT_MODE_TOPOLOGY = 2  /* every round sweeps the activity bitmap of all stops */
+} eat_mode;
+
+typedef struct {
+  int32_t threads_per_vertex; /* lanes sharing one active stop's types: 1,2,4,..,64; 0 = auto */
+  int32_t mode;               /* eat_mode */
+  int32_t max_rounds;         /* round limit per query; 0 = n_vertices + 2 */
+  int32_t frontier_cap;       /* frontier list entries kept on chip; 0 = auto */
+  int32_t reserved[4];        /* must be zero */
+} eat_run_options;
+
+typedef struct {
+  int32_t status;        /* EAT_OK or EAT_ERR_NOT_CONVERGED */
+  int32_t rounds;        /* relaxation rounds until no arrival improved */
+  int32_t sweep_rounds;  /* of which topology sweeps */
+  int32_t max_frontier;  /* largest frontier (capped at frontier_cap + 1) */
+  int64_t activations;   /* active stops processed */
+  int64_t type_evals;    /* connection types examined */
+  int64_t header_loads;  /* cluster headers read (hybrid) */
+  int64_t pool_loads;    /* departure words read from the pool */
+  int64_t improvements;  /* successful atomic minimum updates */
+} eat_query_stats;
+
+/* One query (s, ts) on g.  arr: device, >= n_vertices int32, caller-owned;
+ * it receives the earliest arrival times.  Asynchronous on stream when stats
+ * is NULL; with stats (host pointer) the call waits for the stream, fills it
+ * and returns EAT_ERR_NOT_CONVERGED if the round limit was hit.
+ * EAT_ERR_INVALID_ARGUMENT (arr untouched) for s outside [0, n_vertices),
+ * ts < 0 or arr NULL. */
+eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32_t *arr,
+                     void *stream, const eat_run_options *ro, eat_query_stats *stats);
+
+/* A prepared batch of n_q queries over n_graphs graphs, run by one persistent
+ * launch in which each work-group takes whole queries from a shared counter.
+ * q_graph/q_src/q_ts: host arrays; arr: host array of n_q device pointers, slab
+ * i holding >= n_vertices(graphs[q_graph[i]]) int32.  Descriptors are copied to
+ * the device during create; graphs and slabs must outlive the batch. */
+typedef struct eat_batch eat_batch;
+eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n_graphs,
+                            const int32_t *q_graph, const int32_t *q_src,
+                            const int32_t *q_ts, int32_t n_q, int32_t *const *arr,
+                            const eat_run_options *ro, eat_batch **out);
+/* Enqueues the whole batch on stream (asynchronous; repeatable). */
+eat_status eat_batch_run(eat_batch *b, void *stream);
+/* Waits for the last run and copies per-query stats (host array of n_q,
+ * nullable); returns EAT_ERR_NOT_CONVERGED if any query hit its limit. */
+eat_status eat_batch_wait(eat_batch *b, eat_query_stats *stats);
+void eat_batch_free(eat_batch *b); /* NULL-safe; waits for the last run */
+
+/* create + run + wait + free.  Returns after the batch has finished. */
+eat_status eat_query_batch(const eat_graph *const *graphs, int32_t n_graphs,
+                           const int32_t *q_graph, const int32_t *q_src,
+                           const int32_t *q_ts, int32_t n_q, int32_t *const *arr,
+                           void *stream, const eat_run_options *ro,
+                           eat_query_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Diagnostics
+ * ------------------------------------------------------------------------- */
+/* For each probe i: out[i] = the first departure >= x[i] of connection type
+ * type_ids[i] (Section II-B), or EAT_INF, computed on the GPU by the same
+ * device function the relaxation uses.  All three arrays are device arrays of
+ * n int32.  Asynchronous on stream. */
+eat_status eat_next_departure(const eat_graph *g, const int32_t *type_ids,
+                              const int32_t *x, int32_t *out, int32_t n, void *stream);
+
+const char *eat_status_string(eat_status s);
+const char *eat_last_error(void);
+/* Library version as major * 10000 + minor * 100 + patch. */
+int32_t eat_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EAT_H */

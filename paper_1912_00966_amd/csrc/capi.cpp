@@ -1,0 +1,544 @@
+// capi.cpp -- the C ABI of libeat (declared in include/eat.h): graph objects,
+// single queries, prepared batches, diagnostics and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "eat.h"
+#include "layout.hpp"
+
+using eat::GraphDev;
+using eat::QueryDev;
+using eat::RunArgs;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+eat_status set_err(eat_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+eat_status hip_err(hipError_t e, const char *what) {
+  return set_err(EAT_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                   \
+  do {                                                  \
+    hipError_t e_ = (call);                             \
+    if (e_ != hipSuccess) return hip_err(e_, #call);    \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct DeviceLimits {
+  int cus = 0;
+  size_t lds = 0;
+};
+
+eat_status device_limits(int dev, DeviceLimits *out) {
+  hipDeviceProp_t p;
+  HIP_TRY(hipGetDeviceProperties(&p, dev));
+  out->cus = p.multiProcessorCount;
+  out->lds = p.sharedMemPerBlock;
+  return EAT_OK;
+}
+
+int auto_tpv(int64_t n_types, int32_t n_vertices) {
+  // one lane per type of an average stop, rounded up to a power of two
+  double avg = n_vertices > 0 ? (double)n_types / (double)n_vertices : 1.0;
+  int t = 1;
+  while (t < 64 && t < avg) t <<= 1;
+  return t;
+}
+
+bool valid_tpv(int t) { return t == 1 || t == 2 || t == 4 || t == 8 || t == 16 || t == 32 || t == 64; }
+
+}  // namespace
+
+struct eat_graph {
+  int device = 0;
+  eat_graph_info_t info{};
+  GraphDev desc{};            // device pointers
+  GraphDev *d_desc = nullptr; // device copy of desc
+  void *d_buf = nullptr;
+  std::mutex mu;              // guards the single-query scratch
+  eat_query_stats *d_stats = nullptr;
+  int32_t *d_failed = nullptr;
+};
+
+struct eat_batch {
+  int device = 0;
+  int32_t n_q = 0;
+  int tpv = 0, kind = 0, grid = 0;
+  size_t lds = 0;
+  RunArgs args{};
+  void *d_buf = nullptr;
+  hipEvent_t done = nullptr;
+  bool ran = false;
+};
+
+// ---------------------------------------------------------------------------
+// status / version
+// ---------------------------------------------------------------------------
+extern "C" const char *eat_status_string(eat_status s) {
+  switch (s) {
+    case EAT_OK: return "ok";
+    case EAT_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case EAT_ERR_OUT_OF_MEMORY: return "out of memory";
+    case EAT_ERR_DEVICE: return "device error";
+    case EAT_ERR_NOT_CONVERGED: return "not converged";
+    case EAT_ERR_BUSY: return "busy";
+    case EAT_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+extern "C" const char *eat_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" int32_t eat_version(void) { return 100; }
+
+// ---------------------------------------------------------------------------
+// host layout
+// ---------------------------------------------------------------------------
+static void fill_info(const eat_layout &L, eat_graph_info_t *o) {
+  std::memset(o, 0, sizeof(*o));
+  o->n_vertices = L.n_vertices;
+  o->layout = L.kind;
+  o->cluster_seconds = L.cluster_seconds;
+  o->n_clusters = L.n_clusters;
+  o->max_departure = L.max_departure;
+  o->max_types_per_vertex = L.max_types_per_vertex;
+  o->n_conn_input = L.n_conn_input;
+  o->n_self_loops = L.n_self_loops;
+  o->n_duplicates = L.n_duplicates;
+  o->n_conn = L.n_conn;
+  o->n_edges = L.n_edges;
+  o->n_types = L.n_types;
+  o->n_headers = L.n_headers;
+  o->n_ap_clusters = L.n_ap;
+  o->n_array_clusters = L.n_array;
+  o->n_pool = (int64_t)L.pool.size();
+}
+
+extern "C" eat_status eat_layout_build(const int32_t *u, const int32_t *v, const int32_t *t,
+                                       const int32_t *lam, int64_t n_conn, int32_t n_vertices,
+                                       const eat_build_options *opt, eat_layout **out) {
+  if (!out) return set_err(EAT_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  eat_build_options o{};
+  if (opt) o = *opt;
+  eat_layout *L = new (std::nothrow) eat_layout();
+  if (!L) return set_err(EAT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  std::string err;
+  eat_status s;
+  try {
+    s = eat::build_layout(u, v, t, lam, n_conn, n_vertices, o, *L, &err);
+  } catch (const std::bad_alloc &) {
+    s = EAT_ERR_OUT_OF_MEMORY;
+    err = "host allocation failed";
+  }
+  if (s != EAT_OK) {
+    delete L;
+    return set_err(s, err);
+  }
+  *out = L;
+  return EAT_OK;
+}
+
+extern "C" void eat_layout_free(eat_layout *layout) { delete layout; }
+
+extern "C" eat_status eat_layout_info(const eat_layout *layout, eat_graph_info_t *out) {
+  if (!layout || !out) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL argument");
+  fill_info(*layout, out);
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_layout_view_get(const eat_layout *L, eat_layout_view *out) {
+  if (!L || !out) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL argument");
+  out->layout = L->kind;
+  out->n_vertices = L->n_vertices;
+  out->cluster_seconds = L->cluster_seconds;
+  out->n_clusters = L->n_clusters;
+  out->n_types = L->n_types;
+  out->n_headers = L->n_headers;
+  out->n_pool = (int64_t)L->pool.size();
+  out->vt_off = L->vt_off.data();
+  out->ty = L->ty.data();
+  out->ty_mask_hi = L->kind == EAT_LAYOUT_HYBRID ? L->mask_hi.data() : nullptr;
+  out->hdr = L->kind == EAT_LAYOUT_HYBRID ? L->hdr.data() : nullptr;
+  out->pool = L->pool.data();
+  return EAT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device graph
+// ---------------------------------------------------------------------------
+extern "C" eat_status eat_graph_upload(const eat_layout *L, eat_graph **out) {
+  if (!L || !out) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL argument");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+    return set_err(EAT_ERR_DEVICE, "no HIP device available");
+  eat_graph *g = new (std::nothrow) eat_graph();
+  if (!g) return set_err(EAT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  HIP_TRY(hipGetDevice(&g->device));
+  fill_info(*L, &g->info);
+
+  const bool hybrid = L->kind == EAT_LAYOUT_HYBRID;
+  const bool need_hi = hybrid && L->n_clusters > 32;
+  const int64_t T = L->n_types;
+  const size_t b_vt = align_up(L->vt_off.size() * 4);
+  const size_t b_ty = align_up((size_t)std::max<int64_t>(T, 1) * 16);
+  const size_t b_hi = need_hi ? align_up((size_t)std::max<int64_t>(T, 1) * 4) : 0;
+  const size_t b_hdr = hybrid ? align_up((size_t)(L->n_headers + 1) * 8) : 0;
+  const size_t b_pool = align_up(std::max<size_t>(L->pool.size(), 1) * 4);
+  const size_t b_desc = align_up(sizeof(GraphDev));
+  const size_t b_stats = align_up(sizeof(eat_query_stats)) + align_up(4);
+  const size_t total = b_vt + b_ty + b_hi + b_hdr + b_pool + b_desc + b_stats;
+  hipError_t e = hipMalloc(&g->d_buf, total);
+  if (e != hipSuccess) {
+    delete g;
+    return set_err(EAT_ERR_OUT_OF_MEMORY, std::string("hipMalloc of the graph failed: ") + hipGetErrorString(e));
+  }
+  char *p = static_cast<char *>(g->d_buf);
+  auto take = [&](size_t b) {
+    char *q = p;
+    p += b;
+    return q;
+  };
+  g->desc.vt_off = reinterpret_cast<const int32_t *>(take(b_vt));
+  g->desc.ty = reinterpret_cast<const int4 *>(take(b_ty));
+  g->desc.mask_hi = need_hi ? reinterpret_cast<const uint32_t *>(take(b_hi)) : nullptr;
+  g->desc.hdr = hybrid ? reinterpret_cast<const int2 *>(take(b_hdr)) : nullptr;
+  g->desc.pool = reinterpret_cast<const int32_t *>(take(b_pool));
+  g->d_desc = reinterpret_cast<GraphDev *>(take(b_desc));
+  g->d_stats = reinterpret_cast<eat_query_stats *>(take(align_up(sizeof(eat_query_stats))));
+  g->d_failed = reinterpret_cast<int32_t *>(take(align_up(4)));
+  g->desc.n_types = T;
+  g->desc.n_vertices = L->n_vertices;
+  g->desc.cluster_seconds = L->cluster_seconds;
+  g->desc.n_clusters = L->n_clusters;
+  g->desc.kind = L->kind;
+  g->info.device_bytes = (int64_t)total;
+
+  auto up = [&](const void *dst, const void *src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpy(const_cast<void *>(dst), src, bytes, hipMemcpyHostToDevice);
+  };
+  hipError_t ue = hipSuccess;
+  if (ue == hipSuccess) ue = up(g->desc.vt_off, L->vt_off.data(), L->vt_off.size() * 4);
+  if (ue == hipSuccess) ue = up(g->desc.ty, L->ty.data(), (size_t)T * 16);
+  if (ue == hipSuccess && need_hi) ue = up(g->desc.mask_hi, L->mask_hi.data(), (size_t)T * 4);
+  if (ue == hipSuccess && hybrid) {
+    ue = up(g->desc.hdr, L->hdr.data(), (size_t)L->n_headers * 8);
+    if (ue == hipSuccess) ue = hipMemset(const_cast<int2 *>(g->desc.hdr) + L->n_headers, 0, 8);
+  }
+  if (ue == hipSuccess) ue = up(g->desc.pool, L->pool.data(), L->pool.size() * 4);
+  if (ue == hipSuccess) ue = up(g->d_desc, &g->desc, sizeof(GraphDev));
+  if (ue == hipSuccess) ue = hipDeviceSynchronize();
+  if (ue != hipSuccess) {
+    (void)hipFree(g->d_buf);
+    delete g;
+    return hip_err(ue, "graph upload");
+  }
+  *out = g;
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_graph_build(const int32_t *u, const int32_t *v, const int32_t *t,
+                                      const int32_t *lam, int64_t n_conn, int32_t n_vertices,
+                                      const eat_build_options *opt, eat_graph **out) {
+  if (!out) return set_err(EAT_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  eat_layout *L = nullptr;
+  eat_status s = eat_layout_build(u, v, t, lam, n_conn, n_vertices, opt, &L);
+  if (s != EAT_OK) return s;
+  s = eat_graph_upload(L, out);
+  eat_layout_free(L);
+  return s;
+}
+
+extern "C" void eat_graph_free(eat_graph *g) {
+  if (!g) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(g->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(g->d_buf);
+  (void)hipSetDevice(cur);
+  delete g;
+}
+
+extern "C" eat_status eat_graph_info(const eat_graph *g, eat_graph_info_t *out) {
+  if (!g || !out) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL argument");
+  *out = g->info;
+  return EAT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// run options
+// ---------------------------------------------------------------------------
+struct Plan {
+  int tpv = 1;
+  int mode = EAT_MODE_AUTO;
+  int max_rounds = 0;
+  int fcap = 0;
+  int bm_words = 0;
+  size_t lds = 0;
+};
+
+static eat_status make_plan(const eat_run_options *ro, int32_t max_v, int64_t n_types_sum,
+                            int64_t n_vertices_sum, int device, Plan *pl) {
+  eat_run_options o{};
+  if (ro) o = *ro;
+  for (int r : o.reserved)
+    if (r != 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "reserved run options must be zero");
+  if (o.mode < EAT_MODE_AUTO || o.mode > EAT_MODE_TOPOLOGY) return set_err(EAT_ERR_INVALID_ARGUMENT, "unknown mode");
+  if (o.max_rounds < 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "max_rounds must be >= 0");
+  if (o.threads_per_vertex != 0 && !valid_tpv(o.threads_per_vertex))
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_vertex must be 0 or a power of two up to 64");
+  if (o.frontier_cap < 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "frontier_cap must be >= 0");
+  pl->tpv = o.threads_per_vertex ? o.threads_per_vertex
+                                 : auto_tpv(n_types_sum, (int32_t)std::min<int64_t>(n_vertices_sum, INT32_MAX));
+  pl->mode = o.mode;
+  pl->max_rounds = o.max_rounds;
+  pl->bm_words = (max_v + 31) / 32;
+  int fcap = o.frontier_cap ? o.frontier_cap : 4096;
+  fcap = (fcap + 31) / 32 * 32;
+  fcap = std::min(fcap, std::max(32, (max_v + 31) / 32 * 32));
+  pl->fcap = fcap;
+  pl->lds = (size_t)pl->bm_words * 4 + (size_t)fcap * 8;
+  DeviceLimits lim;
+  eat_status s = device_limits(device, &lim);
+  if (s != EAT_OK) return s;
+  if (pl->lds > lim.lds)
+    return set_err(EAT_ERR_UNSUPPORTED, "graph too large for the on-chip activity bitmap (" +
+                                            std::to_string(pl->lds) + " bytes of LDS needed, " +
+                                            std::to_string(lim.lds) + " available)");
+  return EAT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// single query
+// ---------------------------------------------------------------------------
+extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32_t *arr,
+                                void *stream, const eat_run_options *ro, eat_query_stats *stats) {
+  if (!g) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (!arr) return set_err(EAT_ERR_INVALID_ARGUMENT, "arr is NULL");
+  if (s < 0 || s >= g->info.n_vertices) return set_err(EAT_ERR_INVALID_ARGUMENT, "source out of range");
+  if (ts < 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "ts must be >= 0");
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != g->device) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph lives on another device than the current one");
+  Plan pl;
+  eat_status st = make_plan(ro, g->info.n_vertices, g->info.n_types, g->info.n_vertices, g->device, &pl);
+  if (st != EAT_OK) return st;
+  RunArgs a{};
+  a.graphs = g->d_desc;
+  a.queries = nullptr;
+  a.single = QueryDev{0, s, ts, 0, arr};
+  a.nq = 1;
+  a.max_rounds = pl.max_rounds;
+  a.mode = pl.mode;
+  a.fcap = pl.fcap;
+  a.bm_words = pl.bm_words;
+  a.work = nullptr;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  eat_graph *gm = const_cast<eat_graph *>(g);
+  if (!stats) {
+    a.stats = nullptr;
+    a.n_failed = nullptr;
+    hipError_t e = eat::launch_relax(a, pl.tpv, g->info.layout, 1, pl.lds, hs);
+    if (e != hipSuccess) return hip_err(e, "relaxation launch");
+    return EAT_OK;
+  }
+  std::lock_guard<std::mutex> lk(gm->mu);
+  a.stats = gm->d_stats;
+  a.n_failed = nullptr;
+  hipError_t e = eat::launch_relax(a, pl.tpv, g->info.layout, 1, pl.lds, hs);
+  if (e != hipSuccess) return hip_err(e, "relaxation launch");
+  HIP_TRY(hipMemcpyAsync(stats, gm->d_stats, sizeof(eat_query_stats), hipMemcpyDeviceToHost, hs));
+  HIP_TRY(hipStreamSynchronize(hs));
+  if (stats->status != EAT_OK) return set_err(EAT_ERR_NOT_CONVERGED, "query hit its round limit");
+  return EAT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batches
+// ---------------------------------------------------------------------------
+extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n_graphs,
+                                       const int32_t *q_graph, const int32_t *q_src,
+                                       const int32_t *q_ts, int32_t n_q, int32_t *const *arr,
+                                       const eat_run_options *ro, eat_batch **out) {
+  if (!out) return set_err(EAT_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (!graphs || n_graphs < 1) return set_err(EAT_ERR_INVALID_ARGUMENT, "need at least one graph");
+  if (n_q < 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "n_q must be >= 0");
+  if (n_q > 0 && (!q_graph || !q_src || !q_ts || !arr))
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL query array");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  int kind = -1;
+  int32_t max_v = 1;
+  for (int32_t i = 0; i < n_graphs; ++i) {
+    if (!graphs[i]) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph " + std::to_string(i) + " is NULL");
+    if (graphs[i]->device != dev)
+      return set_err(EAT_ERR_INVALID_ARGUMENT, "graph " + std::to_string(i) + " lives on another device");
+    if (kind < 0) kind = graphs[i]->info.layout;
+    if (graphs[i]->info.layout != kind)
+      return set_err(EAT_ERR_UNSUPPORTED, "all graphs of one batch must share a layout kind");
+  }
+  std::vector<QueryDev> qs((size_t)n_q);
+  int64_t types_sum = 0, verts_sum = 0;
+  for (int32_t i = 0; i < n_q; ++i) {
+    const int32_t gi = q_graph[i];
+    if (gi < 0 || gi >= n_graphs) return set_err(EAT_ERR_INVALID_ARGUMENT, "query " + std::to_string(i) + ": graph index out of range");
+    const eat_graph *g = graphs[gi];
+    if (q_src[i] < 0 || q_src[i] >= g->info.n_vertices)
+      return set_err(EAT_ERR_INVALID_ARGUMENT, "query " + std::to_string(i) + ": source out of range");
+    if (q_ts[i] < 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "query " + std::to_string(i) + ": ts < 0");
+    if (!arr[i]) return set_err(EAT_ERR_INVALID_ARGUMENT, "query " + std::to_string(i) + ": arr is NULL");
+    qs[(size_t)i] = QueryDev{gi, q_src[i], q_ts[i], i, arr[i]};
+    max_v = std::max(max_v, g->info.n_vertices);
+    types_sum += g->info.n_types;
+    verts_sum += g->info.n_vertices;
+  }
+  // Larger graphs first: the longest queries start first and the tail is short.
+  std::stable_sort(qs.begin(), qs.end(), [&](const QueryDev &a, const QueryDev &b) {
+    return graphs[a.graph]->info.n_vertices > graphs[b.graph]->info.n_vertices;
+  });
+  Plan pl;
+  eat_status st = make_plan(ro, max_v, std::max<int64_t>(types_sum, 1), std::max<int64_t>(verts_sum, 1), dev, &pl);
+  if (st != EAT_OK) return st;
+
+  eat_batch *b = new (std::nothrow) eat_batch();
+  if (!b) return set_err(EAT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  b->device = dev;
+  b->n_q = n_q;
+  b->tpv = pl.tpv;
+  b->kind = kind;
+  b->lds = pl.lds;
+  const size_t b_g = align_up((size_t)n_graphs * sizeof(GraphDev));
+  const size_t b_q = align_up(std::max<size_t>((size_t)n_q, 1) * sizeof(QueryDev));
+  const size_t b_s = align_up(std::max<size_t>((size_t)n_q, 1) * sizeof(eat_query_stats));
+  const size_t b_c = align_up(4 * sizeof(int32_t));
+  hipError_t e = hipMalloc(&b->d_buf, b_g + b_q + b_s + b_c);
+  if (e != hipSuccess) {
+    delete b;
+    return set_err(EAT_ERR_OUT_OF_MEMORY, "hipMalloc of the batch failed");
+  }
+  char *p = static_cast<char *>(b->d_buf);
+  GraphDev *d_g = reinterpret_cast<GraphDev *>(p);
+  QueryDev *d_q = reinterpret_cast<QueryDev *>(p + b_g);
+  eat_query_stats *d_s = reinterpret_cast<eat_query_stats *>(p + b_g + b_q);
+  int32_t *d_c = reinterpret_cast<int32_t *>(p + b_g + b_q + b_s);
+  std::vector<GraphDev> gd((size_t)n_graphs);
+  for (int32_t i = 0; i < n_graphs; ++i) gd[(size_t)i] = graphs[i]->desc;
+  e = hipMemcpy(d_g, gd.data(), gd.size() * sizeof(GraphDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess && n_q > 0) e = hipMemcpy(d_q, qs.data(), qs.size() * sizeof(QueryDev), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(d_s, 0, b_s + b_c);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipFree(b->d_buf);
+    delete b;
+    return hip_err(e, "batch upload");
+  }
+  DeviceLimits lim;
+  st = device_limits(dev, &lim);
+  if (st != EAT_OK) {
+    (void)hipFree(b->d_buf);
+    (void)hipEventDestroy(b->done);
+    delete b;
+    return st;
+  }
+  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, kind, pl.lds));
+  b->grid = std::max(1, std::min<int>(n_q, lim.cus * per_cu));
+  RunArgs &a = b->args;
+  a.graphs = d_g;
+  a.queries = d_q;
+  a.nq = n_q;
+  a.max_rounds = pl.max_rounds;
+  a.mode = pl.mode;
+  a.fcap = pl.fcap;
+  a.bm_words = pl.bm_words;
+  a.work = d_c;
+  a.stats = d_s;
+  a.n_failed = d_c + 2;
+  *out = b;
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_batch_run(eat_batch *b, void *stream) {
+  if (!b) return set_err(EAT_ERR_INVALID_ARGUMENT, "batch is NULL");
+  if (b->n_q == 0) return EAT_OK;
+  hipStream_t hs = static_cast<hipStream_t>(stream);
+  hipError_t e = eat::launch_relax(b->args, b->tpv, b->kind, b->grid, b->lds, hs);
+  if (e != hipSuccess) return hip_err(e, "relaxation launch");
+  HIP_TRY(hipEventRecord(b->done, hs));
+  b->ran = true;
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_batch_wait(eat_batch *b, eat_query_stats *stats) {
+  if (!b) return set_err(EAT_ERR_INVALID_ARGUMENT, "batch is NULL");
+  if (!b->ran) {
+    if (stats && b->n_q > 0) std::memset(stats, 0, sizeof(eat_query_stats) * (size_t)b->n_q);
+    return EAT_OK;
+  }
+  HIP_TRY(hipEventSynchronize(b->done));
+  int32_t failed = 0;
+  HIP_TRY(hipMemcpy(&failed, b->args.work + 3, 4, hipMemcpyDeviceToHost));
+  if (stats && b->n_q > 0)
+    HIP_TRY(hipMemcpy(stats, b->args.stats, sizeof(eat_query_stats) * (size_t)b->n_q, hipMemcpyDeviceToHost));
+  if (failed) return set_err(EAT_ERR_NOT_CONVERGED, std::to_string(failed) + " queries hit their round limit");
+  return EAT_OK;
+}
+
+extern "C" void eat_batch_free(eat_batch *b) {
+  if (!b) return;
+  if (b->ran) (void)hipEventSynchronize(b->done);
+  if (b->done) (void)hipEventDestroy(b->done);
+  (void)hipFree(b->d_buf);
+  delete b;
+}
+
+extern "C" eat_status eat_query_batch(const eat_graph *const *graphs, int32_t n_graphs,
+                                      const int32_t *q_graph, const int32_t *q_src,
+                                      const int32_t *q_ts, int32_t n_q, int32_t *const *arr,
+                                      void *stream, const eat_run_options *ro,
+                                      eat_query_stats *stats) {
+  eat_batch *b = nullptr;
+  eat_status s = eat_batch_create(graphs, n_graphs, q_graph, q_src, q_ts, n_q, arr, ro, &b);
+  if (s != EAT_OK) return s;
+  s = eat_batch_run(b, stream);
+  if (s == EAT_OK) s = eat_batch_wait(b, stats);
+  std::string keep = g_last_error;
+  eat_batch_free(b);
+  g_last_error = keep;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// diagnostics
+// ---------------------------------------------------------------------------
+extern "C" eat_status eat_next_departure(const eat_graph *g, const int32_t *type_ids, const int32_t *x,
+                                         int32_t *out, int32_t n, void *stream) {
+  if (!g) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph is NULL");
+  if (n < 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "n must be >= 0");
+  if (n > 0 && (!type_ids || !x || !out)) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL array");
+  hipError_t e = eat::launch_next_departure(g->d_desc, g->info.layout, type_ids, x, out, n,
+                                            static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_err(e, "next-departure launch");
+  return EAT_OK;
+}

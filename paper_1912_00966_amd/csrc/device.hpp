@@ -1,0 +1,67 @@
+// device.hpp -- descriptors shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "eat.h"
+
+namespace eat {
+
+// One device-resident timetable (see eat_layout_view in eat.h for the arrays).
+struct GraphDev {
+  const int32_t *vt_off;   // [V+1]
+  const int4 *ty;          // [T] {v, lam, a, b}
+  const uint32_t *mask_hi; // [T] hybrid, or nullptr when every cluster index < 32
+  const int2 *hdr;         // [K + 1] hybrid (one padding entry)
+  const int32_t *pool;     // departures
+  int64_t n_types;
+  int32_t n_vertices;
+  int32_t cluster_seconds;
+  int32_t n_clusters;
+  int32_t kind;            // eat_layout_kind
+  int32_t pad_;
+};
+
+// One query: the graph index, the source, the departure time, the caller's
+// result slab, and the query's index in the caller's order (for its stats).
+struct QueryDev {
+  int32_t graph;
+  int32_t s;
+  int32_t ts;
+  int32_t index;
+  int32_t *arr;
+};
+
+// Arguments of one launch of the relaxation kernel.
+struct RunArgs {
+  const GraphDev *graphs;    // device array
+  const QueryDev *queries;   // device array of nq, or nullptr: use `single`
+  QueryDev single;           // the one query when queries == nullptr
+  int32_t nq;
+  int32_t max_rounds;        // 0: n_vertices + 2 of the query's graph
+  int32_t mode;              // eat_mode
+  int32_t fcap;              // frontier list capacity (entries, multiple of 32)
+  int32_t bm_words;          // activity bitmap words (>= ceil(V / 32) of every graph)
+  // Batch counters (batch only; zero before the first launch, re-armed by the
+  // last work-group of every launch): [0] next query, [1] work-groups done,
+  // [2] queries of this launch that hit the round limit, [3] that count for
+  // the previous completed launch.
+  int32_t *work;
+  eat_query_stats *stats;    // per query, indexed by QueryDev::index; nullable
+  int32_t *n_failed;         // == work + 2 in a batch; nullable
+};
+
+constexpr int kBlock = 256;
+
+// Host-side launchers (kernels.hip).
+hipError_t launch_relax(const RunArgs &a, int tpv, int kind, int grid, size_t lds_bytes,
+                        hipStream_t stream);
+hipError_t launch_zero(int32_t *p, int n, hipStream_t stream);
+hipError_t launch_next_departure(const GraphDev *g_dev, int kind, const int32_t *type_ids,
+                                 const int32_t *x, int32_t *out, int32_t n, hipStream_t stream);
+// Work-groups of the relaxation kernel that fit on one CU with lds_bytes of LDS.
+int relax_blocks_per_cu(int tpv, int kind, size_t lds_bytes);
+
+}  // namespace eat

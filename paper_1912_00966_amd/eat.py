@@ -1,0 +1,398 @@
+"""Python binding of libeat (C ABI in include/eat.h).
+
+Argument marshalling only: every step of a query runs in the library's HIP
+kernels.  PyTorch provides device memory (result slabs, probe arrays) and the
+stream a call is enqueued on.  The names follow the C ABI (``eat_graph_build``,
+``eat_query``, ``eat_query_batch`` ...); ``Graph`` and ``Batch`` wrap the
+opaque handles.  If ``libeat.so`` is missing, every call raises: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libeat.so")
+EAT_INF = np.iinfo(np.int32).max
+
+EAT_OK = 0
+EAT_ERR_INVALID_ARGUMENT = 1
+EAT_ERR_OUT_OF_MEMORY = 2
+EAT_ERR_DEVICE = 3
+EAT_ERR_NOT_CONVERGED = 4
+EAT_ERR_BUSY = 5
+EAT_ERR_UNSUPPORTED = 6
+
+EAT_LAYOUT_HYBRID = 0
+EAT_LAYOUT_FLAT = 1
+EAT_MODE_AUTO = 0
+EAT_MODE_FRONTIER = 1
+EAT_MODE_TOPOLOGY = 2
+
+# every function include/eat.h declares
+EXPORTS = (
+    "eat_layout_build", "eat_layout_free", "eat_layout_info", "eat_layout_view_get",
+    "eat_graph_build", "eat_graph_upload", "eat_graph_free", "eat_graph_info",
+    "eat_query", "eat_batch_create", "eat_batch_run", "eat_batch_wait", "eat_batch_free",
+    "eat_query_batch", "eat_next_departure", "eat_status_string", "eat_last_error",
+    "eat_version",
+)
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_vp = ctypes.c_void_p
+
+
+class BuildOptions(ctypes.Structure):
+    _fields_ = [("layout", ctypes.c_int32), ("cluster_seconds", ctypes.c_int32),
+                ("n_threads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("cluster_seconds", ctypes.c_int32), ("n_clusters", ctypes.c_int32),
+                ("max_departure", ctypes.c_int32), ("max_types_per_vertex", ctypes.c_int32),
+                ("n_conn_input", ctypes.c_int64), ("n_self_loops", ctypes.c_int64),
+                ("n_duplicates", ctypes.c_int64), ("n_conn", ctypes.c_int64),
+                ("n_edges", ctypes.c_int64), ("n_types", ctypes.c_int64),
+                ("n_headers", ctypes.c_int64), ("n_ap_clusters", ctypes.c_int64),
+                ("n_array_clusters", ctypes.c_int64), ("n_pool", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class LayoutView(ctypes.Structure):
+    _fields_ = [("layout", ctypes.c_int32), ("n_vertices", ctypes.c_int32),
+                ("cluster_seconds", ctypes.c_int32), ("n_clusters", ctypes.c_int32),
+                ("n_types", ctypes.c_int64), ("n_headers", ctypes.c_int64),
+                ("n_pool", ctypes.c_int64), ("vt_off", _i32p), ("ty", _i32p),
+                ("ty_mask_hi", _u32p), ("hdr", _i32p), ("pool", _i32p)]
+
+
+class RunOptions(ctypes.Structure):
+    _fields_ = [("threads_per_vertex", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("max_rounds", ctypes.c_int32), ("frontier_cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class QueryStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("rounds", ctypes.c_int32),
+                ("sweep_rounds", ctypes.c_int32), ("max_frontier", ctypes.c_int32),
+                ("activations", ctypes.c_int64), ("type_evals", ctypes.c_int64),
+                ("header_loads", ctypes.c_int64), ("pool_loads", ctypes.c_int64),
+                ("improvements", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class EatError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libeat.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1912_00966_amd.build`"
+                           " (there is no non-GPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    conn = [_i32p, _i32p, _i32p, _i32p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(BuildOptions)]
+    L.eat_layout_build.argtypes = conn + [ctypes.POINTER(_vp)]
+    L.eat_layout_free.argtypes = [_vp]
+    L.eat_layout_free.restype = None
+    L.eat_layout_info.argtypes = [_vp, ctypes.POINTER(GraphInfo)]
+    L.eat_layout_view_get.argtypes = [_vp, ctypes.POINTER(LayoutView)]
+    L.eat_graph_build.argtypes = conn + [ctypes.POINTER(_vp)]
+    L.eat_graph_upload.argtypes = [_vp, ctypes.POINTER(_vp)]
+    L.eat_graph_free.argtypes = [_vp]
+    L.eat_graph_free.restype = None
+    L.eat_graph_info.argtypes = [_vp, ctypes.POINTER(GraphInfo)]
+    L.eat_query.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
+                            ctypes.POINTER(RunOptions), ctypes.POINTER(QueryStats)]
+    L.eat_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, _i32p, _i32p, _i32p,
+                                   ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(RunOptions),
+                                   ctypes.POINTER(_vp)]
+    L.eat_batch_run.argtypes = [_vp, _vp]
+    L.eat_batch_wait.argtypes = [_vp, ctypes.POINTER(QueryStats)]
+    L.eat_batch_free.argtypes = [_vp]
+    L.eat_batch_free.restype = None
+    L.eat_query_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, _i32p, _i32p, _i32p,
+                                  ctypes.c_int32, ctypes.POINTER(_vp), _vp,
+                                  ctypes.POINTER(RunOptions), ctypes.POINTER(QueryStats)]
+    L.eat_next_departure.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp]
+    L.eat_status_string.argtypes = [ctypes.c_int]
+    L.eat_status_string.restype = ctypes.c_char_p
+    L.eat_last_error.argtypes = []
+    L.eat_last_error.restype = ctypes.c_char_p
+    L.eat_version.argtypes = []
+    L.eat_version.restype = ctypes.c_int32
+    for name in EXPORTS:
+        f = getattr(L, name)
+        if name not in ("eat_layout_free", "eat_graph_free", "eat_batch_free", "eat_status_string",
+                        "eat_last_error", "eat_version"):
+            f.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != EAT_OK:
+        msg = lib().eat_last_error().decode(errors="replace")
+        raise EatError(status, msg or lib().eat_status_string(status).decode())
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _ptr32(a):
+    return a.ctypes.data_as(_i32p)
+
+
+def _build_opts(layout, cluster_seconds, n_threads):
+    o = BuildOptions()
+    o.layout = int(layout)
+    o.cluster_seconds = int(cluster_seconds)
+    o.n_threads = int(n_threads)
+    return o
+
+
+def _run_opts(options):
+    if options is None:
+        return None
+    if isinstance(options, RunOptions):
+        return options
+    o = RunOptions()
+    for k, v in dict(options).items():
+        setattr(o, k, int(v))
+    return o
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev_ptr(t, n_min: int, what: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32:
+        raise TypeError(f"{what} must be a CUDA int32 tensor")
+    if not t.is_contiguous() or t.numel() < n_min:
+        raise ValueError(f"{what} must be contiguous with at least {n_min} elements")
+    return t.data_ptr()
+
+
+# ---------------------------------------------------------------------------
+# host layout
+# ---------------------------------------------------------------------------
+class Layout:
+    """Host-side layout (eat_layout_build); needs no GPU."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    def info(self) -> GraphInfo:
+        gi = GraphInfo()
+        _check(lib().eat_layout_info(self._h, ctypes.byref(gi)))
+        return gi
+
+    def view(self) -> dict:
+        """Copies of the layout arrays as numpy arrays (see eat_layout_view)."""
+        lv = LayoutView()
+        _check(lib().eat_layout_view_get(self._h, ctypes.byref(lv)))
+
+        def take(p, n, dt=np.int32):
+            if n == 0 or not p:
+                return np.zeros(0, dtype=dt)
+            return np.ctypeslib.as_array(p, shape=(int(n),)).astype(dt, copy=True)
+
+        out = dict(layout=lv.layout, n_vertices=lv.n_vertices, cluster_seconds=lv.cluster_seconds,
+                   n_clusters=lv.n_clusters, n_types=lv.n_types, n_headers=lv.n_headers,
+                   n_pool=lv.n_pool)
+        out["vt_off"] = take(lv.vt_off, lv.n_vertices + 1)
+        out["ty"] = take(lv.ty, 4 * lv.n_types).reshape(-1, 4)
+        out["ty_mask_hi"] = take(lv.ty_mask_hi, lv.n_types if lv.ty_mask_hi else 0, np.uint32)
+        out["hdr"] = take(lv.hdr, 2 * lv.n_headers if lv.hdr else 0).reshape(-1, 2)
+        out["pool"] = take(lv.pool, lv.n_pool)
+        return out
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().eat_layout_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def eat_layout_build(u, v, t, lam, n_vertices, layout=EAT_LAYOUT_HYBRID, cluster_seconds=0,
+                     n_threads=0) -> Layout:
+    u, v, t, lam = (_i32(x) for x in (u, v, t, lam))
+    h = _vp()
+    o = _build_opts(layout, cluster_seconds, n_threads)
+    _check(lib().eat_layout_build(_ptr32(u), _ptr32(v), _ptr32(t), _ptr32(lam), len(u),
+                                  int(n_vertices), ctypes.byref(o), ctypes.byref(h)))
+    return Layout(h)
+
+
+# ---------------------------------------------------------------------------
+# device graphs and queries
+# ---------------------------------------------------------------------------
+class Graph:
+    """A device-resident timetable (eat_graph_build)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        gi = GraphInfo()
+        _check(lib().eat_graph_info(self._h, ctypes.byref(gi)))
+        self.info = gi
+        self.n_vertices = gi.n_vertices
+
+    @property
+    def handle(self):
+        return self._h
+
+    def query(self, s: int, ts: int, out=None, stream=None, options=None, stats: bool = False):
+        """Earliest arrival times from (s, ts) into `out` (a new CUDA int32 tensor
+        if None).  Returns out, or (out, stats dict) with stats=True."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n_vertices, dtype=torch.int32, device="cuda")
+        st = eat_query(self, s, ts, out, stream=stream, options=options, stats=stats)
+        return (out, st) if stats else out
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().eat_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def eat_graph_build(u, v, t, lam, n_vertices, layout=EAT_LAYOUT_HYBRID, cluster_seconds=0,
+                    n_threads=0) -> Graph:
+    u, v, t, lam = (_i32(x) for x in (u, v, t, lam))
+    h = _vp()
+    o = _build_opts(layout, cluster_seconds, n_threads)
+    _check(lib().eat_graph_build(_ptr32(u), _ptr32(v), _ptr32(t), _ptr32(lam), len(u),
+                                 int(n_vertices), ctypes.byref(o), ctypes.byref(h)))
+    return Graph(h)
+
+
+def eat_graph_upload(layout: Layout) -> Graph:
+    h = _vp()
+    _check(lib().eat_graph_upload(layout._h, ctypes.byref(h)))
+    return Graph(h)
+
+
+def graph_from_timetable(tt, layout=EAT_LAYOUT_HYBRID, cluster_seconds=0) -> Graph:
+    return eat_graph_build(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices, layout=layout,
+                           cluster_seconds=cluster_seconds)
+
+
+def eat_query(g: Graph, s: int, ts: int, arr, stream=None, options=None, stats: bool = False):
+    ptr = _dev_ptr(arr, g.n_vertices, "arr")
+    ro = _run_opts(options)
+    st = QueryStats() if stats else None
+    _check(lib().eat_query(g.handle, int(s), int(ts), ptr, _stream_handle(stream),
+                           ctypes.byref(ro) if ro is not None else None,
+                           ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
+
+
+class Batch:
+    """A prepared batch (eat_batch_create); run() enqueues all its queries in one launch."""
+
+    def __init__(self, graphs: Sequence[Graph], q_graph, q_src, q_ts, outs, options=None):
+        self.graphs = list(graphs)
+        q_graph, q_src, q_ts = _i32(q_graph), _i32(q_src), _i32(q_ts)
+        n = len(q_src)
+        if not (len(q_graph) == len(q_ts) == len(outs) == n):
+            raise ValueError("q_graph, q_src, q_ts and outs must have equal length")
+        gh = (_vp * len(self.graphs))(*[g.handle for g in self.graphs])
+        ptrs = []
+        for i in range(n):
+            gi = int(q_graph[i])
+            nv = self.graphs[gi].n_vertices if 0 <= gi < len(self.graphs) else 0
+            ptrs.append(_dev_ptr(outs[i], nv, f"outs[{i}]"))
+        ah = (_vp * max(n, 1))(*ptrs)
+        ro = _run_opts(options)
+        h = _vp()
+        _check(lib().eat_batch_create(gh, len(self.graphs), _ptr32(q_graph), _ptr32(q_src),
+                                      _ptr32(q_ts), n, ah,
+                                      ctypes.byref(ro) if ro is not None else None, ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        self._outs = outs  # keep the slabs alive as long as the batch
+
+    def run(self, stream=None):
+        _check(lib().eat_batch_run(self._h, _stream_handle(stream)))
+
+    def wait(self, stats: bool = False):
+        if stats:
+            arr = (QueryStats * max(self.n, 1))()
+            _check(lib().eat_batch_wait(self._h, arr))
+            return [arr[i].as_dict() for i in range(self.n)]
+        _check(lib().eat_batch_wait(self._h, None))
+        return None
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().eat_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def eat_query_batch(graphs: Sequence[Graph], q_graph, q_src, q_ts, outs, stream=None,
+                    options=None, stats: bool = False):
+    q_graph, q_src, q_ts = _i32(q_graph), _i32(q_src), _i32(q_ts)
+    n = len(q_src)
+    gh = (_vp * len(graphs))(*[g.handle for g in graphs])
+    ptrs = [_dev_ptr(outs[i], graphs[int(q_graph[i])].n_vertices, f"outs[{i}]") for i in range(n)]
+    ah = (_vp * max(n, 1))(*ptrs)
+    ro = _run_opts(options)
+    st = (QueryStats * max(n, 1))() if stats else None
+    _check(lib().eat_query_batch(gh, len(graphs), _ptr32(q_graph), _ptr32(q_src), _ptr32(q_ts), n, ah,
+                                 _stream_handle(stream), ctypes.byref(ro) if ro is not None else None,
+                                 st))
+    return [st[i].as_dict() for i in range(n)] if stats else None
+
+
+def eat_next_departure(g: Graph, type_ids, x, out, stream=None):
+    n = int(type_ids.numel())
+    _check(lib().eat_next_departure(g.handle, _dev_ptr(type_ids, n, "type_ids"), _dev_ptr(x, n, "x"),
+                                    _dev_ptr(out, n, "out"), n, _stream_handle(stream)))
+
+
+def eat_version() -> int:
+    return int(lib().eat_version())

@@ -1,0 +1,220 @@
+"""Host-side checks of libeat that need no GPU: the library loads and exports
+every function its header declares, the preprocessing (Section III-A) keeps
+exactly the input departures, the paper's worked examples come out as printed,
+and invalid input is rejected."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1912_00966_amd import eat, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_examples.json")))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "eat.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(eat_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    declared = _declared_functions()
+    assert len(declared) >= 15
+    assert sorted(eat.EXPORTS) == declared
+    L = eat.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+    assert eat.eat_version() >= 100
+    assert L.eat_status_string(eat.EAT_ERR_NOT_CONVERGED) == b"not converged"
+
+
+def _expand(view, tcol=None):
+    """{type index: sorted departures} from the layout arrays."""
+    out = {}
+    ty = view["ty"]
+    if view["layout"] == eat.EAT_LAYOUT_FLAT:
+        for i in range(len(ty)):
+            out[i] = view["pool"][ty[i, 2]: ty[i, 2] + ty[i, 3]].tolist()
+        return out
+    hdr, pool, hi = view["hdr"], view["pool"], view["ty_mask_hi"]
+    cw = view["cluster_seconds"]
+    for i in range(len(ty)):
+        mask = int(np.uint32(ty[i, 3])) | ((int(hi[i]) << 32) if len(hi) else 0)
+        deps = []
+        idx = ty[i, 2]
+        for k in range(64):
+            if not (mask >> k) & 1:
+                continue
+            t0, c = int(hdr[idx, 0]), int(hdr[idx, 1])
+            if c >= 0:
+                n, h = c >> 16, c & 0xFFFF
+                terms = [t0 + j * h for j in range(n)]
+            else:
+                off = ~c
+                n = int(pool[off])
+                terms = pool[off + 1: off + 1 + n].tolist()
+                assert terms[0] == t0
+            assert all(t // cw == k for t in terms), (i, k, terms)
+            assert terms == sorted(set(terms))
+            deps += terms
+            idx += 1
+        out[i] = deps
+    return out
+
+
+def _reference_types(tt):
+    """{(u, v, lam): sorted distinct departures}, self-loops dropped."""
+    keep = tt.u != tt.v
+    key = np.stack([tt.u[keep], tt.v[keep], tt.lam[keep], tt.t[keep]], axis=1).astype(np.int64)
+    key = np.unique(key, axis=0)
+    ref = {}
+    for a, b, l, t in key:
+        ref.setdefault((int(a), int(b), int(l)), []).append(int(t))
+    return ref
+
+
+@pytest.mark.parametrize("layout", [eat.EAT_LAYOUT_HYBRID, eat.EAT_LAYOUT_FLAT])
+@pytest.mark.parametrize("cw", [3600, 1800, 7200])
+def test_layout_keeps_exactly_the_input_departures(layout, cw):
+    tt, _ = synth.workload("city-1k")
+    lay = eat.eat_layout_build(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices, layout=layout, cluster_seconds=cw)
+    view = lay.view()
+    info = lay.info()
+    ref = _reference_types(tt)
+    got = _expand(view)
+    ty, vt = view["ty"], view["vt_off"]
+    assert vt[0] == 0 and vt[-1] == len(ty) == info.n_types == len(ref)
+    seen = {}
+    for uu in range(tt.n_vertices):
+        rows = ty[vt[uu]:vt[uu + 1]]
+        keys = [(int(r[0]), int(r[1])) for r in rows]
+        assert keys == sorted(keys) and len(set(keys)) == len(keys)
+        for j in range(vt[uu], vt[uu + 1]):
+            seen[(uu, int(ty[j, 0]), int(ty[j, 1]))] = got[j]
+    assert seen == ref
+    assert info.n_conn == sum(len(d) for d in ref.values())
+    assert info.n_edges == len({(a, b) for a, b, _ in ref})
+    if layout == eat.EAT_LAYOUT_HYBRID:
+        assert info.n_headers == info.n_ap_clusters + info.n_array_clusters
+        assert info.n_clusters == int(tt.t.max()) // cw + 1
+
+
+def test_layout_on_random_tiny_timetables_with_duplicates_and_loops():
+    rng = np.random.default_rng(3)
+    for _ in range(300):
+        tt = synth.random_tiny(rng, max_v=6, max_c=60, max_t=20000, max_lam=50)
+        # add exact duplicates
+        if tt.n_conn:
+            pick = rng.integers(0, tt.n_conn, size=min(5, tt.n_conn))
+            tt.u, tt.v = np.concatenate([tt.u, tt.u[pick]]), np.concatenate([tt.v, tt.v[pick]])
+            tt.t, tt.lam = np.concatenate([tt.t, tt.t[pick]]), np.concatenate([tt.lam, tt.lam[pick]])
+        for layout in (eat.EAT_LAYOUT_HYBRID, eat.EAT_LAYOUT_FLAT):
+            cw = int(rng.choice([1, 7, 600, 3600]))
+            keep = tt.u != tt.v
+            if layout == eat.EAT_LAYOUT_HYBRID and int(tt.t[keep].max(initial=0)) // cw + 1 > 64:
+                with pytest.raises(eat.EatError) as ei:
+                    eat.eat_layout_build(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices, layout=layout,
+                                         cluster_seconds=cw)
+                assert ei.value.status == eat.EAT_ERR_UNSUPPORTED
+                continue
+            lay = eat.eat_layout_build(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices, layout=layout,
+                                       cluster_seconds=cw if layout == 0 else 0)
+            view = lay.view()
+            got = _expand(view)
+            ref = _reference_types(tt)
+            vt, ty = view["vt_off"], view["ty"]
+            seen = {}
+            for uu in range(tt.n_vertices):
+                for j in range(vt[uu], vt[uu + 1]):
+                    seen[(uu, int(ty[j, 0]), int(ty[j, 1]))] = got[j]
+            assert seen == ref
+            info = lay.info()
+            assert info.n_self_loops == int((tt.u == tt.v).sum())
+            assert info.n_conn + info.n_duplicates + info.n_self_loops == info.n_conn_input
+
+
+def test_hybrid_layout_with_more_than_32_clusters_uses_high_mask_bits():
+    # departures over 50 hours -> 50 one-hour clusters
+    t = np.arange(0, 50 * 3600, 1800, dtype=np.int32)
+    n = len(t)
+    lay = eat.eat_layout_build(np.zeros(n), np.ones(n), t, np.full(n, 60), 2)
+    view = lay.view()
+    assert view["n_clusters"] == 50
+    mask = int(np.uint32(view["ty"][0, 3])) | (int(view["ty_mask_hi"][0]) << 32)
+    assert mask == (1 << 50) - 1
+    assert _expand(view)[0] == t.tolist()
+
+
+# ---------------------------------------------------------------- paper examples
+
+def _one_type_layout(deps, cw):
+    n = len(deps)
+    lay = eat.eat_layout_build(np.zeros(n), np.ones(n), np.asarray(deps), np.full(n, 60), 2,
+                               cluster_seconds=cw)
+    return lay.view()
+
+
+def test_paper_ap_example_is_one_progression():
+    ex = GOLDEN["ap_cover"]
+    view = _one_type_layout(ex["departures"], 3600)
+    assert view["n_headers"] == 1
+    t0, c = view["hdr"][0]
+    n, h = c >> 16, c & 0xFFFF
+    assert (t0, t0 + (n - 1) * h, h) == (ex["first"], ex["last"], ex["difference"])
+
+
+def test_paper_quarter_hour_service_splits_into_hourly_clusters():
+    ex = GOLDEN["quarter_hour_service"]
+    deps = list(range(ex["first"], ex["last"] + 1, ex["difference"]))
+    assert len(deps) == ex["n_terms"]
+    view = _one_type_layout(deps, 3600)
+    mask = int(np.uint32(view["ty"][0, 3]))
+    assert mask == sum(1 << int(k) for k in ex["clusters"])
+    for row, k in zip(view["hdr"], sorted(ex["clusters"], key=int)):
+        t0, c = int(row[0]), int(row[1])
+        assert [t0, c & 0xFFFF, c >> 16] == ex["clusters"][k]
+
+
+def test_paper_time_format_example_falls_in_hour_13():
+    ex = GOLDEN["time_format"]
+    hh, mm, ss = (int(x) for x in ex["hhmmss"].split(":"))
+    assert hh * 3600 + mm * 60 + ss == ex["seconds"]
+    view = _one_type_layout([ex["seconds"]], 3600)
+    assert int(np.uint32(view["ty"][0, 3])) == 1 << ex["cluster"]
+
+
+# ---------------------------------------------------------------- rejections
+
+@pytest.mark.parametrize("u,v,t,lam,nv,status", [
+    ([0], [1], [0], [0], 2, eat.EAT_ERR_INVALID_ARGUMENT),            # lam < 1
+    ([0], [1], [-5], [3], 2, eat.EAT_ERR_INVALID_ARGUMENT),           # t < 0
+    ([0], [2], [0], [3], 2, eat.EAT_ERR_INVALID_ARGUMENT),            # v out of range
+    ([-1], [1], [0], [3], 2, eat.EAT_ERR_INVALID_ARGUMENT),           # u out of range
+    ([0], [1], [2**31 - 10], [9], 2, eat.EAT_ERR_INVALID_ARGUMENT),   # t + lam = INT32_MAX
+    ([0], [1], [0], [1], 0, eat.EAT_ERR_INVALID_ARGUMENT),            # no vertices
+])
+def test_invalid_connections_are_rejected(u, v, t, lam, nv, status):
+    with pytest.raises(eat.EatError) as ei:
+        eat.eat_layout_build(u, v, t, lam, nv)
+    assert ei.value.status == status
+
+
+def test_long_horizons_need_the_flat_layout_or_wider_clusters():
+    t = [0, 70 * 3600]
+    with pytest.raises(eat.EatError) as ei:
+        eat.eat_layout_build([0, 0], [1, 1], t, [5, 5], 2)
+    assert ei.value.status == eat.EAT_ERR_UNSUPPORTED
+    eat.eat_layout_build([0, 0], [1, 1], t, [5, 5], 2, layout=eat.EAT_LAYOUT_FLAT)
+    eat.eat_layout_build([0, 0], [1, 1], t, [5, 5], 2, cluster_seconds=7200)
+    with pytest.raises(eat.EatError):
+        eat.eat_layout_build([0], [1], [0], [5], 2, cluster_seconds=40000)
+
+
+def test_empty_timetable_is_valid():
+    lay = eat.eat_layout_build([], [], [], [], 3)
+    info = lay.info()
+    assert info.n_types == 0 and info.n_conn == 0 and info.n_vertices == 3
