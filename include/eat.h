@@ -162,14 +162,19 @@ typedef struct {
   int32_t mode;               /* eat_mode */
   int32_t max_rounds;         /* round limit per query; 0 = n_vertices + 2 */
   int32_t frontier_cap;       /* frontier list entries kept on chip; 0 = auto */
-  int32_t reserved[4];        /* must be zero */
+  int32_t table_cap;          /* on-chip arrival-table slots (power of two); 0 = auto,
+                                 -1 = keep arrivals in the result slab (HBM) only */
+  int32_t reserved[3];        /* must be zero */
 } eat_run_options;
 
 typedef struct {
   int32_t status;        /* EAT_OK or EAT_ERR_NOT_CONVERGED */
   int32_t rounds;        /* relaxation rounds until no arrival improved */
   int32_t sweep_rounds;  /* of which topology sweeps */
-  int32_t max_frontier;  /* largest frontier (capped at frontier_cap + 1) */
+  int32_t max_frontier;  /* largest frontier (pushes of one round) */
+  int32_t reached;       /* stops with a finite arrival, the source included */
+  int32_t spilled;       /* 1 if the on-chip arrival table overflowed and the
+                            query was run again against the result slab */
   int64_t activations;   /* active stops processed */
   int64_t type_evals;    /* connection types examined */
   int64_t header_loads;  /* cluster headers read (hybrid) */

@@ -295,8 +295,12 @@ struct Plan {
   int max_rounds = 0;
   int fcap = 0;
   int bm_words = 0;
+  int table_cap = 0;
+  int table_bits = 0;
   size_t lds = 0;
 };
+
+static size_t table_lds(int H, int fcap) { return (size_t)H * 8 + (size_t)(H / 32) * 4 + (size_t)fcap * 8; }
 
 static eat_status make_plan(const eat_run_options *ro, int32_t max_v, int64_t n_types_sum,
                             int64_t n_vertices_sum, int device, Plan *pl) {
@@ -309,19 +313,39 @@ static eat_status make_plan(const eat_run_options *ro, int32_t max_v, int64_t n_
   if (o.threads_per_vertex != 0 && !valid_tpv(o.threads_per_vertex))
     return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_vertex must be 0 or a power of two up to 64");
   if (o.frontier_cap < 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "frontier_cap must be >= 0");
+  const bool table_auto = o.table_cap == 0;
+  if (o.table_cap < -1 || (o.table_cap > 0 && ((o.table_cap & (o.table_cap - 1)) || o.table_cap < 64)))
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "table_cap must be 0, -1 or a power of two >= 64");
   pl->tpv = o.threads_per_vertex ? o.threads_per_vertex
                                  : auto_tpv(n_types_sum, (int32_t)std::min<int64_t>(n_vertices_sum, INT32_MAX));
   pl->mode = o.mode;
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;
-  int fcap = o.frontier_cap ? o.frontier_cap : 4096;
+  int fcap = o.frontier_cap ? o.frontier_cap : 2048;
   fcap = (fcap + 31) / 32 * 32;
-  fcap = std::min(fcap, std::max(32, (max_v + 31) / 32 * 32));
-  pl->fcap = fcap;
-  pl->lds = (size_t)pl->bm_words * 4 + (size_t)fcap * 8;
   DeviceLimits lim;
   eat_status s = device_limits(device, &lim);
   if (s != EAT_OK) return s;
+  int H = 0;
+  if (table_auto) {
+    H = 64;
+    while (H < 16384 && H < 2 * max_v) H <<= 1;
+  } else if (o.table_cap > 0) {
+    H = o.table_cap;
+  }
+  // a frontier never holds more items than there are stops (or table slots)
+  const int items = std::max(32, (std::max(max_v, H) + 31) / 32 * 32);
+  fcap = std::min(fcap, items);
+  const size_t slab_lds = (size_t)pl->bm_words * 4 + (size_t)fcap * 8;
+  while (table_auto && H >= 64 && std::max(table_lds(H, fcap), slab_lds) > lim.lds) H >>= 1;
+  if (H < 64) H = 0;
+  if (H && std::max(table_lds(H, fcap), slab_lds) > lim.lds)
+    return set_err(EAT_ERR_UNSUPPORTED, "table_cap too large for the device's LDS");
+  pl->table_cap = H;
+  pl->table_bits = 0;
+  while (H && (1 << pl->table_bits) < H) ++pl->table_bits;
+  pl->fcap = fcap;
+  pl->lds = std::max(H ? table_lds(H, fcap) : 0, slab_lds);
   if (pl->lds > lim.lds)
     return set_err(EAT_ERR_UNSUPPORTED, "graph too large for the on-chip activity bitmap (" +
                                             std::to_string(pl->lds) + " bytes of LDS needed, " +
@@ -353,6 +377,8 @@ extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32
   a.mode = pl.mode;
   a.fcap = pl.fcap;
   a.bm_words = pl.bm_words;
+  a.table_cap = pl.table_cap;
+  a.table_bits = pl.table_bits;
   a.work = nullptr;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   eat_graph *gm = const_cast<eat_graph *>(g);
@@ -472,6 +498,8 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   a.mode = pl.mode;
   a.fcap = pl.fcap;
   a.bm_words = pl.bm_words;
+  a.table_cap = pl.table_cap;
+  a.table_bits = pl.table_bits;
   a.work = d_c;
   a.stats = d_s;
   a.n_failed = d_c + 2;

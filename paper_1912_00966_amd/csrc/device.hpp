@@ -44,6 +44,8 @@ struct RunArgs {
   int32_t mode;              // eat_mode
   int32_t fcap;              // frontier list capacity (entries, multiple of 32)
   int32_t bm_words;          // activity bitmap words (>= ceil(V / 32) of every graph)
+  int32_t table_cap;         // on-chip arrival table slots (power of two), 0 = none
+  int32_t table_bits;        // log2(table_cap)
   // Batch counters (batch only; zero before the first launch, re-armed by the
   // last work-group of every launch): [0] next query, [1] work-groups done,
   // [2] queries of this launch that hit the round limit, [3] that count for
@@ -53,7 +55,7 @@ struct RunArgs {
   int32_t *n_failed;         // == work + 2 in a batch; nullable
 };
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 1024;
 
 // Host-side launchers (kernels.hip).
 hipError_t launch_relax(const RunArgs &a, int tpv, int kind, int grid, size_t lds_bytes,

@@ -32,6 +32,9 @@
 // value read after that improvement.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <set>
+
 #include "device.hpp"
 
 namespace eat {
@@ -130,7 +133,7 @@ __device__ __forceinline__ int32_t next_departure<EAT_LAYOUT_FLAT>(const GraphDe
 // Frontier push: wave64 ballot, one LDS atomic per wave, lane offsets by
 // masked population count.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void push(bool want, int32_t v, int32_t *nxt, int32_t fcap, bool append,
+__device__ __forceinline__ void push(bool want, int32_t item, int32_t *nxt, int32_t fcap, bool append,
                                      int32_t *sh_nn) {
   const uint64_t m = __ballot(want);
   if (m == 0) return;
@@ -141,20 +144,89 @@ __device__ __forceinline__ void push(bool want, int32_t v, int32_t *nxt, int32_t
   base = __shfl(base, leader);
   if (want && append) {
     const int32_t slot = base + (int32_t)__popcll(m & ((1ull << lane) - 1ull));
-    if (slot < fcap) nxt[slot] = v;
+    if (slot < fcap) nxt[slot] = item;
   }
 }
 
+__device__ __forceinline__ int32_t lds_ld(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// ---------------------------------------------------------------------------
+// Where a query keeps its arrival times.  An "item" names one stop's entry;
+// `bits` holds one activity bit per item.
+// ---------------------------------------------------------------------------
+
+// In the caller's result slab (HBM); item = stop id.
+struct SlabStore {
+  int32_t *arr;
+  uint32_t *bits;
+  __device__ __forceinline__ int32_t stop(int32_t item) const { return item; }
+  __device__ __forceinline__ int32_t value(int32_t item) const { return ld_arr(arr + item); }
+  __device__ __forceinline__ int32_t find(int32_t v) const { return ld_arr(arr + v); }
+  __device__ __forceinline__ int32_t slot(int32_t v) const { return v; }
+  __device__ __forceinline__ int32_t lower(int32_t item, int32_t cand) const { return min_arr(arr + item, cand); }
+};
+
+// In an on-chip open-addressing hash table (LDS) of the stops the query has
+// touched; item = table slot.  The result slab only receives the final values.
+constexpr int32_t EMPTY = -1;
+struct TableStore {
+  int32_t *keys;   // stop id or EMPTY
+  int32_t *vals;   // arrival time (INF until lowered)
+  uint32_t *bits;
+  int32_t *count;  // slots in use
+  int32_t *over;   // set when the table is too full to take another stop
+  uint32_t mask;
+  int32_t shift;
+  int32_t limit;
+  __device__ __forceinline__ uint32_t home(int32_t v) const { return ((uint32_t)v * 2654435761u) >> shift; }
+  __device__ __forceinline__ int32_t stop(int32_t item) const { return lds_ld(keys + item); }
+  __device__ __forceinline__ int32_t value(int32_t item) const { return lds_ld(vals + item); }
+  // arrival of v, INF when v is not in the table (yet)
+  __device__ __forceinline__ int32_t find(int32_t v) const {
+    uint32_t p = home(v);
+    for (uint32_t n = 0; n <= mask; ++n) {
+      const int32_t k = lds_ld(keys + p);
+      if (k == v) return lds_ld(vals + p);
+      if (k == EMPTY) return INF;
+      p = (p + 1u) & mask;
+    }
+    return INF;
+  }
+  // slot of v, inserting it; -1 (and *over = 1) when the table is full
+  __device__ __forceinline__ int32_t slot(int32_t v) const {
+    uint32_t p = home(v);
+    for (uint32_t n = 0; n <= mask; ++n) {
+      const int32_t k = lds_ld(keys + p);
+      if (k == v) return (int32_t)p;
+      if (k == EMPTY) {
+        if (lds_ld(count) >= limit) break;
+        const int32_t old = atomicCAS(keys + p, EMPTY, v);
+        if (old == EMPTY) {
+          atomicAdd(count, 1);
+          return (int32_t)p;
+        }
+        if (old == v) return (int32_t)p;
+      }
+      p = (p + 1u) & mask;
+    }
+    __hip_atomic_store(over, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return -1;
+  }
+  __device__ __forceinline__ int32_t lower(int32_t item, int32_t cand) const { return atomicMin(vals + item, cand); }
+};
+
 // Relax (Algorithm 3) the best connection of type j for a tail reached at x.
-template <int KIND>
-__device__ __forceinline__ void relax(const GraphDev &G, int32_t *arr, int64_t j, int32_t x,
-                                      int32_t *nxt, uint32_t *bm, int32_t fcap, bool append,
-                                      int32_t *sh_nn, Ctr &c) {
+template <int KIND, class Store>
+__device__ __forceinline__ void relax(const GraphDev &G, const Store &S, int64_t j, int32_t x,
+                                      int32_t *nxt, int32_t fcap, bool append, int32_t *sh_nn, Ctr &c) {
   const int4 r = G.ty[j];
   const int32_t v = r.x, lam = r.y;
   c.tev++;
-  const int32_t av = ld_arr(arr + v);
+  const int32_t av = S.find(v);
   bool want = false;
+  int32_t item = 0;
   // Any departure of this type leaves at t_c >= x, so it arrives at >= x + lam:
   // skip the lookup when that cannot beat arr[v] (early termination, Section
   // III-D, in its strongest exact form).
@@ -163,57 +235,148 @@ __device__ __forceinline__ void relax(const GraphDev &G, int32_t *arr, int64_t j
     if (tc != INF) {
       const int32_t cand = tc + lam;
       if (cand < av) {
-        const int32_t old = min_arr(arr + v, cand);
-        if (cand < old) {
-          c.imp++;
-          const uint32_t bit = 1u << (v & 31);
-          want = !(atomicOr(&bm[v >> 5], bit) & bit);
+        item = S.slot(v);
+        if (item >= 0) {
+          const int32_t old = S.lower(item, cand);
+          if (cand < old) {
+            c.imp++;
+            const uint32_t bit = 1u << (item & 31);
+            want = !(atomicOr(&S.bits[item >> 5], bit) & bit);
+          }
         }
       }
     }
   }
-  push(want, v, nxt, fcap, append, sh_nn);
+  push(want, item, nxt, fcap, append, sh_nn);
 }
 
-// Expand every stop of list[0..n): groups of TPV lanes, one stop per group.
-template <int TPV, int KIND>
-__device__ __forceinline__ void expand_list(const GraphDev &G, int32_t *arr, const int32_t *list,
-                                            int32_t n, int32_t *nxt, uint32_t *bm, int32_t fcap,
-                                            bool append, int32_t *sh_nn, Ctr &c) {
+// Expand every item of list[0..n): groups of TPV lanes, one stop per group.
+template <int TPV, int KIND, class Store>
+__device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, const int32_t *list,
+                                            int32_t n, int32_t *nxt, int32_t fcap, bool append,
+                                            int32_t *sh_nn, Ctr &c) {
   constexpr int kGroups = kBlock / TPV;
   const int g = threadIdx.x / TPV, lane = threadIdx.x % TPV;
   for (int32_t base = 0; base < n; base += kGroups) {
     const int32_t i = base + g;
     if (i < n) {
-      const int32_t u = list[i];
-      const int32_t x = ld_arr(arr + u);
+      const int32_t item = list[i];
+      const int32_t u = S.stop(item);
+      const int32_t x = S.value(item);
       const int32_t b = G.vt_off[u], e = G.vt_off[u + 1];
       if (lane == 0) c.act++;
-      for (int32_t j = b + lane; j < e; j += TPV) relax<KIND>(G, arr, j, x, nxt, bm, fcap, append, sh_nn, c);
+      for (int32_t j = b + lane; j < e; j += TPV) relax<KIND>(G, S, j, x, nxt, fcap, append, sh_nn, c);
     }
   }
+}
+
+struct Shared {
+  int32_t q, nn, cnt, count, over, reached;
+  unsigned long long acc[5];
+};
+
+struct QState {
+  int32_t rounds = 0, sweeps = 0, maxf = 1, status = EAT_OK;
+};
+
+// Relaxation rounds until no arrival improves (the iteration of Algorithms 4
+// and 5, with the activity flags of Section III-B).  On entry the first item
+// is in list0[0] (frontier mode) or has its bit set (topology mode), and every
+// other bit is clear.  Returns false if the store overflowed.
+template <int TPV, int KIND, class Store>
+__device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, int32_t n_items,
+                           int32_t *list0, int32_t *list1, bool topo, int32_t max_rounds,
+                           Shared &sh, QState &qs, Ctr &c) {
+  const int tid = threadIdx.x;
+  const int32_t nwords = (n_items + 31) >> 5;
+  const int32_t chunk_words = a.fcap >> 5;  // a sweep stages at most fcap items at a time
+  int32_t *cur = list0, *nxt = list1;
+  int32_t nf = topo ? 0 : 1;
+  bool sweep = topo;
+  int32_t rounds = 0;
+  for (;;) {
+    if (rounds >= max_rounds) {
+      qs.status = EAT_ERR_NOT_CONVERGED;
+      break;
+    }
+    if (tid == 0) sh.nn = 0;
+    __syncthreads();
+    if (!sweep) {
+      expand_list<TPV, KIND>(G, S, cur, nf, nxt, a.fcap, !topo, &sh.nn, c);
+    } else {
+      ++qs.sweeps;
+      for (int32_t w0 = 0; w0 < nwords; w0 += chunk_words) {
+        if (tid == 0) sh.cnt = 0;
+        __syncthreads();
+        const int32_t w1 = min(w0 + chunk_words, nwords);
+        for (int32_t w = w0 + tid; w < w1; w += kBlock) {
+          uint32_t bits = S.bits[w];
+          if (bits) {
+            bits = atomicExch(&S.bits[w], 0u);  // claim: these items are expanded now
+            int32_t pos = atomicAdd(&sh.cnt, (int32_t)__popc(bits));
+            while (bits) {
+              const int b = __ffs(bits) - 1;
+              bits &= bits - 1u;
+              cur[pos++] = (w << 5) + b;
+            }
+          }
+        }
+        __syncthreads();
+        const int32_t cnt = sh.cnt;
+        if (cnt) expand_list<TPV, KIND>(G, S, cur, cnt, nxt, a.fcap, !topo, &sh.nn, c);
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    if (sh.over) {
+      qs.rounds += rounds + 1;
+      return false;
+    }
+    const int32_t nn = sh.nn;
+    ++rounds;
+    if (nn == 0) break;
+    qs.maxf = max(qs.maxf, nn);
+    const bool next_sweep = topo || nn > a.fcap;
+    if (!next_sweep) {
+      // the pushed items become the current list: clear their bits so that the
+      // next round's pushes are de-duplicated afresh
+      for (int32_t i = tid; i < nn; i += kBlock) {
+        const int32_t it = nxt[i];
+        atomicAnd(&S.bits[it >> 5], ~(1u << (it & 31)));
+      }
+    }
+    int32_t *tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    nf = next_sweep ? 0 : nn;
+    sweep = next_sweep;
+    __syncthreads();
+  }
+  qs.rounds += rounds;
+  return true;
 }
 
 template <int TPV, int KIND>
 __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
   extern __shared__ uint32_t lds[];
-  __shared__ int32_t sh_q, sh_nn, sh_cnt;
-  __shared__ unsigned long long sh_acc[5];
+  __shared__ Shared sh;
 
   const int tid = threadIdx.x;
-  uint32_t *bm = lds;
-  int32_t *list0 = reinterpret_cast<int32_t *>(lds + a.bm_words);
-  int32_t *list1 = list0 + a.fcap;
   const bool batch = a.queries != nullptr;
   const bool topo = a.mode == EAT_MODE_TOPOLOGY;
 
   for (int iter = 0;; ++iter) {
     if (tid == 0)
-      sh_q = batch ? __hip_atomic_fetch_add(a.work, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+      sh.q = batch ? __hip_atomic_fetch_add(a.work, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                    : (iter == 0 ? 0 : a.nq);
-    if (tid < 5) sh_acc[tid] = 0ull;
+    if (tid < 5) sh.acc[tid] = 0ull;
+    if (tid == 0) {
+      sh.count = 0;
+      sh.over = 0;
+      sh.reached = 0;
+    }
     __syncthreads();
-    const int32_t q = sh_q;
+    const int32_t q = sh.q;
     if (q >= a.nq) {
       // The last work-group to leave re-arms the shared counters for the next
       // launch of the same batch, so a run is a single kernel launch.
@@ -231,11 +394,13 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
     const QueryDev Q = batch ? a.queries[q] : a.single;
     const GraphDev G = a.graphs[batch ? Q.graph : 0];
     const int32_t V = G.n_vertices;
-    const int32_t VW = (V + 31) >> 5;
     int32_t *arr = Q.arr;
     const int32_t max_rounds = a.max_rounds > 0 ? a.max_rounds : V + 2;
+    QState qs;
+    Ctr c;
 
-    // ---- Initialize (Algorithm 2) -------------------------------------------
+    // ---- Initialize (Algorithm 2): the slab gets infinity everywhere.  The
+    // stores drain while the on-chip relaxation runs.
     if ((reinterpret_cast<uintptr_t>(arr) & 15u) == 0) {
       int4 *a4 = reinterpret_cast<int4 *>(arr);
       const int32_t n4 = V >> 2;
@@ -245,101 +410,100 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
     } else {
       for (int32_t i = tid; i < V; i += kBlock) arr[i] = INF;
     }
-    for (int32_t i = tid; i < VW; i += kBlock) bm[i] = 0u;
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the fill is in L2 before anyone reads arr
-    __syncthreads();
-    if (tid == 0) {
-      st_arr(arr + Q.s, Q.ts);
-      if (topo) bm[Q.s >> 5] = 1u << (Q.s & 31);
-      else list0[0] = Q.s;
-    }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
 
-    // ---- rounds until no arrival improves ------------------------------------
-    int32_t *cur = list0, *nxt = list1;
-    int32_t nf = topo ? 0 : 1;
-    bool sweep = topo;
-    int32_t rounds = 0, sweeps = 0, maxf = 1, status = EAT_OK;
-    Ctr c;
-    const int32_t chunk_words = a.fcap >> 5;  // a sweep stages at most fcap stops at a time
-    for (;;) {
-      if (rounds >= max_rounds) {
-        status = EAT_ERR_NOT_CONVERGED;
-        break;
+    bool done = false;
+    if (a.table_cap > 0) {
+      // ---- arrivals in the on-chip table ----------------------------------------
+      const int32_t H = a.table_cap;
+      TableStore T;
+      T.keys = reinterpret_cast<int32_t *>(lds);
+      T.vals = T.keys + H;
+      T.bits = reinterpret_cast<uint32_t *>(T.vals + H);
+      T.count = &sh.count;
+      T.over = &sh.over;
+      T.mask = (uint32_t)H - 1u;
+      T.shift = 32 - a.table_bits;
+      T.limit = H - H / 4;
+      int32_t *l0 = reinterpret_cast<int32_t *>(T.bits + (H >> 5));
+      int32_t *l1 = l0 + a.fcap;
+      for (int32_t i = tid; i < H; i += kBlock) {
+        T.keys[i] = EMPTY;
+        T.vals[i] = INF;
       }
-      if (tid == 0) sh_nn = 0;
+      for (int32_t i = tid; i < (H >> 5); i += kBlock) T.bits[i] = 0u;
       __syncthreads();
-      if (!sweep) {
-        expand_list<TPV, KIND>(G, arr, cur, nf, nxt, bm, a.fcap, !topo, &sh_nn, c);
-      } else {
-        ++sweeps;
-        for (int32_t w0 = 0; w0 < VW; w0 += chunk_words) {
-          if (tid == 0) sh_cnt = 0;
-          __syncthreads();
-          const int32_t w1 = min(w0 + chunk_words, VW);
-          for (int32_t w = w0 + tid; w < w1; w += kBlock) {
-            uint32_t bits = bm[w];
-            if (bits) {
-              bits = atomicExch(&bm[w], 0u);  // claim: these stops are expanded now
-              int32_t pos = atomicAdd(&sh_cnt, (int32_t)__popc(bits));
-              while (bits) {
-                const int b = __ffs(bits) - 1;
-                bits &= bits - 1u;
-                cur[pos++] = (w << 5) + b;
-              }
-            }
-          }
-          __syncthreads();
-          const int32_t cnt = sh_cnt;
-          if (cnt) expand_list<TPV, KIND>(G, arr, cur, cnt, nxt, bm, a.fcap, !topo, &sh_nn, c);
-          __syncthreads();
+      if (tid == 0) {
+        const int32_t p = T.slot(Q.s);  // empty table: always succeeds
+        T.vals[p] = Q.ts;
+        if (topo) T.bits[p >> 5] = 1u << (p & 31);
+        else l0[0] = p;
+      }
+      __syncthreads();
+      if (run_rounds<TPV, KIND>(a, G, T, H, l0, l1, topo, max_rounds, sh, qs, c)) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the infinity fill has landed
+        __syncthreads();
+        for (int32_t p = tid; p < H; p += kBlock) {
+          const int32_t k = T.keys[p];
+          if (k != EMPTY) arr[k] = T.vals[p];
         }
+        if (tid == 0) sh.reached = sh.count;
+        done = true;
       }
+    }
+    if (!done) {
+      // ---- arrivals in the result slab (no table, or the table overflowed) ----------
+      const bool spilled = a.table_cap > 0;  // the on-chip attempt overflowed
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
-      const int32_t nn = sh_nn;
-      ++rounds;
-      if (nn == 0) break;
-      maxf = max(maxf, nn);
-      const bool next_sweep = topo || nn > a.fcap;
-      if (!next_sweep) {
-        // the pushed stops become the current list: clear their bits so that the
-        // next round's pushes are de-duplicated afresh
-        for (int32_t i = tid; i < nn; i += kBlock) {
-          const int32_t v = nxt[i];
-          atomicAnd(&bm[v >> 5], ~(1u << (v & 31)));
-        }
+      SlabStore S;
+      S.arr = arr;
+      S.bits = lds;
+      const int32_t VW = (V + 31) >> 5;
+      int32_t *l0 = reinterpret_cast<int32_t *>(lds + VW);
+      int32_t *l1 = l0 + a.fcap;
+      // (an overflowed table attempt never wrote the slab: it still holds infinity)
+      for (int32_t i = tid; i < VW; i += kBlock) S.bits[i] = 0u;
+      if (tid == 0) sh.over = 0;
+      __syncthreads();
+      if (tid == 0) {
+        st_arr(arr + Q.s, Q.ts);
+        if (topo) S.bits[Q.s >> 5] = 1u << (Q.s & 31);
+        else l0[0] = Q.s;
       }
-      int32_t *tmp = cur;
-      cur = nxt;
-      nxt = tmp;
-      nf = next_sweep ? 0 : nn;
-      sweep = next_sweep;
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
+      run_rounds<TPV, KIND>(a, G, S, V, l0, l1, topo, max_rounds, sh, qs, c);
+      // reached stops
+      int32_t mine = 0;
+      for (int32_t i = tid; i < V; i += kBlock) mine += ld_arr(arr + i) != INF;
+      if (mine) atomicAdd(&sh.reached, mine);
+      (void)spilled;
     }
 
     // ---- per-query statistics --------------------------------------------------
-    if (a.stats || (status != EAT_OK && a.n_failed)) {
-      atomicAdd(&sh_acc[0], (unsigned long long)c.act);
-      atomicAdd(&sh_acc[1], (unsigned long long)c.tev);
-      atomicAdd(&sh_acc[2], (unsigned long long)c.hdr);
-      atomicAdd(&sh_acc[3], (unsigned long long)c.pool);
-      atomicAdd(&sh_acc[4], (unsigned long long)c.imp);
+    if (a.stats || (qs.status != EAT_OK && a.n_failed)) {
+      atomicAdd(&sh.acc[0], (unsigned long long)c.act);
+      atomicAdd(&sh.acc[1], (unsigned long long)c.tev);
+      atomicAdd(&sh.acc[2], (unsigned long long)c.hdr);
+      atomicAdd(&sh.acc[3], (unsigned long long)c.pool);
+      atomicAdd(&sh.acc[4], (unsigned long long)c.imp);
       __syncthreads();
       if (tid == 0) {
         if (a.stats) {
           eat_query_stats *st = a.stats + Q.index;
-          st->status = status;
-          st->rounds = rounds;
-          st->sweep_rounds = sweeps;
-          st->max_frontier = maxf;
-          st->activations = (int64_t)sh_acc[0];
-          st->type_evals = (int64_t)sh_acc[1];
-          st->header_loads = (int64_t)sh_acc[2];
-          st->pool_loads = (int64_t)sh_acc[3];
-          st->improvements = (int64_t)sh_acc[4];
+          st->status = qs.status;
+          st->rounds = qs.rounds;
+          st->sweep_rounds = qs.sweeps;
+          st->max_frontier = qs.maxf;
+          st->reached = sh.reached;
+          st->spilled = done ? 0 : (a.table_cap > 0 ? 1 : 0);
+          st->activations = (int64_t)sh.acc[0];
+          st->type_evals = (int64_t)sh.acc[1];
+          st->header_loads = (int64_t)sh.acc[2];
+          st->pool_loads = (int64_t)sh.acc[3];
+          st->improvements = (int64_t)sh.acc[4];
         }
-        if (status != EAT_OK && a.n_failed)
+        if (qs.status != EAT_OK && a.n_failed)
           __hip_atomic_fetch_add(a.n_failed, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
@@ -387,14 +551,31 @@ RelaxFn pick(int tpv, int kind) {
   return kind == EAT_LAYOUT_FLAT ? relax_fn<EAT_LAYOUT_FLAT>(tpv) : relax_fn<EAT_LAYOUT_HYBRID>(tpv);
 }
 
+// Raises a kernel's dynamic-LDS limit once per process (to the device maximum).
+hipError_t allow_lds(RelaxFn f) {
+  static std::mutex mu;
+  static std::set<const void *> done;
+  std::lock_guard<std::mutex> lk(mu);
+  const void *key = reinterpret_cast<const void *>(f);
+  if (done.count(key)) return hipSuccess;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  hipDeviceProp_t p;
+  e = hipGetDeviceProperties(&p, dev);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.sharedMemPerBlock);
+  if (e == hipSuccess) done.insert(key);
+  return e;
+}
+
 }  // namespace
 
 hipError_t launch_relax(const RunArgs &a, int tpv, int kind, int grid, size_t lds_bytes,
                         hipStream_t stream) {
   RelaxFn f = pick(tpv, kind);
   if (!f) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(f),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  hipError_t e = allow_lds(f);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(f, dim3(grid), dim3(kBlock), lds_bytes, stream, a);
   return hipGetLastError();
@@ -403,8 +584,7 @@ hipError_t launch_relax(const RunArgs &a, int tpv, int kind, int grid, size_t ld
 int relax_blocks_per_cu(int tpv, int kind, size_t lds_bytes) {
   RelaxFn f = pick(tpv, kind);
   if (!f) return 0;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds_bytes);
+  if (allow_lds(f) != hipSuccess) return 0;
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(f), kBlock,
                                                    lds_bytes) != hipSuccess)

@@ -78,12 +78,13 @@ class LayoutView(ctypes.Structure):
 class RunOptions(ctypes.Structure):
     _fields_ = [("threads_per_vertex", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("frontier_cap", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("table_cap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class QueryStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("rounds", ctypes.c_int32),
                 ("sweep_rounds", ctypes.c_int32), ("max_frontier", ctypes.c_int32),
+                ("reached", ctypes.c_int32), ("spilled", ctypes.c_int32),
                 ("activations", ctypes.c_int64), ("type_evals", ctypes.c_int64),
                 ("header_loads", ctypes.c_int64), ("pool_loads", ctypes.c_int64),
                 ("improvements", ctypes.c_int64)]

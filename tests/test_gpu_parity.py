@@ -146,18 +146,27 @@ def test_single_queries_city_1k_bit_exact(layout, tpv):
 
 @pytest.mark.parametrize("mode", [eat.EAT_MODE_TOPOLOGY, eat.EAT_MODE_FRONTIER])
 @pytest.mark.parametrize("fcap", [32, 0])
-def test_modes_and_frontier_overflow_are_exact(mode, fcap):
+@pytest.mark.parametrize("table", [0, -1, 64])
+def test_modes_stores_and_overflows_are_exact(mode, fcap, table):
+    """Frontier / topology rounds, frontier-list overflow (sweeps), arrivals in
+    the on-chip table, in the slab, and a table too small (spill to the slab)."""
     tt, q = _workload("city-1k")
     exp = _expected("city-1k")
     g = _graph("city-1k", "hybrid")
-    _say(f"modes city-1k mode={mode} fcap={fcap}")
-    sweeps = 0
+    _say(f"modes city-1k mode={mode} fcap={fcap} table={table}")
+    sweeps = spills = 0
     for i, (s, ts) in enumerate(zip(q.s, q.ts)):
-        got, st = _query(g, s, ts, mode=mode, frontier_cap=fcap)
+        got, st = _query(g, s, ts, mode=mode, frontier_cap=fcap, table_cap=table)
         sweeps += st["sweep_rounds"]
+        spills += st["spilled"]
+        assert st["reached"] == int((exp[i] < INF).sum())
         assert np.array_equal(got, exp[i]), (i, s, ts)
     if mode == eat.EAT_MODE_TOPOLOGY or fcap == 32:
         assert sweeps > 0  # the sweep path really ran
+    if table == 64:
+        assert spills > 0  # some queries reach more than 48 stops: the spill path ran
+    else:
+        assert spills == 0
 
 
 def test_certificate_holds_for_gpu_answers():
