@@ -54,6 +54,8 @@ def main():
     ap.add_argument("--layout", default="hybrid", choices=["hybrid", "flat"])
     ap.add_argument("--reading", default="S", choices=["S", "F"])
     ap.add_argument("--tpv", type=int, default=0, help="threads per active stop (0 = auto)")
+    ap.add_argument("--table", type=int, default=0,
+                    help="on-chip arrival-table slots (0 = auto, -1 = arrivals in HBM only)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-query comparison")
     ap.add_argument("--no-verify", action="store_true")
@@ -88,7 +90,7 @@ def main():
 
     V, Q = tt.n_vertices, len(q)
     slab = torch.empty((Q, V), dtype=torch.int32, device=dev)
-    opts = {"threads_per_vertex": args.tpv} if args.tpv else None
+    opts = {"threads_per_vertex": args.tpv, "table_cap": args.table}
     batch = eat.Batch([g], np.zeros(Q, np.int32), q.s, q.ts, [slab[i] for i in range(Q)], options=opts)
     stream = torch.cuda.current_stream()
 

@@ -50,7 +50,8 @@ eat_status device_limits(int dev, DeviceLimits *out) {
   hipDeviceProp_t p;
   HIP_TRY(hipGetDeviceProperties(&p, dev));
   out->cus = p.multiProcessorCount;
-  out->lds = p.sharedMemPerBlock;
+  // leave room for the kernel's static shared variables
+  out->lds = p.sharedMemPerBlock > 1024 ? p.sharedMemPerBlock - 1024 : p.sharedMemPerBlock;
   return EAT_OK;
 }
 

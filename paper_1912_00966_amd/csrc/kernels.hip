@@ -33,7 +33,7 @@
 #include <hip/hip_runtime.h>
 
 #include <mutex>
-#include <set>
+#include <map>
 
 #include "device.hpp"
 
@@ -551,21 +551,17 @@ RelaxFn pick(int tpv, int kind) {
   return kind == EAT_LAYOUT_FLAT ? relax_fn<EAT_LAYOUT_FLAT>(tpv) : relax_fn<EAT_LAYOUT_HYBRID>(tpv);
 }
 
-// Raises a kernel's dynamic-LDS limit once per process (to the device maximum).
-hipError_t allow_lds(RelaxFn f) {
+// Raises a kernel's dynamic-LDS limit when a launch needs more than any earlier
+// launch of the same kernel in this process.
+hipError_t allow_lds(RelaxFn f, size_t bytes) {
   static std::mutex mu;
-  static std::set<const void *> done;
+  static std::map<const void *, size_t> granted;
   std::lock_guard<std::mutex> lk(mu);
   const void *key = reinterpret_cast<const void *>(f);
-  if (done.count(key)) return hipSuccess;
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  hipDeviceProp_t p;
-  e = hipGetDeviceProperties(&p, dev);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.sharedMemPerBlock);
-  if (e == hipSuccess) done.insert(key);
+  auto it = granted.find(key);
+  if (it != granted.end() && it->second >= bytes) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) granted[key] = bytes;
   return e;
 }
 
@@ -575,7 +571,7 @@ hipError_t launch_relax(const RunArgs &a, int tpv, int kind, int grid, size_t ld
                         hipStream_t stream) {
   RelaxFn f = pick(tpv, kind);
   if (!f) return hipErrorInvalidValue;
-  hipError_t e = allow_lds(f);
+  hipError_t e = allow_lds(f, lds_bytes);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(f, dim3(grid), dim3(kBlock), lds_bytes, stream, a);
   return hipGetLastError();
@@ -584,7 +580,7 @@ hipError_t launch_relax(const RunArgs &a, int tpv, int kind, int grid, size_t ld
 int relax_blocks_per_cu(int tpv, int kind, size_t lds_bytes) {
   RelaxFn f = pick(tpv, kind);
   if (!f) return 0;
-  if (allow_lds(f) != hipSuccess) return 0;
+  if (allow_lds(f, lds_bytes) != hipSuccess) return 0;
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(f), kBlock,
                                                    lds_bytes) != hipSuccess)
