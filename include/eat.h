@@ -105,7 +105,8 @@ typedef struct eat_layout eat_layout;
  *     {t0, c}: t0 = first departure of the cluster; c >= 0 encodes the
  *     progression t0 + i*h, i = 0..n-1 as c = (n << 16) | h; c < 0 encodes a
  *     sorted array at pool[~c]: pool[~c] = n, pool[~c + 1 ..] = departures.
- *   pool[n_pool]: hybrid array clusters, or flat departures. */
+ *   pool[n_pool]: hybrid array clusters, or flat departures.  Every entry
+ *     starts at a multiple of 4 words; the gaps hold EAT_INF. */
 typedef struct {
   int32_t layout;
   int32_t n_vertices;
@@ -180,6 +181,7 @@ typedef struct {
   int64_t header_loads;  /* cluster headers read (hybrid) */
   int64_t pool_loads;    /* departure words read from the pool */
   int64_t improvements;  /* successful atomic minimum updates */
+  int64_t elapsed_ns;    /* device wall-clock time from the query's start to its end */
 } eat_query_stats;
 
 /* One query (s, ts) on g.  arr: device, >= n_vertices int32, caller-owned;

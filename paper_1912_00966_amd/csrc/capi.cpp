@@ -44,6 +44,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct DeviceLimits {
   int cus = 0;
   size_t lds = 0;
+  int64_t ns_per_tick = 10 << 10;  // wall clock period in ns, fixed point x 1024
 };
 
 eat_status device_limits(int dev, DeviceLimits *out) {
@@ -52,6 +53,9 @@ eat_status device_limits(int dev, DeviceLimits *out) {
   out->cus = p.multiProcessorCount;
   // leave room for the kernel's static shared variables
   out->lds = p.sharedMemPerBlock > 1024 ? p.sharedMemPerBlock - 1024 : p.sharedMemPerBlock;
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+    out->ns_per_tick = (int64_t)((1000000.0 / khz) * 1024.0);
   return EAT_OK;
 }
 
@@ -129,7 +133,7 @@ static void fill_info(const eat_layout &L, eat_graph_info_t *o) {
   o->n_headers = L.n_headers;
   o->n_ap_clusters = L.n_ap;
   o->n_array_clusters = L.n_array;
-  o->n_pool = (int64_t)L.pool.size();
+  o->n_pool = (int64_t)L.pool.size() - eat::kPoolTail;
 }
 
 extern "C" eat_status eat_layout_build(const int32_t *u, const int32_t *v, const int32_t *t,
@@ -173,7 +177,7 @@ extern "C" eat_status eat_layout_view_get(const eat_layout *L, eat_layout_view *
   out->n_clusters = L->n_clusters;
   out->n_types = L->n_types;
   out->n_headers = L->n_headers;
-  out->n_pool = (int64_t)L->pool.size();
+  out->n_pool = (int64_t)L->pool.size() - eat::kPoolTail;
   out->vt_off = L->vt_off.data();
   out->ty = L->ty.data();
   out->ty_mask_hi = L->kind == EAT_LAYOUT_HYBRID ? L->mask_hi.data() : nullptr;
@@ -298,6 +302,7 @@ struct Plan {
   int bm_words = 0;
   int table_cap = 0;
   int table_bits = 0;
+  int64_t ns_per_tick = 0;
   size_t lds = 0;
 };
 
@@ -343,6 +348,7 @@ static eat_status make_plan(const eat_run_options *ro, int32_t max_v, int64_t n_
   if (H && std::max(table_lds(H, fcap), slab_lds) > lim.lds)
     return set_err(EAT_ERR_UNSUPPORTED, "table_cap too large for the device's LDS");
   pl->table_cap = H;
+  pl->ns_per_tick = lim.ns_per_tick;
   pl->table_bits = 0;
   while (H && (1 << pl->table_bits) < H) ++pl->table_bits;
   pl->fcap = fcap;
@@ -380,6 +386,7 @@ extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32
   a.bm_words = pl.bm_words;
   a.table_cap = pl.table_cap;
   a.table_bits = pl.table_bits;
+  a.ns_per_tick = pl.ns_per_tick;
   a.work = nullptr;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   eat_graph *gm = const_cast<eat_graph *>(g);
@@ -501,6 +508,7 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   a.bm_words = pl.bm_words;
   a.table_cap = pl.table_cap;
   a.table_bits = pl.table_bits;
+  a.ns_per_tick = pl.ns_per_tick;
   a.work = d_c;
   a.stats = d_s;
   a.n_failed = d_c + 2;

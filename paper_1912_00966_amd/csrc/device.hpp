@@ -53,6 +53,7 @@ struct RunArgs {
   int32_t *work;
   eat_query_stats *stats;    // per query, indexed by QueryDev::index; nullable
   int32_t *n_failed;         // == work + 2 in a batch; nullable
+  int64_t ns_per_tick;       // device wall clock period in ns (x 1024)
 };
 
 constexpr int kBlock = 1024;

@@ -67,13 +67,28 @@ template <int KIND>
 __device__ __forceinline__ int32_t next_departure(const GraphDev &G, const int4 r, int64_t j,
                                                   int32_t x, Ctr &c);
 
+// First of the sorted departures d[0..n) (n <= 16, read from 16-byte chunks)
+// that is >= x, or INF.  Words past n are ignored.
+__device__ __forceinline__ int32_t first_at_or_after(const int32_t *d, int32_t n, int32_t x) {
+  int32_t best = INF;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int32_t t = d[i];
+    best = (i < n && t >= x && t < best) ? t : best;
+  }
+  return best;
+}
+
 // Hybrid layout: hourly clusters (Section II-D) + one progression or a sorted
 // array per cluster.  Cluster k = x / width.  If cluster k holds departures,
 // the first one >= x inside it comes from the progression closed form
-// t0 + ceil((x - t0) / h) * h (Algorithm 6) or a bisection of its array;
+// t0 + ceil((x - t0) / h) * h (Algorithm 6) or from its sorted array;
 // otherwise -- cluster k empty, or all its departures earlier than x -- the
 // answer is the first departure of the next non-empty cluster (Section II-D),
-// which is the next header because only non-empty clusters have one.
+// which is the next header because only non-empty clusters have one.  That
+// next header is read together with the first, so the fall-through costs no
+// extra dependent memory access; short arrays (<= 7 departures, the common
+// case) are read as two independent 16-byte chunks.
 template <>
 __device__ __forceinline__ int32_t next_departure<EAT_LAYOUT_HYBRID>(const GraphDev &G, const int4 r,
                                                                      int64_t j, int32_t x, Ctr &c) {
@@ -85,44 +100,62 @@ __device__ __forceinline__ int32_t next_departure<EAT_LAYOUT_HYBRID>(const Graph
   if (ahead == 0) return INF;     // no departure in cluster k or later
   const int32_t idx = r.z + __popcll(m & ((1ull << k) - 1ull));
   const int2 h = G.hdr[idx];
-  c.hdr++;
+  const int2 h_next = G.hdr[idx + 1];  // in bounds: the header array has one padding entry
+  c.hdr += 2;
   if (!(ahead & 1ull) || x <= h.x) return h.x;
   if (h.y >= 0) {  // one progression t0 + i*d, i < n
     const int32_t d = h.y & 0xffff, n = h.y >> 16;
     const int32_t i = (x - h.x - 1) / d + 1;  // ceil((x - t0) / d), x > t0
     if (i < n) return h.x + i * d;
-  } else {  // sorted array p[1..n], p[1] = t0 < x
+  } else {  // sorted array p[1..n], p[0] = n, p[1] = t0 < x
     const int32_t *p = G.pool + (~h.y);
-    const int32_t n = p[0];
-    int32_t lo = 2, hi = n + 1;
-    c.pool++;
-    while (lo < hi) {
-      const int32_t mid = (lo + hi) >> 1;
-      c.pool++;
-      if (p[mid] < x) lo = mid + 1; else hi = mid;
+    const int4 c0 = reinterpret_cast<const int4 *>(p)[0];
+    const int4 c1 = reinterpret_cast<const int4 *>(p)[1];
+    const int32_t n = c0.x;
+    c.pool += 8;
+    int32_t t = INF;
+    if (n <= 7) {
+      const int32_t d7[8] = {c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w, INF};
+#pragma unroll
+      for (int i = 0; i < 7; ++i) t = (i < n && d7[i] >= x && d7[i] < t) ? d7[i] : t;
+    } else {
+      int32_t lo = 2, hi = n + 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        c.pool++;
+        if (p[mid] < x) lo = mid + 1; else hi = mid;
+      }
+      if (lo <= n) t = p[lo];
     }
-    if (lo <= n) {
-      c.pool++;
-      return p[lo];
-    }
+    if (t != INF) return t;
   }
   if ((ahead >> 1) == 0) return INF;
-  c.hdr++;
-  return G.hdr[idx + 1].x;
+  return h_next.x;
 }
 
-// Flat layout: one sorted array per type, bisection.
+// Flat layout: one sorted array per type.  Up to 16 departures are read as
+// four independent 16-byte chunks and scanned in registers; longer arrays are
+// bisected.
 template <>
 __device__ __forceinline__ int32_t next_departure<EAT_LAYOUT_FLAT>(const GraphDev &G, const int4 r,
                                                                    int64_t, int32_t x, Ctr &c) {
   const int32_t *p = G.pool + r.z;
-  int32_t lo = 0, hi = r.w;
+  const int32_t n = r.w;
+  if (n <= 16) {
+    const int4 *p4 = reinterpret_cast<const int4 *>(p);
+    const int4 q0 = p4[0], q1 = p4[1], q2 = p4[2], q3 = p4[3];
+    c.pool += 16;
+    const int32_t d[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                           q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+    return first_at_or_after(d, n, x);
+  }
+  int32_t lo = 0, hi = n;
   while (lo < hi) {
     const int32_t mid = (lo + hi) >> 1;
     c.pool++;
     if (p[mid] < x) lo = mid + 1; else hi = mid;
   }
-  if (lo < r.w) {
+  if (lo < n) {
     c.pool++;
     return p[lo];
   }
@@ -391,6 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       }
       break;
     }
+    const uint64_t t_start = wall_clock64();
     const QueryDev Q = batch ? a.queries[q] : a.single;
     const GraphDev G = a.graphs[batch ? Q.graph : 0];
     const int32_t V = G.n_vertices;
@@ -502,6 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
           st->header_loads = (int64_t)sh.acc[2];
           st->pool_loads = (int64_t)sh.acc[3];
           st->improvements = (int64_t)sh.acc[4];
+          st->elapsed_ns = (int64_t)((wall_clock64() - t_start) * (uint64_t)a.ns_per_tick >> 10);
         }
         if (qs.status != EAT_OK && a.n_failed)
           __hip_atomic_fetch_add(a.n_failed, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -38,6 +38,10 @@ inline bool rec_less(const Rec &a, const Rec &b) {
 }
 inline bool same_type(const Rec &a, const Rec &b) { return a.v == b.v && a.lam == b.lam; }
 
+// Pool entries start on 16-byte boundaries (the device reads them in int4
+// chunks); the gaps hold infinity.
+inline int64_t pad4(int64_t words) { return (words + 3) & ~int64_t(3); }
+
 int resolve_threads(int32_t req) {
   unsigned hw = std::thread::hardware_concurrency();
   int n = req > 0 ? req : (hw ? (int)hw : 4);
@@ -222,11 +226,11 @@ eat_status build_layout(const int32_t *u, const int32_t *v, const int32_t *t,
               if (ap) ++ap_c[(size_t)c];
               else {
                 ++arr_c[(size_t)c];
-                npl += 1 + cnt;
+                npl += pad4(1 + cnt);
               }
             });
           } else {
-            npl += j - i;
+            npl += pad4(j - i);
           }
           i = j;
         }
@@ -264,7 +268,9 @@ eat_status build_layout(const int32_t *u, const int32_t *v, const int32_t *t,
       L.mask_hi.assign((size_t)std::max<int64_t>(L.n_types, 1), 0u);
       L.hdr.assign((size_t)(2 * std::max<int64_t>(L.n_headers, 1)), 0);
     }
-    L.pool.assign((size_t)std::max<int64_t>(npool, 1), 0);
+    // kPoolTail words of infinity after the last entry keep the fixed-size
+    // chunk reads of the lookup inside the array
+    L.pool.assign((size_t)(npool + kPoolTail), EAT_INF);
   } catch (const std::bad_alloc &) {
     return fail(EAT_ERR_OUT_OF_MEMORY, "host allocation failed");
   }
@@ -295,8 +301,9 @@ eat_status build_layout(const int32_t *u, const int32_t *v, const int32_t *t,
                                  L.hdr[(size_t)(2 * hi + 1)] = (int32_t)((cnt << 16) | (cnt >= 2 ? h : 1));
                                } else {
                                  L.hdr[(size_t)(2 * hi + 1)] = ~(int32_t)pi;
-                                 L.pool[(size_t)pi++] = (int32_t)cnt;
-                                 for (int64_t q = 0; q < cnt; ++q) L.pool[(size_t)pi++] = b[i + beg + q].t;
+                                 L.pool[(size_t)pi] = (int32_t)cnt;
+                                 for (int64_t q = 0; q < cnt; ++q) L.pool[(size_t)(pi + 1 + q)] = b[i + beg + q].t;
+                                 pi += pad4(1 + cnt);
                                }
                                ++hi;
                              });
@@ -305,7 +312,8 @@ eat_status build_layout(const int32_t *u, const int32_t *v, const int32_t *t,
           } else {
             r[2] = (int32_t)pi;
             r[3] = (int32_t)(j - i);
-            for (int64_t q = i; q < j; ++q) L.pool[(size_t)pi++] = b[q].t;
+            for (int64_t q = i; q < j; ++q) L.pool[(size_t)(pi + (q - i))] = b[q].t;
+            pi += pad4(j - i);
           }
           ++ti;
           i = j;

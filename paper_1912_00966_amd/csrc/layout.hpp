@@ -25,6 +25,9 @@ struct eat_layout {
 
 namespace eat {
 
+// Words of infinity after the last pool entry.
+constexpr int64_t kPoolTail = 16;
+
 // Builds the layout; on failure returns a status and sets *err.
 eat_status build_layout(const int32_t *u, const int32_t *v, const int32_t *t,
                         const int32_t *lam, int64_t n, int32_t nv,

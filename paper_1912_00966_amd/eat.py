@@ -87,7 +87,7 @@ class QueryStats(ctypes.Structure):
                 ("reached", ctypes.c_int32), ("spilled", ctypes.c_int32),
                 ("activations", ctypes.c_int64), ("type_evals", ctypes.c_int64),
                 ("header_loads", ctypes.c_int64), ("pool_loads", ctypes.c_int64),
-                ("improvements", ctypes.c_int64)]
+                ("improvements", ctypes.c_int64), ("elapsed_ns", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
