@@ -59,14 +59,6 @@ eat_status device_limits(int dev, DeviceLimits *out) {
   return EAT_OK;
 }
 
-int auto_tpv(int64_t n_types, int32_t n_vertices) {
-  // one lane per type of an average stop, rounded up to a power of two
-  double avg = n_vertices > 0 ? (double)n_types / (double)n_vertices : 1.0;
-  int t = 1;
-  while (t < 64 && t < avg) t <<= 1;
-  return t;
-}
-
 bool valid_tpv(int t) { return t == 1 || t == 2 || t == 4 || t == 8 || t == 16 || t == 32 || t == 64; }
 
 }  // namespace
@@ -306,7 +298,10 @@ struct Plan {
   size_t lds = 0;
 };
 
-static size_t table_lds(int H, int fcap) { return (size_t)H * 8 + (size_t)(H / 32) * 4 + (size_t)fcap * 8; }
+// LDS bytes: two frontier lists + three scratch arrays of the load-balanced
+// expansion (fcap entries each), plus the arrival table or the stop bitmap.
+static size_t lists_lds(int fcap) { return (size_t)fcap * 20; }
+static size_t table_lds(int H, int fcap) { return (size_t)H * 8 + (size_t)(H / 32) * 4 + lists_lds(fcap); }
 
 static eat_status make_plan(const eat_run_options *ro, int32_t max_v, int64_t n_types_sum,
                             int64_t n_vertices_sum, int device, Plan *pl) {
@@ -322,12 +317,14 @@ static eat_status make_plan(const eat_run_options *ro, int32_t max_v, int64_t n_
   const bool table_auto = o.table_cap == 0;
   if (o.table_cap < -1 || (o.table_cap > 0 && ((o.table_cap & (o.table_cap - 1)) || o.table_cap < 64)))
     return set_err(EAT_ERR_INVALID_ARGUMENT, "table_cap must be 0, -1 or a power of two >= 64");
-  pl->tpv = o.threads_per_vertex ? o.threads_per_vertex
-                                 : auto_tpv(n_types_sum, (int32_t)std::min<int64_t>(n_vertices_sum, INT32_MAX));
+  // 0 = load-balanced expansion (one connection type per lane)
+  pl->tpv = o.threads_per_vertex;
+  (void)n_types_sum;
+  (void)n_vertices_sum;
   pl->mode = o.mode;
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;
-  int fcap = o.frontier_cap ? o.frontier_cap : 2048;
+  int fcap = o.frontier_cap ? o.frontier_cap : 1024;
   fcap = (fcap + 31) / 32 * 32;
   DeviceLimits lim;
   eat_status s = device_limits(device, &lim);
@@ -342,7 +339,7 @@ static eat_status make_plan(const eat_run_options *ro, int32_t max_v, int64_t n_
   // a frontier never holds more items than there are stops (or table slots)
   const int items = std::max(32, (std::max(max_v, H) + 31) / 32 * 32);
   fcap = std::min(fcap, items);
-  const size_t slab_lds = (size_t)pl->bm_words * 4 + (size_t)fcap * 8;
+  const size_t slab_lds = (size_t)pl->bm_words * 4 + lists_lds(fcap);
   while (table_auto && H >= 64 && std::max(table_lds(H, fcap), slab_lds) > lim.lds) H >>= 1;
   if (H < 64) H = 0;
   if (H && std::max(table_lds(H, fcap), slab_lds) > lim.lds)

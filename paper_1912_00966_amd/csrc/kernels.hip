@@ -283,30 +283,104 @@ __device__ __forceinline__ void relax(const GraphDev &G, const Store &S, int64_t
   push(want, item, nxt, fcap, append, sh_nn);
 }
 
-// Expand every item of list[0..n): groups of TPV lanes, one stop per group.
+struct Shared {
+  int32_t q, nn, cnt, count, over, reached;
+  int32_t wsum[kBlock / 64];
+  unsigned long long acc[5];
+};
+
+// Scratch arrays of the load-balanced expansion (fcap entries each).
+struct Prep {
+  int32_t *beg;  // first type of the entry's stop
+  int32_t *x;    // the stop's arrival time
+  int32_t *off;  // exclusive prefix sum of the entries' type counts
+};
+
+// Exclusive prefix sum of v over the work-group; *total receives the sum.
+// Every thread must call it; it ends with a barrier.
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, Shared &sh, int32_t *total) {
+  constexpr int kWaves = kBlock / 64;
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  int32_t s = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t o = __shfl_up(s, d);
+    if (lane >= d) s += o;
+  }
+  if (lane == 63) sh.wsum[w] = s;
+  __syncthreads();
+  if (w == 0) {
+    int32_t t = lane < kWaves ? sh.wsum[lane] : 0;
+#pragma unroll
+    for (int d = 1; d < kWaves; d <<= 1) {
+      const int32_t o = __shfl_up(t, d);
+      if (lane >= d) t += o;
+    }
+    if (lane < kWaves) sh.wsum[lane] = t;
+  }
+  __syncthreads();
+  const int32_t base = w ? sh.wsum[w - 1] : 0;
+  *total = sh.wsum[kWaves - 1];
+  __syncthreads();  // wsum may be reused by the next call
+  return base + s - v;
+}
+
+// Expand every item of list[0..n).
+// TPV == 0: load-balanced -- the connection types of all listed stops form one
+//   index space (prefix sum of their type counts) and lane k relaxes types
+//   k, k + kBlock, ...; a lane finds its stop by bisection of the prefix sums.
+// TPV > 0: virtual warps (Section IV-B) -- groups of TPV lanes, one stop per
+//   group, lane i of a group takes the stop's types i, i + TPV, ...
 template <int TPV, int KIND, class Store>
 __device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, const int32_t *list,
                                             int32_t n, int32_t *nxt, int32_t fcap, bool append,
-                                            int32_t *sh_nn, Ctr &c) {
-  constexpr int kGroups = kBlock / TPV;
-  const int g = threadIdx.x / TPV, lane = threadIdx.x % TPV;
-  for (int32_t base = 0; base < n; base += kGroups) {
-    const int32_t i = base + g;
-    if (i < n) {
-      const int32_t item = list[i];
-      const int32_t u = S.stop(item);
-      const int32_t x = S.value(item);
-      const int32_t b = G.vt_off[u], e = G.vt_off[u + 1];
-      if (lane == 0) c.act++;
-      for (int32_t j = b + lane; j < e; j += TPV) relax<KIND>(G, S, j, x, nxt, fcap, append, sh_nn, c);
+                                            Shared &sh, const Prep &P, Ctr &c) {
+  if constexpr (TPV == 0) {
+    int32_t carry = 0;
+    for (int32_t e0 = 0; e0 < n; e0 += kBlock) {
+      const int32_t e = e0 + (int32_t)threadIdx.x;
+      int32_t d = 0;
+      if (e < n) {
+        const int32_t item = list[e];
+        const int32_t u = S.stop(item);
+        const int32_t b = G.vt_off[u];
+        d = G.vt_off[u + 1] - b;
+        P.beg[e] = b;
+        P.x[e] = S.value(item);
+        c.act++;
+      }
+      int32_t tot;
+      const int32_t off = block_exclusive_scan(d, sh, &tot);
+      if (e < n) P.off[e] = carry + off;
+      carry += tot;
+    }
+    __syncthreads();
+    const int32_t total = carry;
+    for (int32_t k = threadIdx.x; k < total; k += kBlock) {
+      int32_t lo = 0, hi = n;  // first entry whose offset exceeds k
+      while (lo < hi) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (P.off[mid] <= k) lo = mid + 1; else hi = mid;
+      }
+      const int32_t i = lo - 1;
+      relax<KIND>(G, S, (int64_t)P.beg[i] + (k - P.off[i]), P.x[i], nxt, fcap, append, &sh.nn, c);
+    }
+  } else {
+    constexpr int kGroups = kBlock / TPV;
+    const int g = threadIdx.x / TPV, lane = threadIdx.x % TPV;
+    for (int32_t base = 0; base < n; base += kGroups) {
+      const int32_t i = base + g;
+      if (i < n) {
+        const int32_t item = list[i];
+        const int32_t u = S.stop(item);
+        const int32_t x = S.value(item);
+        const int32_t b = G.vt_off[u], e = G.vt_off[u + 1];
+        if (lane == 0) c.act++;
+        for (int32_t j = b + lane; j < e; j += TPV) relax<KIND>(G, S, j, x, nxt, fcap, append, &sh.nn, c);
+      }
     }
   }
 }
-
-struct Shared {
-  int32_t q, nn, cnt, count, over, reached;
-  unsigned long long acc[5];
-};
 
 struct QState {
   int32_t rounds = 0, sweeps = 0, maxf = 1, status = EAT_OK;
@@ -318,7 +392,7 @@ struct QState {
 // other bit is clear.  Returns false if the store overflowed.
 template <int TPV, int KIND, class Store>
 __device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, int32_t n_items,
-                           int32_t *list0, int32_t *list1, bool topo, int32_t max_rounds,
+                           int32_t *list0, int32_t *list1, const Prep &P, bool topo, int32_t max_rounds,
                            Shared &sh, QState &qs, Ctr &c) {
   const int tid = threadIdx.x;
   const int32_t nwords = (n_items + 31) >> 5;
@@ -335,7 +409,7 @@ __device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, 
     if (tid == 0) sh.nn = 0;
     __syncthreads();
     if (!sweep) {
-      expand_list<TPV, KIND>(G, S, cur, nf, nxt, a.fcap, !topo, &sh.nn, c);
+      expand_list<TPV, KIND>(G, S, cur, nf, nxt, a.fcap, !topo, sh, P, c);
     } else {
       ++qs.sweeps;
       for (int32_t w0 = 0; w0 < nwords; w0 += chunk_words) {
@@ -356,7 +430,7 @@ __device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, 
         }
         __syncthreads();
         const int32_t cnt = sh.cnt;
-        if (cnt) expand_list<TPV, KIND>(G, S, cur, cnt, nxt, a.fcap, !topo, &sh.nn, c);
+        if (cnt) expand_list<TPV, KIND>(G, S, cur, cnt, nxt, a.fcap, !topo, sh, P, c);
         __syncthreads();
       }
     }
@@ -460,6 +534,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       T.limit = H - H / 4;
       int32_t *l0 = reinterpret_cast<int32_t *>(T.bits + (H >> 5));
       int32_t *l1 = l0 + a.fcap;
+      const Prep P{l1 + a.fcap, l1 + 2 * a.fcap, l1 + 3 * a.fcap};
       for (int32_t i = tid; i < H; i += kBlock) {
         T.keys[i] = EMPTY;
         T.vals[i] = INF;
@@ -473,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
         else l0[0] = p;
       }
       __syncthreads();
-      if (run_rounds<TPV, KIND>(a, G, T, H, l0, l1, topo, max_rounds, sh, qs, c)) {
+      if (run_rounds<TPV, KIND>(a, G, T, H, l0, l1, P, topo, max_rounds, sh, qs, c)) {
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the infinity fill has landed
         __syncthreads();
         for (int32_t p = tid; p < H; p += kBlock) {
@@ -495,6 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       const int32_t VW = (V + 31) >> 5;
       int32_t *l0 = reinterpret_cast<int32_t *>(lds + VW);
       int32_t *l1 = l0 + a.fcap;
+      const Prep P{l1 + a.fcap, l1 + 2 * a.fcap, l1 + 3 * a.fcap};
       // (an overflowed table attempt never wrote the slab: it still holds infinity)
       for (int32_t i = tid; i < VW; i += kBlock) S.bits[i] = 0u;
       if (tid == 0) sh.over = 0;
@@ -506,7 +582,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       }
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
-      run_rounds<TPV, KIND>(a, G, S, V, l0, l1, topo, max_rounds, sh, qs, c);
+      run_rounds<TPV, KIND>(a, G, S, V, l0, l1, P, topo, max_rounds, sh, qs, c);
       // reached stops
       int32_t mine = 0;
       for (int32_t i = tid; i < V; i += kBlock) mine += ld_arr(arr + i) != INF;
@@ -571,6 +647,7 @@ using RelaxFn = void (*)(RunArgs);
 template <int KIND>
 RelaxFn relax_fn(int tpv) {
   switch (tpv) {
+    case 0: return k_relax<0, KIND>;
     case 1: return k_relax<1, KIND>;
     case 2: return k_relax<2, KIND>;
     case 4: return k_relax<4, KIND>;

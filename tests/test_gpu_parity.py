@@ -132,7 +132,7 @@ def test_next_departure_matches_definition(layout):
 # ------------------------------------------------------------- single queries
 
 @pytest.mark.parametrize("layout", ["hybrid", "flat"])
-@pytest.mark.parametrize("tpv", [1, 4, 16, 64])
+@pytest.mark.parametrize("tpv", [0, 1, 4, 16, 64])
 def test_single_queries_city_1k_bit_exact(layout, tpv):
     tt, q = _workload("city-1k")
     exp = _expected("city-1k")
@@ -182,7 +182,7 @@ def test_repeated_runs_are_identical():
     g = _graph("city-1k", "hybrid")
     s, ts = int(q.s[0]), int(q.ts[0])
     first, _ = _query(g, s, ts)
-    for tpv in (2, 8, 32):
+    for tpv in (0, 2, 8, 32):
         for _ in range(5):
             again, _ = _query(g, s, ts, threads_per_vertex=tpv)
             assert np.array_equal(first, again)
