@@ -63,9 +63,6 @@ struct Ctr {
 // Next departure of connection type j at or after x (Section II-B:
 // t_c = min{t in C_{u,v,lam} : t >= x}); INF when there is none.
 // ---------------------------------------------------------------------------
-template <int KIND>
-__device__ __forceinline__ int32_t next_departure(const GraphDev &G, const int4 r, int64_t j,
-                                                  int32_t x, Ctr &c);
 
 // First of the sorted departures d[0..n) (n <= 16, read from 16-byte chunks)
 // that is >= x, or INF.  Words past n are ignored.
@@ -79,87 +76,150 @@ __device__ __forceinline__ int32_t first_at_or_after(const int32_t *d, int32_t n
   return best;
 }
 
+// A lookup is split into stages so that a lane can keep several lookups in
+// flight: locate (needs the type record), fetch (header / departure chunks),
+// finish (arithmetic on registers).
+//
 // Hybrid layout: hourly clusters (Section II-D) + one progression or a sorted
 // array per cluster.  Cluster k = x / width.  If cluster k holds departures,
 // the first one >= x inside it comes from the progression closed form
 // t0 + ceil((x - t0) / h) * h (Algorithm 6) or from its sorted array;
 // otherwise -- cluster k empty, or all its departures earlier than x -- the
 // answer is the first departure of the next non-empty cluster (Section II-D),
-// which is the next header because only non-empty clusters have one.  That
-// next header is read together with the first, so the fall-through costs no
-// extra dependent memory access; short arrays (<= 7 departures, the common
-// case) are read as two independent 16-byte chunks.
-template <>
-__device__ __forceinline__ int32_t next_departure<EAT_LAYOUT_HYBRID>(const GraphDev &G, const int4 r,
-                                                                     int64_t j, int32_t x, Ctr &c) {
-  const uint32_t k = (uint32_t)x / (uint32_t)G.cluster_seconds;
-  if (k >= (uint32_t)G.n_clusters) return INF;  // after the last departure of the timetable
-  uint64_t m = (uint32_t)r.w;
-  if (G.mask_hi) m |= (uint64_t)G.mask_hi[j] << 32;
-  const uint64_t ahead = m >> k;  // bit 0: cluster k itself
-  if (ahead == 0) return INF;     // no departure in cluster k or later
-  const int32_t idx = r.z + __popcll(m & ((1ull << k) - 1ull));
-  const int2 h = G.hdr[idx];
-  const int2 h_next = G.hdr[idx + 1];  // in bounds: the header array has one padding entry
-  c.hdr += 2;
-  if (!(ahead & 1ull) || x <= h.x) return h.x;
-  if (h.y >= 0) {  // one progression t0 + i*d, i < n
-    const int32_t d = h.y & 0xffff, n = h.y >> 16;
-    const int32_t i = (x - h.x - 1) / d + 1;  // ceil((x - t0) / d), x > t0
-    if (i < n) return h.x + i * d;
-  } else {  // sorted array p[1..n], p[0] = n, p[1] = t0 < x
-    const int32_t *p = G.pool + (~h.y);
-    const int4 c0 = reinterpret_cast<const int4 *>(p)[0];
-    const int4 c1 = reinterpret_cast<const int4 *>(p)[1];
-    const int32_t n = c0.x;
-    c.pool += 8;
-    int32_t t = INF;
-    if (n <= 7) {
-      const int32_t d7[8] = {c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w, INF};
-#pragma unroll
-      for (int i = 0; i < 7; ++i) t = (i < n && d7[i] >= x && d7[i] < t) ? d7[i] : t;
-    } else {
-      int32_t lo = 2, hi = n + 1;
-      while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        c.pool++;
-        if (p[mid] < x) lo = mid + 1; else hi = mid;
-      }
-      if (lo <= n) t = p[lo];
-    }
-    if (t != INF) return t;
+// which is the next header because only non-empty clusters have one.  The
+// next header is fetched together with the first; arrays of <= 7 departures
+// (the common case) are read as two independent 16-byte chunks.
+struct Look {
+  int32_t idx;    // header index (hybrid)
+  int32_t mode;   // 0: no departure >= x; 1: the first departure of header idx; 2: search in header idx
+  bool has_next;  // another non-empty cluster follows cluster idx
+  int2 h, hn;     // header idx and idx + 1 (hybrid)
+  int4 c0, c1;    // first chunks of an array cluster (hybrid) or departures 0..7 (flat)
+  int4 c2, c3;    // departures 8..15 (flat)
+};
+
+template <int KIND>
+__device__ __forceinline__ void look_locate(const GraphDev &G, const int4 r, uint32_t mhi, int32_t x, Look &L) {
+  if constexpr (KIND == EAT_LAYOUT_HYBRID) {
+    L.mode = 0;
+    L.idx = 0;
+    L.has_next = false;
+    const uint32_t k = (uint32_t)x / (uint32_t)G.cluster_seconds;
+    if (k >= (uint32_t)G.n_clusters) return;  // after the last departure of the timetable
+    const uint64_t m = (uint64_t)(uint32_t)r.w | ((uint64_t)mhi << 32);
+    const uint64_t ahead = m >> k;  // bit 0: cluster k itself
+    if (ahead == 0) return;         // no departure in cluster k or later
+    L.idx = r.z + __popcll(m & ((1ull << k) - 1ull));
+    L.mode = (ahead & 1ull) ? 2 : 1;
+    L.has_next = (ahead >> 1) != 0;
+  } else {
+    L.mode = r.w > 0 ? 2 : 0;
   }
-  if ((ahead >> 1) == 0) return INF;
-  return h_next.x;
 }
 
-// Flat layout: one sorted array per type.  Up to 16 departures are read as
-// four independent 16-byte chunks and scanned in registers; longer arrays are
-// bisected.
-template <>
-__device__ __forceinline__ int32_t next_departure<EAT_LAYOUT_FLAT>(const GraphDev &G, const int4 r,
-                                                                   int64_t, int32_t x, Ctr &c) {
-  const int32_t *p = G.pool + r.z;
-  const int32_t n = r.w;
-  if (n <= 16) {
-    const int4 *p4 = reinterpret_cast<const int4 *>(p);
-    const int4 q0 = p4[0], q1 = p4[1], q2 = p4[2], q3 = p4[3];
-    c.pool += 16;
-    const int32_t d[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
-                           q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
-    return first_at_or_after(d, n, x);
+// Issues the memory reads of a located lookup (no use of their results).
+template <int KIND>
+__device__ __forceinline__ void look_fetch_headers(const GraphDev &G, const int4 r, Look &L) {
+  if constexpr (KIND == EAT_LAYOUT_HYBRID) {
+    // header idx + 1 exists: the header array carries one padding entry
+    L.h = G.hdr[L.idx];
+    L.hn = G.hdr[L.idx + 1];
+  } else {
+    if (L.mode != 0 && r.w <= 16) {
+      const int4 *p4 = reinterpret_cast<const int4 *>(G.pool + r.z);
+      L.c0 = p4[0];
+      L.c1 = p4[1];
+      L.c2 = p4[2];
+      L.c3 = p4[3];
+    }
   }
-  int32_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int32_t mid = (lo + hi) >> 1;
-    c.pool++;
-    if (p[mid] < x) lo = mid + 1; else hi = mid;
+}
+
+// Hybrid only: the chunks of an array cluster that x falls into (needs the header).
+template <int KIND>
+__device__ __forceinline__ void look_fetch_chunks(const GraphDev &G, int32_t x, Look &L, Ctr &c) {
+  if constexpr (KIND == EAT_LAYOUT_HYBRID) {
+    if (L.mode == 2 && L.h.y < 0 && x > L.h.x) {
+      const int4 *p4 = reinterpret_cast<const int4 *>(G.pool + (~L.h.y));
+      L.c0 = p4[0];
+      L.c1 = p4[1];
+      c.pool += 8;
+    }
   }
-  if (lo < n) {
-    c.pool++;
-    return p[lo];
+}
+
+template <int KIND>
+__device__ __forceinline__ int32_t look_finish(const GraphDev &G, const int4 r, int32_t x, const Look &L, Ctr &c) {
+  if (L.mode == 0) return INF;
+  if constexpr (KIND == EAT_LAYOUT_HYBRID) {
+    const int2 h = L.h;
+    if (L.mode == 1 || x <= h.x) return h.x;
+    if (h.y >= 0) {  // one progression t0 + i*d, i < n
+      const int32_t d = h.y & 0xffff, n = h.y >> 16;
+      const int32_t i = (x - h.x - 1) / d + 1;  // ceil((x - t0) / d), x > t0
+      if (i < n) return h.x + i * d;
+    } else {  // sorted array p[1..n], p[0] = n, p[1] = t0 < x
+      const int32_t n = L.c0.x;
+      int32_t t = INF;
+      if (n <= 7) {
+        const int32_t d7[7] = {L.c0.y, L.c0.z, L.c0.w, L.c1.x, L.c1.y, L.c1.z, L.c1.w};
+#pragma unroll
+        for (int i = 0; i < 7; ++i) t = (i < n && d7[i] >= x && d7[i] < t) ? d7[i] : t;
+      } else {
+        const int32_t *p = G.pool + (~h.y);
+        int32_t lo = 2, hi = n + 1;
+        while (lo < hi) {
+          const int32_t mid = (lo + hi) >> 1;
+          c.pool++;
+          if (p[mid] < x) lo = mid + 1; else hi = mid;
+        }
+        if (lo <= n) t = p[lo];
+      }
+      if (t != INF) return t;
+    }
+    return L.has_next ? L.hn.x : INF;
+  } else {
+    const int32_t n = r.w;
+    if (n <= 16) {
+      const int32_t d[16] = {L.c0.x, L.c0.y, L.c0.z, L.c0.w, L.c1.x, L.c1.y, L.c1.z, L.c1.w,
+                             L.c2.x, L.c2.y, L.c2.z, L.c2.w, L.c3.x, L.c3.y, L.c3.z, L.c3.w};
+      return first_at_or_after(d, n, x);
+    }
+    // long arrays: bisection
+    const int32_t *p = G.pool + r.z;
+    int32_t lo = 0, hi = n;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      c.pool++;
+      if (p[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    if (lo < n) {
+      c.pool++;
+      return p[lo];
+    }
+    return INF;
   }
-  return INF;
+}
+
+// Counts the words of a header fetch that a lookup actually needs.
+template <int KIND>
+__device__ __forceinline__ void count_fetch(const int4 r, const Look &L, Ctr &c) {
+  if constexpr (KIND == EAT_LAYOUT_HYBRID) c.hdr += 2;
+  else if (L.mode != 0 && r.w <= 16) c.pool += 16;
+}
+
+// Next departure of connection type j at or after x (Section II-B:
+// t_c = min{t in C_{u,v,lam} : t >= x}); INF when there is none.
+template <int KIND>
+__device__ __forceinline__ int32_t next_departure(const GraphDev &G, const int4 r, int64_t j, int32_t x, Ctr &c) {
+  Look L;
+  const uint32_t mhi = (KIND == EAT_LAYOUT_HYBRID && G.mask_hi) ? G.mask_hi[j] : 0u;
+  look_locate<KIND>(G, r, mhi, x, L);
+  if (L.mode == 0) return INF;
+  look_fetch_headers<KIND>(G, r, L);
+  count_fetch<KIND>(r, L, c);
+  look_fetch_chunks<KIND>(G, x, L, c);
+  return look_finish<KIND>(G, r, x, L, c);
 }
 
 // ---------------------------------------------------------------------------
@@ -325,6 +385,71 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, Shared &sh, i
   return base + s - v;
 }
 
+// Relax U connection types per lane with their memory reads overlapped: all
+// type records, then all (speculative) cluster headers, then the on-chip
+// arrival lookups, then the rare array chunks, then the updates.
+template <int KIND, int U, class Store>
+__device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, const int64_t *j,
+                                            const int32_t *x, const bool *ok, int32_t *nxt, int32_t fcap,
+                                            bool append, int32_t *sh_nn, Ctr &c) {
+  int4 r[U];
+  uint32_t mhi[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t jj = ok[u] ? j[u] : 0;  // type 0 always exists when any item does
+    r[u] = G.ty[jj];
+    mhi[u] = (KIND == EAT_LAYOUT_HYBRID && G.mask_hi) ? G.mask_hi[jj] : 0u;
+  }
+  Look L[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    look_locate<KIND>(G, r[u], mhi[u], x[u], L[u]);
+    if (!ok[u]) L[u].mode = 0;
+    look_fetch_headers<KIND>(G, r[u], L[u]);
+  }
+  int32_t av[U];
+  bool live[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    av[u] = ok[u] ? S.find(r[u].x) : INF;
+    // any departure leaves at t_c >= x, so it arrives at >= x + lam: skip the
+    // type when that cannot beat arr[v] (early termination, Section III-D)
+    live[u] = ok[u] && x[u] < av[u] - r[u].y && L[u].mode != 0;
+    if (ok[u]) c.tev++;
+    if (live[u]) {
+      count_fetch<KIND>(r[u], L[u], c);
+      look_fetch_chunks<KIND>(G, x[u], L[u], c);
+    }
+  }
+  bool want[U];
+  int32_t item[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    want[u] = false;
+    item[u] = 0;
+    if (live[u]) {
+      const int32_t tc = look_finish<KIND>(G, r[u], x[u], L[u], c);
+      if (tc != INF) {
+        const int32_t cand = tc + r[u].y;
+        if (cand < av[u]) {
+          const int32_t it = S.slot(r[u].x);
+          if (it >= 0) {
+            const int32_t old = S.lower(it, cand);
+            if (cand < old) {
+              c.imp++;
+              const uint32_t bit = 1u << (it & 31);
+              want[u] = !(atomicOr(&S.bits[it >> 5], bit) & bit);
+              item[u] = it;
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) push(want[u], item[u], nxt, fcap, append, sh_nn);
+}
+
 // Expand every item of list[0..n).
 // TPV == 0: load-balanced -- the connection types of all listed stops form one
 //   index space (prefix sum of their type counts) and lane k relaxes types
@@ -356,14 +481,25 @@ __device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, c
     }
     __syncthreads();
     const int32_t total = carry;
-    for (int32_t k = threadIdx.x; k < total; k += kBlock) {
-      int32_t lo = 0, hi = n;  // first entry whose offset exceeds k
-      while (lo < hi) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (P.off[mid] <= k) lo = mid + 1; else hi = mid;
+    constexpr int U = 2;
+    for (int32_t k0 = threadIdx.x; k0 < total; k0 += kBlock * U) {
+      int64_t jj[U];
+      int32_t xx[U];
+      bool ok[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t k = k0 + u * kBlock;
+        ok[u] = k < total;
+        int32_t lo = 0, hi = ok[u] ? n : 0;  // first entry whose offset exceeds k
+        while (lo < hi) {
+          const int32_t mid = (lo + hi) >> 1;
+          if (P.off[mid] <= k) lo = mid + 1; else hi = mid;
+        }
+        const int32_t i = ok[u] ? lo - 1 : 0;
+        jj[u] = ok[u] ? (int64_t)P.beg[i] + (k - P.off[i]) : 0;
+        xx[u] = ok[u] ? P.x[i] : 0;
       }
-      const int32_t i = lo - 1;
-      relax<KIND>(G, S, (int64_t)P.beg[i] + (k - P.off[i]), P.x[i], nxt, fcap, append, &sh.nn, c);
+      relax_batch<KIND, U>(G, S, jj, xx, ok, nxt, fcap, append, &sh.nn, c);
     }
   } else {
     constexpr int kGroups = kBlock / TPV;
