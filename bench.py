@@ -59,6 +59,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-query comparison")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the timed region, run one device-to-device copy of MIB MiB "
+                         "(a kernel of known traffic, to scale profiler byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -87,6 +90,15 @@ def main():
     info = g.info
     log(f"[bench] preprocess+upload {prep_s:.2f}s: T={info.n_types} K={info.n_headers} "
         f"ap={info.n_ap_clusters} array={info.n_array_clusters} device={info.device_bytes / 2**20:.1f} MiB")
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * 2**20 // 4
+        src = torch.ones(n, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written")
+        del src, dst
 
     V, Q = tt.n_vertices, len(q)
     slab = torch.empty((Q, V), dtype=torch.int32, device=dev)
