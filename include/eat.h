@@ -218,6 +218,59 @@ eat_status eat_query_batch(const eat_graph *const *graphs, int32_t n_graphs,
                            eat_query_stats *stats);
 
 /* ---------------------------------------------------------------------------
+ * Serving sessions: continuous batching over device-resident graphs.
+ *
+ * A session owns a pool of device memory for result slots.  eat_session_admit
+ * reserves one slot (n_vertices int32 of the query's graph) or returns
+ * EAT_ERR_BUSY when no free range of the pool fits.  eat_session_step launches,
+ * in one kernel launch, every query admitted since the previous step, on the
+ * next of the session's streams; several steps can be in flight at once, so
+ * queries admitted while earlier ones are still running share the device
+ * with them.  eat_session_poll reports finished slots without blocking; a
+ * finished slot's arrival array stays valid until eat_session_release.
+ * A session is not thread-safe: one thread drives it.
+ * ------------------------------------------------------------------------- */
+typedef struct eat_session eat_session;
+
+typedef struct {
+  int64_t pool_bytes;       /* device memory for result slots; 0 = 256 MiB */
+  int32_t n_streams;        /* launches in flight at once (1..8); 0 = 2 */
+  int32_t max_step_queries; /* queries one step launches at most; 0 = 4096 */
+  eat_run_options run;      /* options of every launch (NULL-equivalent when zero) */
+  int32_t reserved[4];      /* must be zero */
+} eat_session_options;
+
+/* graphs: n_graphs resident graphs (they must outlive the session). */
+eat_status eat_session_create(const eat_graph *const *graphs, int32_t n_graphs,
+                              const eat_session_options *opt, eat_session **out);
+/* Reserves a slot for query (s, ts) on graphs[graph]; *slot receives its id.
+ * EAT_ERR_BUSY: no room in the pool (nothing reserved); EAT_ERR_INVALID_ARGUMENT
+ * for a bad graph index, s or ts. */
+eat_status eat_session_admit(eat_session *sess, int32_t graph, int32_t s, int32_t ts,
+                             int32_t *slot);
+/* Launches the queries admitted since the last step (up to max_step_queries;
+ * the rest wait for the next step).  If every stream is busy it waits for the
+ * oldest launch to finish.  *n_launched (nullable) receives the count. */
+eat_status eat_session_step(eat_session *sess, int32_t *n_launched);
+/* Writes up to cap finished slot ids into done (host array); *n receives the
+ * count.  Never blocks. */
+eat_status eat_session_poll(eat_session *sess, int32_t *done, int32_t cap, int32_t *n);
+/* Blocks until every launched query has finished (they are then reported by
+ * eat_session_poll). */
+eat_status eat_session_sync(eat_session *sess);
+/* Device pointer to a finished slot's arrival array and its length. */
+eat_status eat_session_result(eat_session *sess, int32_t slot, const int32_t **arr,
+                              int32_t *n_vertices);
+/* Copies a finished slot's n_vertices int32 into dst (device or pinned/pageable
+ * host memory), asynchronously on stream. */
+eat_status eat_session_copy(eat_session *sess, int32_t slot, int32_t *dst, void *stream);
+/* Statistics of a finished slot's query (elapsed_ns is device time). */
+eat_status eat_session_query_stats(eat_session *sess, int32_t slot, eat_query_stats *out);
+/* Frees a finished (or admitted but not yet launched) slot. */
+eat_status eat_session_release(eat_session *sess, int32_t slot);
+void eat_session_free(eat_session *sess); /* NULL-safe; waits for the device */
+
+/* ---------------------------------------------------------------------------
  * Diagnostics
  * ------------------------------------------------------------------------- */
 /* For each probe i: out[i] = the first departure >= x[i] of connection type

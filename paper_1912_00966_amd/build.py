@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libeat.so")
-SOURCES = ["layout.cpp", "capi.cpp", "kernels.hip"]
+SOURCES = ["layout.cpp", "capi.cpp", "session.cpp", "kernels.hip"]
 ARCH = "gfx950"
 
 

@@ -13,6 +13,7 @@
 
 #include "device.hpp"
 #include "eat.h"
+#include "internal.hpp"
 #include "layout.hpp"
 
 using eat::GraphDev;
@@ -20,8 +21,11 @@ using eat::QueryDev;
 using eat::RunArgs;
 
 namespace {
-
 thread_local std::string g_last_error;
+bool valid_tpv(int t) { return t == 1 || t == 2 || t == 4 || t == 8 || t == 16 || t == 32 || t == 64; }
+}  // namespace
+
+namespace eat {
 
 eat_status set_err(eat_status s, const std::string &msg) {
   g_last_error = msg;
@@ -31,21 +35,6 @@ eat_status set_err(eat_status s, const std::string &msg) {
 eat_status hip_err(hipError_t e, const char *what) {
   return set_err(EAT_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
-
-#define HIP_TRY(call)                                   \
-  do {                                                  \
-    hipError_t e_ = (call);                             \
-    if (e_ != hipSuccess) return hip_err(e_, #call);    \
-  } while (0)
-
-constexpr size_t kAlign = 256;
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-struct DeviceLimits {
-  int cus = 0;
-  size_t lds = 0;
-  int64_t ns_per_tick = 10 << 10;  // wall clock period in ns, fixed point x 1024
-};
 
 eat_status device_limits(int dev, DeviceLimits *out) {
   hipDeviceProp_t p;
@@ -59,20 +48,16 @@ eat_status device_limits(int dev, DeviceLimits *out) {
   return EAT_OK;
 }
 
-bool valid_tpv(int t) { return t == 1 || t == 2 || t == 4 || t == 8 || t == 16 || t == 32 || t == 64; }
+}  // namespace eat
 
-}  // namespace
+using eat::Plan;
+using eat::set_err;
+using eat::hip_err;
+using eat::align_up;
+using eat::DeviceLimits;
+using eat::device_limits;
+using eat::make_plan;
 
-struct eat_graph {
-  int device = 0;
-  eat_graph_info_t info{};
-  GraphDev desc{};            // device pointers
-  GraphDev *d_desc = nullptr; // device copy of desc
-  void *d_buf = nullptr;
-  std::mutex mu;              // guards the single-query scratch
-  eat_query_stats *d_stats = nullptr;
-  int32_t *d_failed = nullptr;
-};
 
 struct eat_batch {
   int device = 0;
@@ -286,25 +271,14 @@ extern "C" eat_status eat_graph_info(const eat_graph *g, eat_graph_info_t *out) 
 // ---------------------------------------------------------------------------
 // run options
 // ---------------------------------------------------------------------------
-struct Plan {
-  int tpv = 1;
-  int mode = EAT_MODE_AUTO;
-  int max_rounds = 0;
-  int fcap = 0;
-  int bm_words = 0;
-  int table_cap = 0;
-  int table_bits = 0;
-  int64_t ns_per_tick = 0;
-  size_t lds = 0;
-};
+namespace eat {
 
 // LDS bytes: two frontier lists + three scratch arrays of the load-balanced
 // expansion (fcap entries each), plus the arrival table or the stop bitmap.
 static size_t lists_lds(int fcap) { return (size_t)fcap * 20; }
 static size_t table_lds(int H, int fcap) { return (size_t)H * 8 + (size_t)(H / 32) * 4 + lists_lds(fcap); }
 
-static eat_status make_plan(const eat_run_options *ro, int32_t max_v, int64_t n_types_sum,
-                            int64_t n_vertices_sum, int device, Plan *pl) {
+eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan *pl) {
   eat_run_options o{};
   if (ro) o = *ro;
   for (int r : o.reserved)
@@ -319,8 +293,6 @@ static eat_status make_plan(const eat_run_options *ro, int32_t max_v, int64_t n_
     return set_err(EAT_ERR_INVALID_ARGUMENT, "table_cap must be 0, -1 or a power of two >= 64");
   // 0 = load-balanced expansion (one connection type per lane)
   pl->tpv = o.threads_per_vertex;
-  (void)n_types_sum;
-  (void)n_vertices_sum;
   pl->mode = o.mode;
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;
@@ -357,6 +329,19 @@ static eat_status make_plan(const eat_run_options *ro, int32_t max_v, int64_t n_
   return EAT_OK;
 }
 
+void apply_plan(const Plan &pl, RunArgs *a) {
+  a->max_rounds = pl.max_rounds;
+  a->mode = pl.mode;
+  a->fcap = pl.fcap;
+  a->bm_words = pl.bm_words;
+  a->table_cap = pl.table_cap;
+  a->table_bits = pl.table_bits;
+  a->ns_per_tick = pl.ns_per_tick;
+}
+
+}  // namespace eat
+
+
 // ---------------------------------------------------------------------------
 // single query
 // ---------------------------------------------------------------------------
@@ -370,20 +355,14 @@ extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32
   HIP_TRY(hipGetDevice(&cur));
   if (cur != g->device) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph lives on another device than the current one");
   Plan pl;
-  eat_status st = make_plan(ro, g->info.n_vertices, g->info.n_types, g->info.n_vertices, g->device, &pl);
+  eat_status st = make_plan(ro, g->info.n_vertices, g->device, &pl);
   if (st != EAT_OK) return st;
   RunArgs a{};
   a.graphs = g->d_desc;
   a.queries = nullptr;
   a.single = QueryDev{0, s, ts, 0, arr};
   a.nq = 1;
-  a.max_rounds = pl.max_rounds;
-  a.mode = pl.mode;
-  a.fcap = pl.fcap;
-  a.bm_words = pl.bm_words;
-  a.table_cap = pl.table_cap;
-  a.table_bits = pl.table_bits;
-  a.ns_per_tick = pl.ns_per_tick;
+  eat::apply_plan(pl, &a);
   a.work = nullptr;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   eat_graph *gm = const_cast<eat_graph *>(g);
@@ -431,7 +410,6 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
       return set_err(EAT_ERR_UNSUPPORTED, "all graphs of one batch must share a layout kind");
   }
   std::vector<QueryDev> qs((size_t)n_q);
-  int64_t types_sum = 0, verts_sum = 0;
   for (int32_t i = 0; i < n_q; ++i) {
     const int32_t gi = q_graph[i];
     if (gi < 0 || gi >= n_graphs) return set_err(EAT_ERR_INVALID_ARGUMENT, "query " + std::to_string(i) + ": graph index out of range");
@@ -442,15 +420,13 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
     if (!arr[i]) return set_err(EAT_ERR_INVALID_ARGUMENT, "query " + std::to_string(i) + ": arr is NULL");
     qs[(size_t)i] = QueryDev{gi, q_src[i], q_ts[i], i, arr[i]};
     max_v = std::max(max_v, g->info.n_vertices);
-    types_sum += g->info.n_types;
-    verts_sum += g->info.n_vertices;
   }
   // Larger graphs first: the longest queries start first and the tail is short.
   std::stable_sort(qs.begin(), qs.end(), [&](const QueryDev &a, const QueryDev &b) {
     return graphs[a.graph]->info.n_vertices > graphs[b.graph]->info.n_vertices;
   });
   Plan pl;
-  eat_status st = make_plan(ro, max_v, std::max<int64_t>(types_sum, 1), std::max<int64_t>(verts_sum, 1), dev, &pl);
+  eat_status st = make_plan(ro, max_v, dev, &pl);
   if (st != EAT_OK) return st;
 
   eat_batch *b = new (std::nothrow) eat_batch();
@@ -499,13 +475,7 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   a.graphs = d_g;
   a.queries = d_q;
   a.nq = n_q;
-  a.max_rounds = pl.max_rounds;
-  a.mode = pl.mode;
-  a.fcap = pl.fcap;
-  a.bm_words = pl.bm_words;
-  a.table_cap = pl.table_cap;
-  a.table_bits = pl.table_bits;
-  a.ns_per_tick = pl.ns_per_tick;
+  eat::apply_plan(pl, &a);
   a.work = d_c;
   a.stats = d_s;
   a.n_failed = d_c + 2;

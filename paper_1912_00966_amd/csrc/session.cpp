@@ -1,0 +1,384 @@
+// session.cpp -- serving sessions (continuous batching) of the C ABI.
+//
+// Slot memory: one device pool, carved first-fit into result slots (one
+// n_vertices int32 slab per admitted query), with coalescing on release.
+// Launches: each step copies the descriptors of the newly admitted queries from
+// pinned host memory to the device and launches the relaxation kernel over
+// them on one of n_streams streams; a step block (descriptors, statistics,
+// counters, event) is reused only after its previous launch has finished.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "device.hpp"
+#include "eat.h"
+#include "internal.hpp"
+
+using eat::GraphDev;
+using eat::QueryDev;
+using eat::RunArgs;
+using eat::hip_err;
+using eat::set_err;
+
+namespace {
+
+enum SlotState : int32_t { kFree = 0, kAdmitted = 1, kLaunched = 2, kDone = 3 };
+
+struct Slot {
+  int32_t state = kFree;
+  int32_t graph = 0, s = 0, ts = 0;
+  int64_t off = 0;    // words into the pool
+  int64_t words = 0;  // reserved words
+  eat_query_stats stats{};
+};
+
+struct StepBlock {
+  QueryDev *d_q = nullptr;
+  eat_query_stats *d_stats = nullptr;
+  int32_t *d_ctr = nullptr;
+  QueryDev *h_q = nullptr;              // pinned
+  eat_query_stats *h_stats = nullptr;   // pinned
+  hipEvent_t done = nullptr;
+  hipStream_t stream = nullptr;
+  std::vector<int32_t> slots;
+  bool in_flight = false;
+};
+
+constexpr int64_t kSlotAlignWords = 64;  // 256-byte aligned slabs
+
+}  // namespace
+
+struct eat_session {
+  int device = 0;
+  std::vector<const eat_graph *> graphs;
+  GraphDev *d_graphs = nullptr;
+  eat::Plan plan;
+  int grid_cap = 1;
+  int32_t max_step = 4096;
+  int32_t *d_pool = nullptr;
+  int64_t pool_words = 0;
+  std::map<int64_t, int64_t> free_ranges;  // offset -> length (words)
+  std::vector<Slot> slots;
+  std::vector<int32_t> free_ids;
+  std::deque<int32_t> admitted;
+  std::deque<int32_t> finished;
+  std::vector<StepBlock> blocks;
+  size_t next_block = 0;
+  std::deque<size_t> order;  // in-flight blocks, oldest first
+};
+
+namespace {
+
+void destroy(eat_session *S) {
+  if (!S) return;
+  (void)hipSetDevice(S->device);
+  (void)hipDeviceSynchronize();
+  for (auto &b : S->blocks) {
+    if (b.done) (void)hipEventDestroy(b.done);
+    if (b.stream) (void)hipStreamDestroy(b.stream);
+    if (b.h_q) (void)hipHostFree(b.h_q);
+    if (b.h_stats) (void)hipHostFree(b.h_stats);
+    if (b.d_q) (void)hipFree(b.d_q);
+  }
+  if (S->d_graphs) (void)hipFree(S->d_graphs);
+  if (S->d_pool) (void)hipFree(S->d_pool);
+  delete S;
+}
+
+// First-fit allocation of `words` from the pool; -1 if nothing fits.
+int64_t pool_take(eat_session *S, int64_t words) {
+  for (auto it = S->free_ranges.begin(); it != S->free_ranges.end(); ++it) {
+    if (it->second < words) continue;
+    const int64_t off = it->first, len = it->second;
+    S->free_ranges.erase(it);
+    if (len > words) S->free_ranges.emplace(off + words, len - words);
+    return off;
+  }
+  return -1;
+}
+
+void pool_give(eat_session *S, int64_t off, int64_t words) {
+  auto it = S->free_ranges.emplace(off, words).first;
+  auto next = std::next(it);
+  if (next != S->free_ranges.end() && it->first + it->second == next->first) {
+    it->second += next->second;
+    S->free_ranges.erase(next);
+  }
+  if (it != S->free_ranges.begin()) {
+    auto prev = std::prev(it);
+    if (prev->first + prev->second == it->first) {
+      prev->second += it->second;
+      S->free_ranges.erase(it);
+    }
+  }
+}
+
+// Marks the slots of a finished block done and takes their statistics.
+void retire(eat_session *S, StepBlock &b) {
+  for (size_t i = 0; i < b.slots.size(); ++i) {
+    Slot &sl = S->slots[(size_t)b.slots[i]];
+    sl.stats = b.h_stats[i];
+    sl.state = kDone;
+    S->finished.push_back(b.slots[i]);
+  }
+  b.slots.clear();
+  b.in_flight = false;
+}
+
+eat_status retire_ready(eat_session *S, bool wait_oldest) {
+  while (!S->order.empty()) {
+    StepBlock &b = S->blocks[S->order.front()];
+    hipError_t e = wait_oldest ? hipEventSynchronize(b.done) : hipEventQuery(b.done);
+    if (e == hipErrorNotReady) return EAT_OK;
+    if (e != hipSuccess) return hip_err(e, "step completion");
+    retire(S, b);
+    S->order.pop_front();
+    if (wait_oldest) return EAT_OK;
+  }
+  return EAT_OK;
+}
+
+}  // namespace
+
+extern "C" eat_status eat_session_create(const eat_graph *const *graphs, int32_t n_graphs,
+                                         const eat_session_options *opt, eat_session **out) {
+  if (!out) return set_err(EAT_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (!graphs || n_graphs < 1) return set_err(EAT_ERR_INVALID_ARGUMENT, "need at least one graph");
+  eat_session_options o{};
+  if (opt) o = *opt;
+  for (int r : o.reserved)
+    if (r != 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "reserved session options must be zero");
+  if (o.pool_bytes < 0 || o.n_streams < 0 || o.n_streams > 8 || o.max_step_queries < 0)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "invalid session options");
+  const int64_t pool_bytes = o.pool_bytes ? o.pool_bytes : (int64_t)256 << 20;
+  const int n_streams = o.n_streams ? o.n_streams : 2;
+  const int32_t max_step = o.max_step_queries ? o.max_step_queries : 4096;
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  int kind = -1;
+  int32_t max_v = 1;
+  for (int32_t i = 0; i < n_graphs; ++i) {
+    if (!graphs[i]) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph " + std::to_string(i) + " is NULL");
+    if (graphs[i]->device != dev) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph on another device");
+    if (kind < 0) kind = graphs[i]->info.layout;
+    if (graphs[i]->info.layout != kind)
+      return set_err(EAT_ERR_UNSUPPORTED, "all graphs of one session must share a layout kind");
+    max_v = std::max(max_v, graphs[i]->info.n_vertices);
+  }
+  eat::Plan pl;
+  eat_status st = eat::make_plan(&o.run, max_v, dev, &pl);
+  if (st != EAT_OK) return st;
+  eat::DeviceLimits lim;
+  st = eat::device_limits(dev, &lim);
+  if (st != EAT_OK) return st;
+
+  eat_session *S = new (std::nothrow) eat_session();
+  if (!S) return set_err(EAT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  S->device = dev;
+  S->graphs.assign(graphs, graphs + n_graphs);
+  S->plan = pl;
+  S->max_step = max_step;
+  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, kind, pl.lds));
+  S->grid_cap = lim.cus * per_cu;
+  S->pool_words = pool_bytes / 4 / kSlotAlignWords * kSlotAlignWords;
+  auto fail = [&](eat_status s2, const std::string &m) {
+    destroy(S);
+    return set_err(s2, m);
+  };
+  if (S->pool_words < kSlotAlignWords) return fail(EAT_ERR_INVALID_ARGUMENT, "pool_bytes too small");
+  if (hipMalloc(&S->d_pool, (size_t)S->pool_words * 4) != hipSuccess)
+    return fail(EAT_ERR_OUT_OF_MEMORY, "hipMalloc of the slot pool failed");
+  S->free_ranges.emplace(0, S->pool_words);
+  std::vector<GraphDev> gd((size_t)n_graphs);
+  for (int32_t i = 0; i < n_graphs; ++i) gd[(size_t)i] = graphs[i]->desc;
+  if (hipMalloc(&S->d_graphs, gd.size() * sizeof(GraphDev)) != hipSuccess ||
+      hipMemcpy(S->d_graphs, gd.data(), gd.size() * sizeof(GraphDev), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(EAT_ERR_OUT_OF_MEMORY, "graph descriptors");
+  S->blocks.resize((size_t)n_streams);
+  const size_t bq = eat::align_up((size_t)max_step * sizeof(QueryDev));
+  const size_t bs = eat::align_up((size_t)max_step * sizeof(eat_query_stats));
+  for (auto &b : S->blocks) {
+    void *p = nullptr;
+    if (hipMalloc(&p, bq + bs + 256) != hipSuccess) return fail(EAT_ERR_OUT_OF_MEMORY, "step block");
+    b.d_q = static_cast<QueryDev *>(p);
+    b.d_stats = reinterpret_cast<eat_query_stats *>(static_cast<char *>(p) + bq);
+    b.d_ctr = reinterpret_cast<int32_t *>(static_cast<char *>(p) + bq + bs);
+    if (hipMemset(b.d_ctr, 0, 256) != hipSuccess) return fail(EAT_ERR_DEVICE, "step counters");
+    if (hipHostMalloc((void **)&b.h_q, bq, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&b.h_stats, bs, hipHostMallocDefault) != hipSuccess)
+      return fail(EAT_ERR_OUT_OF_MEMORY, "pinned step staging");
+    if (hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
+      return fail(EAT_ERR_DEVICE, "stream or event creation");
+  }
+  *out = S;
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_session_admit(eat_session *S, int32_t graph, int32_t s, int32_t ts,
+                                        int32_t *slot) {
+  if (!S || !slot) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (graph < 0 || graph >= (int32_t)S->graphs.size()) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph index out of range");
+  const int32_t V = S->graphs[(size_t)graph]->info.n_vertices;
+  if (s < 0 || s >= V) return set_err(EAT_ERR_INVALID_ARGUMENT, "source out of range");
+  if (ts < 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "ts must be >= 0");
+  const int64_t words = ((int64_t)V + kSlotAlignWords - 1) / kSlotAlignWords * kSlotAlignWords;
+  const int64_t off = pool_take(S, words);
+  if (off < 0) return set_err(EAT_ERR_BUSY, "no free result slot of that size");
+  int32_t id;
+  if (!S->free_ids.empty()) {
+    id = S->free_ids.back();
+    S->free_ids.pop_back();
+  } else {
+    id = (int32_t)S->slots.size();
+    S->slots.emplace_back();
+  }
+  Slot &sl = S->slots[(size_t)id];
+  sl.state = kAdmitted;
+  sl.graph = graph;
+  sl.s = s;
+  sl.ts = ts;
+  sl.off = off;
+  sl.words = words;
+  std::memset(&sl.stats, 0, sizeof(sl.stats));
+  S->admitted.push_back(id);
+  *slot = id;
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_session_step(eat_session *S, int32_t *n_launched) {
+  if (!S) return set_err(EAT_ERR_INVALID_ARGUMENT, "session is NULL");
+  if (n_launched) *n_launched = 0;
+  if (S->admitted.empty()) return EAT_OK;
+  HIP_TRY(hipSetDevice(S->device));
+  // a free block: the next one in turn, else wait for the oldest launch
+  eat_status st = retire_ready(S, false);
+  if (st != EAT_OK) return st;
+  size_t bi = S->blocks.size();
+  for (size_t k = 0; k < S->blocks.size(); ++k) {
+    const size_t c = (S->next_block + k) % S->blocks.size();
+    if (!S->blocks[c].in_flight) {
+      bi = c;
+      break;
+    }
+  }
+  if (bi == S->blocks.size()) {  // every block busy: wait for the oldest launch
+    st = retire_ready(S, true);
+    if (st != EAT_OK) return st;
+    for (size_t k = 0; k < S->blocks.size() && bi == S->blocks.size(); ++k)
+      if (!S->blocks[k].in_flight) bi = k;
+    if (bi == S->blocks.size()) return set_err(EAT_ERR_DEVICE, "no step block became free");
+  }
+  S->next_block = (bi + 1) % S->blocks.size();
+  StepBlock &b = S->blocks[bi];
+  const int32_t n = (int32_t)std::min<size_t>(S->admitted.size(), (size_t)S->max_step);
+  b.slots.assign(S->admitted.begin(), S->admitted.begin() + n);
+  S->admitted.erase(S->admitted.begin(), S->admitted.begin() + n);
+  // larger graphs first (longest queries start first)
+  std::stable_sort(b.slots.begin(), b.slots.end(), [&](int32_t a, int32_t c) {
+    return S->graphs[(size_t)S->slots[(size_t)a].graph]->info.n_vertices >
+           S->graphs[(size_t)S->slots[(size_t)c].graph]->info.n_vertices;
+  });
+  for (int32_t i = 0; i < n; ++i) {
+    Slot &sl = S->slots[(size_t)b.slots[(size_t)i]];
+    sl.state = kLaunched;
+    b.h_q[i] = QueryDev{sl.graph, sl.s, sl.ts, i, S->d_pool + sl.off};
+  }
+  HIP_TRY(hipMemcpyAsync(b.d_q, b.h_q, sizeof(QueryDev) * (size_t)n, hipMemcpyHostToDevice, b.stream));
+  RunArgs a{};
+  a.graphs = S->d_graphs;
+  a.queries = b.d_q;
+  a.nq = n;
+  eat::apply_plan(S->plan, &a);
+  a.work = b.d_ctr;
+  a.stats = b.d_stats;
+  a.n_failed = b.d_ctr + 2;
+  const int grid = std::max(1, std::min(n, S->grid_cap));
+  hipError_t e = eat::launch_relax(a, S->plan.tpv, S->graphs[0]->info.layout, grid, S->plan.lds, b.stream);
+  if (e != hipSuccess) return hip_err(e, "relaxation launch");
+  HIP_TRY(hipMemcpyAsync(b.h_stats, b.d_stats, sizeof(eat_query_stats) * (size_t)n, hipMemcpyDeviceToHost,
+                         b.stream));
+  HIP_TRY(hipEventRecord(b.done, b.stream));
+  b.in_flight = true;
+  S->order.push_back(bi);
+  if (n_launched) *n_launched = n;
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_session_poll(eat_session *S, int32_t *done, int32_t cap, int32_t *n) {
+  if (!S || !n || cap < 0 || (cap > 0 && !done)) return set_err(EAT_ERR_INVALID_ARGUMENT, "bad argument");
+  *n = 0;
+  eat_status st = retire_ready(S, false);
+  if (st != EAT_OK) return st;
+  while (*n < cap && !S->finished.empty()) {
+    done[(*n)++] = S->finished.front();
+    S->finished.pop_front();
+  }
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_session_sync(eat_session *S) {
+  if (!S) return set_err(EAT_ERR_INVALID_ARGUMENT, "session is NULL");
+  while (!S->order.empty()) {
+    eat_status st = retire_ready(S, true);
+    if (st != EAT_OK) return st;
+  }
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_session_result(eat_session *S, int32_t slot, const int32_t **arr,
+                                         int32_t *n_vertices) {
+  if (!S || !arr) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (slot < 0 || slot >= (int32_t)S->slots.size() || S->slots[(size_t)slot].state != kDone)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "slot is not a finished query");
+  const Slot &sl = S->slots[(size_t)slot];
+  *arr = S->d_pool + sl.off;
+  if (n_vertices) *n_vertices = S->graphs[(size_t)sl.graph]->info.n_vertices;
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_session_copy(eat_session *S, int32_t slot, int32_t *dst, void *stream) {
+  const int32_t *src = nullptr;
+  int32_t n = 0;
+  eat_status st = eat_session_result(S, slot, &src, &n);
+  if (st != EAT_OK) return st;
+  if (!dst) return set_err(EAT_ERR_INVALID_ARGUMENT, "dst is NULL");
+  HIP_TRY(hipMemcpyAsync(dst, src, (size_t)n * 4, hipMemcpyDefault, static_cast<hipStream_t>(stream)));
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_session_query_stats(eat_session *S, int32_t slot, eat_query_stats *out) {
+  if (!S || !out) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL argument");
+  if (slot < 0 || slot >= (int32_t)S->slots.size() || S->slots[(size_t)slot].state != kDone)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "slot is not a finished query");
+  *out = S->slots[(size_t)slot].stats;
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_session_release(eat_session *S, int32_t slot) {
+  if (!S) return set_err(EAT_ERR_INVALID_ARGUMENT, "session is NULL");
+  if (slot < 0 || slot >= (int32_t)S->slots.size()) return set_err(EAT_ERR_INVALID_ARGUMENT, "slot out of range");
+  Slot &sl = S->slots[(size_t)slot];
+  if (sl.state == kAdmitted) {
+    auto it = std::find(S->admitted.begin(), S->admitted.end(), slot);
+    if (it != S->admitted.end()) S->admitted.erase(it);
+  } else if (sl.state != kDone) {
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "slot is not finished (or already free)");
+  }
+  // a finished slot may still be listed as finished if it was never polled
+  auto f = std::find(S->finished.begin(), S->finished.end(), slot);
+  if (f != S->finished.end()) S->finished.erase(f);
+  pool_give(S, sl.off, sl.words);
+  sl.state = kFree;
+  S->free_ids.push_back(slot);
+  return EAT_OK;
+}
+
+extern "C" void eat_session_free(eat_session *S) { destroy(S); }

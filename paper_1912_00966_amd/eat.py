@@ -39,7 +39,10 @@ EXPORTS = (
     "eat_graph_build", "eat_graph_upload", "eat_graph_free", "eat_graph_info",
     "eat_query", "eat_batch_create", "eat_batch_run", "eat_batch_wait", "eat_batch_free",
     "eat_query_batch", "eat_next_departure", "eat_status_string", "eat_last_error",
-    "eat_version",
+    "eat_version", "eat_session_create", "eat_session_admit", "eat_session_step",
+    "eat_session_poll", "eat_session_sync", "eat_session_result", "eat_session_copy",
+    "eat_session_query_stats",
+    "eat_session_release", "eat_session_free",
 )
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -93,6 +96,12 @@ class QueryStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class SessionOptions(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_int64), ("n_streams", ctypes.c_int32),
+                ("max_step_queries", ctypes.c_int32), ("run", RunOptions),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
 class EatError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{message} (status {status})")
@@ -141,10 +150,22 @@ def lib():
     L.eat_last_error.restype = ctypes.c_char_p
     L.eat_version.argtypes = []
     L.eat_version.restype = ctypes.c_int32
+    L.eat_session_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, ctypes.POINTER(SessionOptions),
+                                     ctypes.POINTER(_vp)]
+    L.eat_session_admit.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p]
+    L.eat_session_step.argtypes = [_vp, _i32p]
+    L.eat_session_poll.argtypes = [_vp, _i32p, ctypes.c_int32, _i32p]
+    L.eat_session_sync.argtypes = [_vp]
+    L.eat_session_result.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(_i32p), _i32p]
+    L.eat_session_copy.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
+    L.eat_session_query_stats.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(QueryStats)]
+    L.eat_session_release.argtypes = [_vp, ctypes.c_int32]
+    L.eat_session_free.argtypes = [_vp]
+    L.eat_session_free.restype = None
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("eat_layout_free", "eat_graph_free", "eat_batch_free", "eat_status_string",
-                        "eat_last_error", "eat_version"):
+                        "eat_last_error", "eat_version", "eat_session_free"):
             f.restype = ctypes.c_int
     _lib = L
     return L
@@ -393,6 +414,83 @@ def eat_next_departure(g: Graph, type_ids, x, out, stream=None):
     n = int(type_ids.numel())
     _check(lib().eat_next_departure(g.handle, _dev_ptr(type_ids, n, "type_ids"), _dev_ptr(x, n, "x"),
                                     _dev_ptr(out, n, "out"), n, _stream_handle(stream)))
+
+
+class Session:
+    """A serving session (eat_session_*): continuous batching over resident graphs."""
+
+    def __init__(self, graphs: Sequence[Graph], pool_bytes: int = 0, n_streams: int = 0,
+                 max_step_queries: int = 0, options=None):
+        self.graphs = list(graphs)
+        o = SessionOptions()
+        o.pool_bytes = int(pool_bytes)
+        o.n_streams = int(n_streams)
+        o.max_step_queries = int(max_step_queries)
+        ro = _run_opts(options)
+        if ro is not None:
+            o.run = ro
+        gh = (_vp * len(self.graphs))(*[g.handle for g in self.graphs])
+        h = _vp()
+        _check(lib().eat_session_create(gh, len(self.graphs), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._done = (ctypes.c_int32 * 65536)()
+
+    def admit(self, graph: int, s: int, ts: int):
+        """Slot id, or None when the pool has no room (EAT_ERR_BUSY)."""
+        slot = ctypes.c_int32()
+        st = lib().eat_session_admit(self._h, int(graph), int(s), int(ts), ctypes.byref(slot))
+        if st == EAT_ERR_BUSY:
+            return None
+        _check(st)
+        return int(slot.value)
+
+    def step(self) -> int:
+        n = ctypes.c_int32()
+        _check(lib().eat_session_step(self._h, ctypes.byref(n)))
+        return int(n.value)
+
+    def poll(self):
+        n = ctypes.c_int32()
+        _check(lib().eat_session_poll(self._h, self._done, len(self._done), ctypes.byref(n)))
+        return [int(self._done[i]) for i in range(n.value)]
+
+    def sync(self):
+        _check(lib().eat_session_sync(self._h))
+
+    def result_ptr(self, slot: int):
+        p = _i32p()
+        n = ctypes.c_int32()
+        _check(lib().eat_session_result(self._h, int(slot), ctypes.byref(p), ctypes.byref(n)))
+        return ctypes.cast(p, ctypes.c_void_p).value, int(n.value)
+
+    def result(self, slot: int, out=None, stream=None):
+        """A finished slot's arrival array, copied into `out` (a new CUDA int32
+        tensor if None) on `stream`."""
+        import torch
+        _, n = self.result_ptr(slot)
+        if out is None:
+            out = torch.empty(n, dtype=torch.int32, device="cuda")
+        _check(lib().eat_session_copy(self._h, int(slot), _dev_ptr(out, n, "out"), _stream_handle(stream)))
+        return out
+
+    def stats(self, slot: int) -> dict:
+        st = QueryStats()
+        _check(lib().eat_session_query_stats(self._h, int(slot), ctypes.byref(st)))
+        return st.as_dict()
+
+    def release(self, slot: int):
+        _check(lib().eat_session_release(self._h, int(slot)))
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().eat_session_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def eat_version() -> int:
