@@ -273,9 +273,10 @@ extern "C" eat_status eat_graph_info(const eat_graph *g, eat_graph_info_t *out) 
 // ---------------------------------------------------------------------------
 namespace eat {
 
-// LDS bytes: two frontier lists + three scratch arrays of the load-balanced
-// expansion (fcap entries each), plus the arrival table or the stop bitmap.
-static size_t lists_lds(int fcap) { return (size_t)fcap * 20; }
+// LDS bytes: two frontier lists of (item, type begin, type count) and the
+// prefix sums of the load-balanced expansion (fcap entries each), plus the
+// arrival table or the stop bitmap.
+static size_t lists_lds(int fcap) { return (size_t)fcap * 28; }
 static size_t table_lds(int H, int fcap) { return (size_t)H * 8 + (size_t)(H / 32) * 4 + lists_lds(fcap); }
 
 eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan *pl) {

@@ -223,21 +223,34 @@ __device__ __forceinline__ int32_t next_departure(const GraphDev &G, const int4 
 }
 
 // ---------------------------------------------------------------------------
-// Frontier push: wave64 ballot, one LDS atomic per wave, lane offsets by
-// masked population count.
+// Frontier lists.  An entry names an item (a table slot or a stop) and the
+// item's stop's range of connection types, loaded by the lane that pushed it
+// (cnt < 0: not known yet, the expansion loads it).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void push(bool want, int32_t item, int32_t *nxt, int32_t fcap, bool append,
-                                     int32_t *sh_nn) {
+struct FList {
+  int32_t *item;
+  int32_t *beg;
+  int32_t *cnt;
+};
+
+// Push: wave64 ballot, one LDS atomic per wave, lane offsets by masked
+// population count.
+__device__ __forceinline__ void push(bool want, int32_t item, int32_t beg, int32_t cnt, const FList &nxt,
+                                     int32_t fcap, bool append, int32_t *nn) {
   const uint64_t m = __ballot(want);
   if (m == 0) return;
   const int lane = __lane_id();
   const int leader = __ffsll((unsigned long long)m) - 1;
   int32_t base = 0;
-  if (lane == leader) base = atomicAdd(sh_nn, (int32_t)__popcll(m));
+  if (lane == leader) base = atomicAdd(nn, (int32_t)__popcll(m));
   base = __shfl(base, leader);
   if (want && append) {
     const int32_t slot = base + (int32_t)__popcll(m & ((1ull << lane) - 1ull));
-    if (slot < fcap) nxt[slot] = item;
+    if (slot < fcap) {
+      nxt.item[slot] = item;
+      nxt.beg[slot] = beg;
+      nxt.cnt[slot] = cnt;
+    }
   }
 }
 
@@ -247,7 +260,9 @@ __device__ __forceinline__ int32_t lds_ld(const int32_t *p) {
 
 // ---------------------------------------------------------------------------
 // Where a query keeps its arrival times.  An "item" names one stop's entry;
-// `bits` holds one activity bit per item.
+// `bits` holds one activity bit per item: set when the item's arrival
+// improves (and it is pushed), cleared when the item is taken for expansion
+// (the active / nextactive flags of Section III-B).
 // ---------------------------------------------------------------------------
 
 // In the caller's result slab (HBM); item = stop id.
@@ -310,16 +325,31 @@ struct TableStore {
   __device__ __forceinline__ int32_t lower(int32_t item, int32_t cand) const { return atomicMin(vals + item, cand); }
 };
 
+// After a successful atomic minimum on item (stop v): set the item's bit; the
+// lane that sets it pushes the item with v's type range, whose load is issued
+// here so that it overlaps the push.
+template <class Store>
+__device__ __forceinline__ bool mark_improved(const GraphDev &G, const Store &S, int32_t it, int32_t v,
+                                              int32_t &beg, int32_t &cnt) {
+  const uint32_t bit = 1u << (it & 31);
+  const bool first = !(atomicOr(&S.bits[it >> 5], bit) & bit);
+  if (first) {
+    beg = G.vt_off[v];
+    cnt = G.vt_off[v + 1] - beg;
+  }
+  return first;
+}
+
 // Relax (Algorithm 3) the best connection of type j for a tail reached at x.
 template <int KIND, class Store>
 __device__ __forceinline__ void relax(const GraphDev &G, const Store &S, int64_t j, int32_t x,
-                                      int32_t *nxt, int32_t fcap, bool append, int32_t *sh_nn, Ctr &c) {
+                                      const FList &nxt, int32_t fcap, bool append, int32_t *nn, Ctr &c) {
   const int4 r = G.ty[j];
   const int32_t v = r.x, lam = r.y;
   c.tev++;
   const int32_t av = S.find(v);
   bool want = false;
-  int32_t item = 0;
+  int32_t item = 0, beg = 0, cnt = 0;
   // Any departure of this type leaves at t_c >= x, so it arrives at >= x + lam:
   // skip the lookup when that cannot beat arr[v] (early termination, Section
   // III-D, in its strongest exact form).
@@ -333,56 +363,13 @@ __device__ __forceinline__ void relax(const GraphDev &G, const Store &S, int64_t
           const int32_t old = S.lower(item, cand);
           if (cand < old) {
             c.imp++;
-            const uint32_t bit = 1u << (item & 31);
-            want = !(atomicOr(&S.bits[item >> 5], bit) & bit);
+            want = mark_improved(G, S, item, v, beg, cnt);
           }
         }
       }
     }
   }
-  push(want, item, nxt, fcap, append, sh_nn);
-}
-
-struct Shared {
-  int32_t q, nn, cnt, count, over, reached;
-  int32_t wsum[kBlock / 64];
-  unsigned long long acc[5];
-};
-
-// Scratch arrays of the load-balanced expansion (fcap entries each).
-struct Prep {
-  int32_t *beg;  // first type of the entry's stop
-  int32_t *x;    // the stop's arrival time
-  int32_t *off;  // exclusive prefix sum of the entries' type counts
-};
-
-// Exclusive prefix sum of v over the work-group; *total receives the sum.
-// Every thread must call it; it ends with a barrier.
-__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, Shared &sh, int32_t *total) {
-  constexpr int kWaves = kBlock / 64;
-  const int lane = __lane_id(), w = threadIdx.x >> 6;
-  int32_t s = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int32_t o = __shfl_up(s, d);
-    if (lane >= d) s += o;
-  }
-  if (lane == 63) sh.wsum[w] = s;
-  __syncthreads();
-  if (w == 0) {
-    int32_t t = lane < kWaves ? sh.wsum[lane] : 0;
-#pragma unroll
-    for (int d = 1; d < kWaves; d <<= 1) {
-      const int32_t o = __shfl_up(t, d);
-      if (lane >= d) t += o;
-    }
-    if (lane < kWaves) sh.wsum[lane] = t;
-  }
-  __syncthreads();
-  const int32_t base = w ? sh.wsum[w - 1] : 0;
-  *total = sh.wsum[kWaves - 1];
-  __syncthreads();  // wsum may be reused by the next call
-  return base + s - v;
+  push(want, item, beg, cnt, nxt, fcap, append, nn);
 }
 
 // Relax U connection types per lane with their memory reads overlapped: all
@@ -390,8 +377,8 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, Shared &sh, i
 // arrival lookups, then the rare array chunks, then the updates.
 template <int KIND, int U, class Store>
 __device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, const int64_t *j,
-                                            const int32_t *x, const bool *ok, int32_t *nxt, int32_t fcap,
-                                            bool append, int32_t *sh_nn, Ctr &c) {
+                                            const int32_t *x, const bool *ok, const FList &nxt, int32_t fcap,
+                                            bool append, int32_t *nn, Ctr &c) {
   int4 r[U];
   uint32_t mhi[U];
 #pragma unroll
@@ -422,11 +409,11 @@ __device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, c
     }
   }
   bool want[U];
-  int32_t item[U];
+  int32_t item[U], beg[U], cnt[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     want[u] = false;
-    item[u] = 0;
+    item[u] = beg[u] = cnt[u] = 0;
     if (live[u]) {
       const int32_t tc = look_finish<KIND>(G, r[u], x[u], L[u], c);
       if (tc != INF) {
@@ -437,8 +424,7 @@ __device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, c
             const int32_t old = S.lower(it, cand);
             if (cand < old) {
               c.imp++;
-              const uint32_t bit = 1u << (it & 31);
-              want[u] = !(atomicOr(&S.bits[it >> 5], bit) & bit);
+              want[u] = mark_improved(G, S, it, r[u].x, beg[u], cnt[u]);
               item[u] = it;
             }
           }
@@ -447,39 +433,79 @@ __device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, c
     }
   }
 #pragma unroll
-  for (int u = 0; u < U; ++u) push(want[u], item[u], nxt, fcap, append, sh_nn);
+  for (int u = 0; u < U; ++u) push(want[u], item[u], beg[u], cnt[u], nxt, fcap, append, nn);
 }
 
-// Expand every item of list[0..n).
+struct Shared {
+  int32_t q, cnt, count, over, reached;
+  int32_t nn[3];                // pushes of round r go to nn[r % 3]
+  int32_t wsum[2][kBlock / 64]; // wave totals of the prefix sum, alternating per call
+  unsigned long long acc[5];
+};
+
+// Exclusive prefix sum of v over the work-group; *total receives the sum.
+// Every thread must call it (one barrier).  The wave totals alternate between
+// two buffers, so consecutive calls need no barrier between them.
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, Shared &sh, int32_t call, int32_t *total) {
+  constexpr int kWaves = kBlock / 64;
+  const int lane = __lane_id(), w = threadIdx.x >> 6;
+  int32_t *ws = sh.wsum[call & 1];
+  int32_t s = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int32_t o = __shfl_up(s, d);
+    if (lane >= d) s += o;
+  }
+  if (lane == 63) ws[w] = s;
+  __syncthreads();
+  int32_t base = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) {
+    const int32_t t = ws[k];
+    base += k < w ? t : 0;
+    tot += t;
+  }
+  *total = tot;
+  return base + s - v;
+}
+
+// Expand every entry of list[0..n).  The entries' bits are cleared as they are
+// taken (with `clear`; a sweep has claimed them already) before their arrival
+// times are read, so an improvement that lands later pushes them again.
 // TPV == 0: load-balanced -- the connection types of all listed stops form one
 //   index space (prefix sum of their type counts) and lane k relaxes types
-//   k, k + kBlock, ...; a lane finds its stop by bisection of the prefix sums.
+//   k, k + kBlock, ..., two at a time; a lane finds its stop by bisection of
+//   the prefix sums.
 // TPV > 0: virtual warps (Section IV-B) -- groups of TPV lanes, one stop per
 //   group, lane i of a group takes the stop's types i, i + TPV, ...
 template <int TPV, int KIND, class Store>
-__device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, const int32_t *list,
-                                            int32_t n, int32_t *nxt, int32_t fcap, bool append,
-                                            Shared &sh, const Prep &P, Ctr &c) {
+__device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, const FList &cur, int32_t n,
+                                            bool clear, const FList &nxt, int32_t fcap, bool append,
+                                            int32_t *nn, Shared &sh, int32_t *poff, int32_t &scan_call,
+                                            Ctr &c) {
   if constexpr (TPV == 0) {
     int32_t carry = 0;
     for (int32_t e0 = 0; e0 < n; e0 += kBlock) {
       const int32_t e = e0 + (int32_t)threadIdx.x;
       int32_t d = 0;
       if (e < n) {
-        const int32_t item = list[e];
-        const int32_t u = S.stop(item);
-        const int32_t b = G.vt_off[u];
-        d = G.vt_off[u + 1] - b;
-        P.beg[e] = b;
-        P.x[e] = S.value(item);
+        const int32_t item = cur.item[e];
+        if (clear) atomicAnd(&S.bits[item >> 5], ~(1u << (item & 31)));
+        d = cur.cnt[e];
+        if (d < 0) {  // staged by a sweep: load the stop's type range
+          const int32_t u = S.stop(item);
+          const int32_t b = G.vt_off[u];
+          d = G.vt_off[u + 1] - b;
+          cur.beg[e] = b;
+        }
         c.act++;
       }
       int32_t tot;
-      const int32_t off = block_exclusive_scan(d, sh, &tot);
-      if (e < n) P.off[e] = carry + off;
+      const int32_t off = block_exclusive_scan(d, sh, scan_call++, &tot);
+      if (e < n) poff[e] = carry + off;
       carry += tot;
     }
-    __syncthreads();
+    __syncthreads();  // offsets and type ranges visible to every lane
     const int32_t total = carry;
     constexpr int U = 2;
     for (int32_t k0 = threadIdx.x; k0 < total; k0 += kBlock * U) {
@@ -493,26 +519,37 @@ __device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, c
         int32_t lo = 0, hi = ok[u] ? n : 0;  // first entry whose offset exceeds k
         while (lo < hi) {
           const int32_t mid = (lo + hi) >> 1;
-          if (P.off[mid] <= k) lo = mid + 1; else hi = mid;
+          if (poff[mid] <= k) lo = mid + 1; else hi = mid;
         }
         const int32_t i = ok[u] ? lo - 1 : 0;
-        jj[u] = ok[u] ? (int64_t)P.beg[i] + (k - P.off[i]) : 0;
-        xx[u] = ok[u] ? P.x[i] : 0;
+        jj[u] = ok[u] ? (int64_t)cur.beg[i] + (k - poff[i]) : 0;
+        xx[u] = ok[u] ? S.value(cur.item[i]) : 0;
       }
-      relax_batch<KIND, U>(G, S, jj, xx, ok, nxt, fcap, append, &sh.nn, c);
+      relax_batch<KIND, U>(G, S, jj, xx, ok, nxt, fcap, append, nn, c);
     }
   } else {
     constexpr int kGroups = kBlock / TPV;
     const int g = threadIdx.x / TPV, lane = threadIdx.x % TPV;
+    // take the entries (clear bits, load unknown type ranges) before any push
+    for (int32_t e = threadIdx.x; e < n; e += kBlock) {
+      const int32_t item = cur.item[e];
+      if (clear) atomicAnd(&S.bits[item >> 5], ~(1u << (item & 31)));
+      if (cur.cnt[e] < 0) {
+        const int32_t u = S.stop(item);
+        const int32_t b = G.vt_off[u];
+        cur.beg[e] = b;
+        cur.cnt[e] = G.vt_off[u + 1] - b;
+      }
+    }
+    __syncthreads();
     for (int32_t base = 0; base < n; base += kGroups) {
       const int32_t i = base + g;
       if (i < n) {
-        const int32_t item = list[i];
-        const int32_t u = S.stop(item);
+        const int32_t item = cur.item[i];
         const int32_t x = S.value(item);
-        const int32_t b = G.vt_off[u], e = G.vt_off[u + 1];
+        const int32_t b = cur.beg[i], e = b + cur.cnt[i];
         if (lane == 0) c.act++;
-        for (int32_t j = b + lane; j < e; j += TPV) relax<KIND>(G, S, j, x, nxt, fcap, append, &sh.nn, c);
+        for (int32_t j = b + lane; j < e; j += TPV) relax<KIND>(G, S, j, x, nxt, fcap, append, nn, c);
       }
     }
   }
@@ -524,28 +561,34 @@ struct QState {
 
 // Relaxation rounds until no arrival improves (the iteration of Algorithms 4
 // and 5, with the activity flags of Section III-B).  On entry the first item
-// is in list0[0] (frontier mode) or has its bit set (topology mode), and every
-// other bit is clear.  Returns false if the store overflowed.
+// is list0 entry 0 with its bit set (frontier mode), or only its bit is set
+// (topology mode); every other bit is clear.  Returns false if the store
+// overflowed.
 template <int TPV, int KIND, class Store>
 __device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, int32_t n_items,
-                           int32_t *list0, int32_t *list1, const Prep &P, bool topo, int32_t max_rounds,
-                           Shared &sh, QState &qs, Ctr &c) {
+                           const FList &list0, const FList &list1, int32_t *poff, bool topo,
+                           int32_t max_rounds, Shared &sh, QState &qs, Ctr &c) {
   const int tid = threadIdx.x;
   const int32_t nwords = (n_items + 31) >> 5;
   const int32_t chunk_words = a.fcap >> 5;  // a sweep stages at most fcap items at a time
-  int32_t *cur = list0, *nxt = list1;
+  FList cur = list0, nxt = list1;
   int32_t nf = topo ? 0 : 1;
   bool sweep = topo;
   int32_t rounds = 0;
+  int32_t scan_call = 0;
+  if (tid < 3) sh.nn[tid] = 0;
+  __syncthreads();
   for (;;) {
     if (rounds >= max_rounds) {
       qs.status = EAT_ERR_NOT_CONVERGED;
       break;
     }
-    if (tid == 0) sh.nn = 0;
-    __syncthreads();
+    int32_t *nn = &sh.nn[rounds % 3];
+    // nn[(rounds + 1) % 3] was last read at the end of round rounds - 2, before
+    // the barrier that ended round rounds - 1: safe to reset for the next round
+    if (tid == 0) sh.nn[(rounds + 1) % 3] = 0;
     if (!sweep) {
-      expand_list<TPV, KIND>(G, S, cur, nf, nxt, a.fcap, !topo, sh, P, c);
+      expand_list<TPV, KIND>(G, S, cur, nf, true, nxt, a.fcap, !topo, nn, sh, poff, scan_call, c);
     } else {
       ++qs.sweeps;
       for (int32_t w0 = 0; w0 < nwords; w0 += chunk_words) {
@@ -560,40 +603,33 @@ __device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, 
             while (bits) {
               const int b = __ffs(bits) - 1;
               bits &= bits - 1u;
-              cur[pos++] = (w << 5) + b;
+              cur.item[pos] = (w << 5) + b;
+              cur.cnt[pos] = -1;
+              ++pos;
             }
           }
         }
         __syncthreads();
         const int32_t cnt = sh.cnt;
-        if (cnt) expand_list<TPV, KIND>(G, S, cur, cnt, nxt, a.fcap, !topo, sh, P, c);
+        if (cnt) expand_list<TPV, KIND>(G, S, cur, cnt, false, nxt, a.fcap, !topo, nn, sh, poff, scan_call, c);
         __syncthreads();
       }
     }
-    __syncthreads();
+    __syncthreads();  // all pushes of the round are in
     if (sh.over) {
       qs.rounds += rounds + 1;
       return false;
     }
-    const int32_t nn = sh.nn;
+    const int32_t nnv = *nn;
     ++rounds;
-    if (nn == 0) break;
-    qs.maxf = max(qs.maxf, nn);
-    const bool next_sweep = topo || nn > a.fcap;
-    if (!next_sweep) {
-      // the pushed items become the current list: clear their bits so that the
-      // next round's pushes are de-duplicated afresh
-      for (int32_t i = tid; i < nn; i += kBlock) {
-        const int32_t it = nxt[i];
-        atomicAnd(&S.bits[it >> 5], ~(1u << (it & 31)));
-      }
-    }
-    int32_t *tmp = cur;
+    if (nnv == 0) break;
+    qs.maxf = max(qs.maxf, nnv);
+    const bool next_sweep = topo || nnv > a.fcap;  // an overflowed list: its bits still name every item
+    FList tmp = cur;
     cur = nxt;
     nxt = tmp;
-    nf = next_sweep ? 0 : nn;
+    nf = next_sweep ? 0 : nnv;
     sweep = next_sweep;
-    __syncthreads();
   }
   qs.rounds += rounds;
   return true;
@@ -607,6 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
   const int tid = threadIdx.x;
   const bool batch = a.queries != nullptr;
   const bool topo = a.mode == EAT_MODE_TOPOLOGY;
+  const int32_t F = a.fcap;
 
   for (int iter = 0;; ++iter) {
     if (tid == 0)
@@ -658,6 +695,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
     bool done = false;
     if (a.table_cap > 0) {
       // ---- arrivals in the on-chip table ----------------------------------------
+      // LDS: keys[H] vals[H] bits[H/32] | two lists (item, beg, cnt) x F | offsets[F]
       const int32_t H = a.table_cap;
       TableStore T;
       T.keys = reinterpret_cast<int32_t *>(lds);
@@ -668,9 +706,9 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       T.mask = (uint32_t)H - 1u;
       T.shift = 32 - a.table_bits;
       T.limit = H - H / 4;
-      int32_t *l0 = reinterpret_cast<int32_t *>(T.bits + (H >> 5));
-      int32_t *l1 = l0 + a.fcap;
-      const Prep P{l1 + a.fcap, l1 + 2 * a.fcap, l1 + 3 * a.fcap};
+      int32_t *l = reinterpret_cast<int32_t *>(T.bits + (H >> 5));
+      const FList l0{l, l + F, l + 2 * F}, l1{l + 3 * F, l + 4 * F, l + 5 * F};
+      int32_t *poff = l + 6 * F;
       for (int32_t i = tid; i < H; i += kBlock) {
         T.keys[i] = EMPTY;
         T.vals[i] = INF;
@@ -680,11 +718,12 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       if (tid == 0) {
         const int32_t p = T.slot(Q.s);  // empty table: always succeeds
         T.vals[p] = Q.ts;
-        if (topo) T.bits[p >> 5] = 1u << (p & 31);
-        else l0[0] = p;
+        T.bits[p >> 5] = 1u << (p & 31);
+        l0.item[0] = p;
+        l0.cnt[0] = -1;
       }
       __syncthreads();
-      if (run_rounds<TPV, KIND>(a, G, T, H, l0, l1, P, topo, max_rounds, sh, qs, c)) {
+      if (run_rounds<TPV, KIND>(a, G, T, H, l0, l1, poff, topo, max_rounds, sh, qs, c)) {
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the infinity fill has landed
         __syncthreads();
         for (int32_t p = tid; p < H; p += kBlock) {
@@ -697,33 +736,33 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
     }
     if (!done) {
       // ---- arrivals in the result slab (no table, or the table overflowed) ----------
-      const bool spilled = a.table_cap > 0;  // the on-chip attempt overflowed
+      // LDS: bits[ceil(V/32)] | two lists | offsets.  An overflowed table attempt
+      // never wrote the slab: it still holds infinity.
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
       SlabStore S;
       S.arr = arr;
       S.bits = lds;
       const int32_t VW = (V + 31) >> 5;
-      int32_t *l0 = reinterpret_cast<int32_t *>(lds + VW);
-      int32_t *l1 = l0 + a.fcap;
-      const Prep P{l1 + a.fcap, l1 + 2 * a.fcap, l1 + 3 * a.fcap};
-      // (an overflowed table attempt never wrote the slab: it still holds infinity)
+      int32_t *l = reinterpret_cast<int32_t *>(lds + VW);
+      const FList l0{l, l + F, l + 2 * F}, l1{l + 3 * F, l + 4 * F, l + 5 * F};
+      int32_t *poff = l + 6 * F;
       for (int32_t i = tid; i < VW; i += kBlock) S.bits[i] = 0u;
       if (tid == 0) sh.over = 0;
       __syncthreads();
       if (tid == 0) {
         st_arr(arr + Q.s, Q.ts);
-        if (topo) S.bits[Q.s >> 5] = 1u << (Q.s & 31);
-        else l0[0] = Q.s;
+        S.bits[Q.s >> 5] = 1u << (Q.s & 31);
+        l0.item[0] = Q.s;
+        l0.cnt[0] = -1;
       }
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
-      run_rounds<TPV, KIND>(a, G, S, V, l0, l1, P, topo, max_rounds, sh, qs, c);
+      run_rounds<TPV, KIND>(a, G, S, V, l0, l1, poff, topo, max_rounds, sh, qs, c);
       // reached stops
       int32_t mine = 0;
       for (int32_t i = tid; i < V; i += kBlock) mine += ld_arr(arr + i) != INF;
       if (mine) atomicAdd(&sh.reached, mine);
-      (void)spilled;
     }
 
     // ---- per-query statistics --------------------------------------------------
