@@ -27,22 +27,46 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-def algorithmic_bytes(stats, n_vertices):
-    """Bytes the relaxation must move per query, from its operation counts.
+def algorithmic_bytes(stats, n_vertices, slab_only=False):
+    """HBM bytes the relaxation must move per launch, from its operation counts.
 
-    per query      : 4 * V (result slab written with infinity) + 4 (source)
-    per activation : 4 (arr[u]) + 8 (vt_off[u], vt_off[u+1])
-    per type eval  : 16 (type record) + 4 (arr[v])
-    per header     : 8 (cluster header)
-    per pool word  : 4
-    per improvement: 8 (atomic minimum: read + write of arr[v])
+    per query      : 4 * V (result slab written with infinity) + 4 * reached
+                     (final arrival times scattered from the on-chip table)
+    per activation : 8 (the stop's type range, vt_off[u] and vt_off[u+1])
+    per type eval  : 16 (type record)
+    per header     : 8 (cluster header; a second one only when the next
+                     cluster is needed)
+    per pool word  : 4 (array-cluster chunks, flat departures)
+    A query whose arrivals live in the slab (table overflow, or no table) also
+    moves 4 (arr[u]) per activation, 4 (arr[v]) per type eval and 8 (atomic
+    minimum) per improvement.
     """
     total = 0
     for st in stats:
-        total += 4 * n_vertices + 4
-        total += 12 * st["activations"] + 20 * st["type_evals"] + 8 * st["header_loads"]
-        total += 4 * st["pool_loads"] + 8 * st["improvements"]
+        total += 4 * n_vertices + 8 * st["activations"] + 16 * st["type_evals"]
+        total += 8 * st["header_loads"] + 4 * st["pool_loads"]
+        if slab_only or st["spilled"]:
+            total += 4 * st["activations"] + 4 * st["type_evals"] + 8 * st["improvements"]
+        else:
+            total += 4 * st["reached"]
     return total
+
+
+def profiled_traffic(path, kernel_source):
+    """Bytes per launch measured by the rocprofv3 counter runs recorded in
+    `path`, or None when the kernel source changed since they were taken."""
+    import hashlib
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "kernel_source_sha256")):
+            k, v = line.split(":", 1)
+            fields[k.strip().strip("`- ")] = v.strip().strip("` ")
+    digest = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != digest or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def main():
@@ -59,6 +83,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-query comparison")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="serving mode: Poisson arrivals over resident 10k/50k/500k-stop cities, "
+                         "p50/p99 latency and sustained queries/s per rate (prints its own JSON line)")
+    ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000")
+    ap.add_argument("--requests", type=int, default=20000, help="requests per rate (serving mode)")
+    ap.add_argument("--serve-sizes", default="10000,50000,500000")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, run one device-to-device copy of MIB MiB "
                          "(a kernel of known traffic, to scale profiler byte counters)")
@@ -78,6 +108,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log = lambda m: print(m, file=sys.stderr, flush=True)
+    if args.serve:
+        return run_serving(args, log)
 
     t0 = time.time()
     tt, q = synth.workload(args.workload, reading=args.reading)
@@ -151,10 +183,14 @@ def main():
             plain["bit_exact"] = bool(np.array_equal(slab.cpu().numpy(), exp))
 
     # ---- roofline of the relaxation kernel ---------------------------------------------
-    bytes_per_launch = algorithmic_bytes(stats, V)
+    bytes_per_launch = algorithmic_bytes(stats, V, slab_only=args.table == -1)
     achieved = bytes_per_launch / (kernel_ms / 1e3) / 1e9
+    traffic = None
+    if args.workload == "city-50k" and args.layout == "hybrid" and args.table == 0:
+        traffic = profiled_traffic(os.path.join(ROOT, "profiles", "k_relax_city-50k.md"),
+                                   os.path.join(ROOT, "paper_1912_00966_amd", "csrc", "kernels.hip"))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_relax", "kernel_ms": round(kernel_ms, 4),
                 "algorithmic_bytes_per_launch": int(bytes_per_launch)}
 
@@ -171,7 +207,10 @@ def main():
                          f"({os.cpu_count()} host cores visible)"}
 
     per_q = {k: float(np.mean([s[k] for s in stats])) for k in
-             ("rounds", "activations", "type_evals", "header_loads", "pool_loads", "improvements")}
+             ("rounds", "activations", "type_evals", "header_loads", "pool_loads", "improvements",
+              "reached", "spilled")}
+    per_q["elapsed_us_p50"] = float(np.median([s["elapsed_ns"] for s in stats]) / 1e3)
+    per_q["elapsed_us_max"] = float(np.max([s["elapsed_ns"] for s in stats]) / 1e3)
     out = {
         "metric": "EAT queries/sec & relax-kernel HBM GB/s (% peak), batched vs plain, bit-exact",
         "value": round(value, 1),
@@ -195,6 +234,57 @@ def main():
         "per_query_mean": per_q,
         "preprocess_s": round(prep_s, 3),
     }
+    print(json.dumps(out), flush=True)
+
+
+def run_serving(args, log):
+    """Open-loop serving benchmark: continuous batching over resident graphs."""
+    import torch
+
+    import oracle
+    from paper_1912_00966_amd import eat, serve, synth
+
+    sizes = [int(x) for x in args.serve_sizes.split(",")]
+    tts, graphs = [], []
+    for i, n in enumerate(sizes):
+        t0 = time.time()
+        tt = synth.scaled_city(n, seed=501 + i)
+        g = eat.graph_from_timetable(tt)
+        log(f"[serve] graph {i}: {tt.name} V={tt.n_vertices} C={tt.n_conn} built in {time.time() - t0:.1f}s")
+        tts.append(tt)
+        graphs.append(g)
+    sess = eat.Session(graphs, pool_bytes=1 << 30, n_streams=2)
+    out = {"metric": "served EAT queries/s and latency (Poisson arrivals)", "unit": "queries/s",
+           "graphs": [{"stops": t.n_vertices, "connections": t.n_conn} for t in tts], "rates": []}
+    csa = {}
+    for rate in [float(r) for r in args.rates.split(",")]:
+        reqs = serve.poisson_requests(rate, args.requests, [g.n_vertices for g in graphs], seed=599)
+        check_ids = set(range(0, len(reqs), max(1, len(reqs) // 32)))
+        kept = {}
+
+        def on_done(r, slot):
+            if r.id in check_ids:
+                kept[r.id] = sess.result(slot).cpu().numpy()
+
+        rep = serve.serve(sess, reqs, on_done=on_done, min_batch=64, max_delay_s=50e-6)
+        # spot checks: served == alone on the GPU; a few also against the oracle
+        ok_alone = all(np.array_equal(kept[i], graphs[reqs[i].graph].query(reqs[i].s, reqs[i].ts).cpu().numpy())
+                       for i in kept)
+        n_oracle = 0
+        ok_oracle = True
+        for i in sorted(kept)[:4]:
+            r = reqs[i]
+            if r.graph not in csa:
+                t = tts[r.graph]
+                csa[r.graph] = oracle.Csa(t.u, t.v, t.t, t.lam, t.n_vertices)
+            ok_oracle &= bool(np.array_equal(kept[i], csa[r.graph].query(r.s, r.ts)))
+            n_oracle += 1
+        row = {"offered_qps": rate, **rep.as_dict(), "checked_vs_alone": len(kept),
+               "bit_exact_vs_alone": bool(ok_alone), "checked_vs_oracle": n_oracle,
+               "bit_exact_vs_oracle": bool(ok_oracle)}
+        log(f"[serve] {row}")
+        out["rates"].append(row)
+    sess.free()
     print(json.dumps(out), flush=True)
 
 

@@ -177,7 +177,9 @@ __device__ __forceinline__ int32_t look_finish(const GraphDev &G, const int4 r, 
       }
       if (t != INF) return t;
     }
-    return L.has_next ? L.hn.x : INF;
+    if (!L.has_next) return INF;
+    c.hdr++;
+    return L.hn.x;
   } else {
     const int32_t n = r.w;
     if (n <= 16) {
@@ -204,7 +206,7 @@ __device__ __forceinline__ int32_t look_finish(const GraphDev &G, const int4 r, 
 // Counts the words of a header fetch that a lookup actually needs.
 template <int KIND>
 __device__ __forceinline__ void count_fetch(const int4 r, const Look &L, Ctr &c) {
-  if constexpr (KIND == EAT_LAYOUT_HYBRID) c.hdr += 2;
+  if constexpr (KIND == EAT_LAYOUT_HYBRID) c.hdr += 1;  // +1 more if the next cluster is needed
   else if (L.mode != 0 && r.w <= 16) c.pool += 16;
 }
 
