@@ -94,8 +94,11 @@ typedef struct {
 typedef struct eat_layout eat_layout;
 
 /* Read-only view of a host layout; pointers stay valid until eat_layout_free.
- *   vt_off[n_vertices + 1]: the types leaving u are vt_off[u] .. vt_off[u+1]-1,
- *     ordered by (v, lam).
+ *   vt[2 * n_vertices]: the types leaving u are ty rows vt[2u] .. vt[2u] +
+ *     vt[2u+1] - 1, ordered by (v, lam).
+ *   order[n_vertices]: the stops in the order their type blocks are stored
+ *     (breadth-first over the stop graph: stops close in the graph are close
+ *     in memory).
  *   ty[4 * n_types]: per type {v, lam, a, b}.  Hybrid: a = index of the type's
  *     first cluster header, b = bits 0..31 of its cluster-occupancy mask (bit k
  *     set when cluster k holds a departure).  Flat: a = offset of its
@@ -115,7 +118,8 @@ typedef struct {
   int64_t n_types;
   int64_t n_headers;
   int64_t n_pool;
-  const int32_t *vt_off;
+  const int32_t *vt;
+  const int32_t *order;
   const int32_t *ty;
   const uint32_t *ty_mask_hi;
   const int32_t *hdr;

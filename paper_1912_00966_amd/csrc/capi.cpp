@@ -42,6 +42,8 @@ eat_status device_limits(int dev, DeviceLimits *out) {
   out->cus = p.multiProcessorCount;
   // leave room for the kernel's static shared variables
   out->lds = p.sharedMemPerBlock > 1024 ? p.sharedMemPerBlock - 1024 : p.sharedMemPerBlock;
+  int xcc = 0;
+  if (hipDeviceGetAttribute(&xcc, hipDeviceAttributeNumberOfXccs, dev) == hipSuccess && xcc > 0) out->xccs = xcc;
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
     out->ns_per_tick = (int64_t)((1000000.0 / khz) * 1024.0);
@@ -155,7 +157,8 @@ extern "C" eat_status eat_layout_view_get(const eat_layout *L, eat_layout_view *
   out->n_types = L->n_types;
   out->n_headers = L->n_headers;
   out->n_pool = (int64_t)L->pool.size() - eat::kPoolTail;
-  out->vt_off = L->vt_off.data();
+  out->vt = L->vt.data();
+  out->order = L->order.data();
   out->ty = L->ty.data();
   out->ty_mask_hi = L->kind == EAT_LAYOUT_HYBRID ? L->mask_hi.data() : nullptr;
   out->hdr = L->kind == EAT_LAYOUT_HYBRID ? L->hdr.data() : nullptr;
@@ -176,11 +179,13 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, eat_graph **out) {
   if (!g) return set_err(EAT_ERR_OUT_OF_MEMORY, "host allocation failed");
   HIP_TRY(hipGetDevice(&g->device));
   fill_info(*L, &g->info);
+  g->rank.assign((size_t)L->n_vertices, 0);
+  for (int32_t r = 0; r < L->n_vertices; ++r) g->rank[(size_t)L->order[(size_t)r]] = r;
 
   const bool hybrid = L->kind == EAT_LAYOUT_HYBRID;
   const bool need_hi = hybrid && L->n_clusters > 32;
   const int64_t T = L->n_types;
-  const size_t b_vt = align_up(L->vt_off.size() * 4);
+  const size_t b_vt = align_up(L->vt.size() * 4);
   const size_t b_ty = align_up((size_t)std::max<int64_t>(T, 1) * 16);
   const size_t b_hi = need_hi ? align_up((size_t)std::max<int64_t>(T, 1) * 4) : 0;
   const size_t b_hdr = hybrid ? align_up((size_t)(L->n_headers + 1) * 8) : 0;
@@ -199,7 +204,7 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, eat_graph **out) {
     p += b;
     return q;
   };
-  g->desc.vt_off = reinterpret_cast<const int32_t *>(take(b_vt));
+  g->desc.vt = reinterpret_cast<const int2 *>(take(b_vt));
   g->desc.ty = reinterpret_cast<const int4 *>(take(b_ty));
   g->desc.mask_hi = need_hi ? reinterpret_cast<const uint32_t *>(take(b_hi)) : nullptr;
   g->desc.hdr = hybrid ? reinterpret_cast<const int2 *>(take(b_hdr)) : nullptr;
@@ -219,7 +224,7 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, eat_graph **out) {
     return hipMemcpy(const_cast<void *>(dst), src, bytes, hipMemcpyHostToDevice);
   };
   hipError_t ue = hipSuccess;
-  if (ue == hipSuccess) ue = up(g->desc.vt_off, L->vt_off.data(), L->vt_off.size() * 4);
+  if (ue == hipSuccess) ue = up(g->desc.vt, L->vt.data(), L->vt.size() * 4);
   if (ue == hipSuccess) ue = up(g->desc.ty, L->ty.data(), (size_t)T * 16);
   if (ue == hipSuccess && need_hi) ue = up(g->desc.mask_hi, L->mask_hi.data(), (size_t)T * 4);
   if (ue == hipSuccess && hybrid) {
@@ -330,6 +335,20 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   return EAT_OK;
 }
 
+void order_queries(const std::vector<const eat_graph *> &graphs, std::vector<QueryDev> &qs,
+                   int n_buckets, std::vector<int32_t> &off) {
+  std::stable_sort(qs.begin(), qs.end(), [&](const QueryDev &a, const QueryDev &b) {
+    const eat_graph *ga = graphs[(size_t)a.graph], *gb = graphs[(size_t)b.graph];
+    if (ga->info.n_vertices != gb->info.n_vertices) return ga->info.n_vertices > gb->info.n_vertices;
+    if (a.graph != b.graph) return a.graph < b.graph;
+    return ga->rank[(size_t)a.s] < gb->rank[(size_t)b.s];
+  });
+  const int64_t n = (int64_t)qs.size();
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(n_buckets, std::max<int64_t>(n, 1)));
+  off.assign((size_t)nb + 1, 0);
+  for (int b = 0; b <= nb; ++b) off[(size_t)b] = (int32_t)(n * b / nb);
+}
+
 void apply_plan(const Plan &pl, RunArgs *a) {
   a->max_rounds = pl.max_rounds;
   a->mode = pl.mode;
@@ -362,6 +381,8 @@ extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32
   a.graphs = g->d_desc;
   a.queries = nullptr;
   a.single = QueryDev{0, s, ts, 0, arr};
+  a.buckets = nullptr;
+  a.n_buckets = 1;
   a.nq = 1;
   eat::apply_plan(pl, &a);
   a.work = nullptr;
@@ -422,13 +443,16 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
     qs[(size_t)i] = QueryDev{gi, q_src[i], q_ts[i], i, arr[i]};
     max_v = std::max(max_v, g->info.n_vertices);
   }
-  // Larger graphs first: the longest queries start first and the tail is short.
-  std::stable_sort(qs.begin(), qs.end(), [&](const QueryDev &a, const QueryDev &b) {
-    return graphs[a.graph]->info.n_vertices > graphs[b.graph]->info.n_vertices;
-  });
   Plan pl;
   eat_status st = make_plan(ro, max_v, dev, &pl);
   if (st != EAT_OK) return st;
+  DeviceLimits lim;
+  st = device_limits(dev, &lim);
+  if (st != EAT_OK) return st;
+  std::vector<int32_t> boff;
+  eat::order_queries(std::vector<const eat_graph *>(graphs, graphs + n_graphs), qs,
+                     std::min(lim.xccs, eat::kMaxBuckets), boff);
+  const int nb = (int)boff.size() - 1;
 
   eat_batch *b = new (std::nothrow) eat_batch();
   if (!b) return set_err(EAT_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -440,8 +464,9 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   const size_t b_g = align_up((size_t)n_graphs * sizeof(GraphDev));
   const size_t b_q = align_up(std::max<size_t>((size_t)n_q, 1) * sizeof(QueryDev));
   const size_t b_s = align_up(std::max<size_t>((size_t)n_q, 1) * sizeof(eat_query_stats));
-  const size_t b_c = align_up(4 * sizeof(int32_t));
-  hipError_t e = hipMalloc(&b->d_buf, b_g + b_q + b_s + b_c);
+  const size_t b_c = align_up(eat::kCounterWords * sizeof(int32_t));
+  const size_t b_b = align_up(boff.size() * sizeof(int32_t));
+  hipError_t e = hipMalloc(&b->d_buf, b_g + b_q + b_s + b_c + b_b);
   if (e != hipSuccess) {
     delete b;
     return set_err(EAT_ERR_OUT_OF_MEMORY, "hipMalloc of the batch failed");
@@ -451,24 +476,18 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   QueryDev *d_q = reinterpret_cast<QueryDev *>(p + b_g);
   eat_query_stats *d_s = reinterpret_cast<eat_query_stats *>(p + b_g + b_q);
   int32_t *d_c = reinterpret_cast<int32_t *>(p + b_g + b_q + b_s);
+  int32_t *d_b = reinterpret_cast<int32_t *>(p + b_g + b_q + b_s + b_c);
   std::vector<GraphDev> gd((size_t)n_graphs);
   for (int32_t i = 0; i < n_graphs; ++i) gd[(size_t)i] = graphs[i]->desc;
   e = hipMemcpy(d_g, gd.data(), gd.size() * sizeof(GraphDev), hipMemcpyHostToDevice);
   if (e == hipSuccess && n_q > 0) e = hipMemcpy(d_q, qs.data(), qs.size() * sizeof(QueryDev), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(d_s, 0, b_s + b_c);
+  if (e == hipSuccess) e = hipMemcpy(d_b, boff.data(), boff.size() * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
   if (e != hipSuccess) {
     (void)hipFree(b->d_buf);
     delete b;
     return hip_err(e, "batch upload");
-  }
-  DeviceLimits lim;
-  st = device_limits(dev, &lim);
-  if (st != EAT_OK) {
-    (void)hipFree(b->d_buf);
-    (void)hipEventDestroy(b->done);
-    delete b;
-    return st;
   }
   const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, kind, pl.lds));
   b->grid = std::max(1, std::min<int>(n_q, lim.cus * per_cu));
@@ -477,9 +496,11 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   a.queries = d_q;
   a.nq = n_q;
   eat::apply_plan(pl, &a);
+  a.buckets = d_b;
+  a.n_buckets = nb;
   a.work = d_c;
   a.stats = d_s;
-  a.n_failed = d_c + 2;
+  a.n_failed = d_c + 1;
   *out = b;
   return EAT_OK;
 }
@@ -503,7 +524,7 @@ extern "C" eat_status eat_batch_wait(eat_batch *b, eat_query_stats *stats) {
   }
   HIP_TRY(hipEventSynchronize(b->done));
   int32_t failed = 0;
-  HIP_TRY(hipMemcpy(&failed, b->args.work + 3, 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(&failed, b->args.work + 2, 4, hipMemcpyDeviceToHost));
   if (stats && b->n_q > 0)
     HIP_TRY(hipMemcpy(stats, b->args.stats, sizeof(eat_query_stats) * (size_t)b->n_q, hipMemcpyDeviceToHost));
   if (failed) return set_err(EAT_ERR_NOT_CONVERGED, std::to_string(failed) + " queries hit their round limit");

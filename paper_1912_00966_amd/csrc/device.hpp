@@ -11,7 +11,7 @@ namespace eat {
 
 // One device-resident timetable (see eat_layout_view in eat.h for the arrays).
 struct GraphDev {
-  const int32_t *vt_off;   // [V+1]
+  const int2 *vt;          // [V] per stop: first type, type count
   const int4 *ty;          // [T] {v, lam, a, b}
   const uint32_t *mask_hi; // [T] hybrid, or nullptr when every cluster index < 32
   const int2 *hdr;         // [K + 1] hybrid (one padding entry)
@@ -46,17 +46,25 @@ struct RunArgs {
   int32_t bm_words;          // activity bitmap words (>= ceil(V / 32) of every graph)
   int32_t table_cap;         // on-chip arrival table slots (power of two), 0 = none
   int32_t table_bits;        // log2(table_cap)
+  // Queries are split into n_buckets contiguous buckets (queries[buckets[b]]
+  // .. queries[buckets[b+1]-1]); work-group w takes queries from bucket
+  // w % n_buckets first (work-groups are dealt to the XCDs in turn, so a
+  // bucket's queries share one XCD's L2), then helps the other buckets.
+  const int32_t *buckets;    // device array of n_buckets + 1 offsets (batch only)
+  int32_t n_buckets;
   // Batch counters (batch only; zero before the first launch, re-armed by the
-  // last work-group of every launch): [0] next query, [1] work-groups done,
-  // [2] queries of this launch that hit the round limit, [3] that count for
-  // the previous completed launch.
+  // last work-group of every launch): [0] work-groups done, [1] queries of
+  // this launch that hit the round limit, [2] that count for the previous
+  // completed launch, [4 + b] next query of bucket b.
   int32_t *work;
   eat_query_stats *stats;    // per query, indexed by QueryDev::index; nullable
-  int32_t *n_failed;         // == work + 2 in a batch; nullable
+  int32_t *n_failed;         // == work + 1 in a batch; nullable
   int64_t ns_per_tick;       // device wall clock period in ns (x 1024)
 };
 
 constexpr int kBlock = 1024;
+constexpr int kMaxBuckets = 32;
+constexpr int kCounterWords = 4 + kMaxBuckets;
 
 // Host-side launchers (kernels.hip).
 hipError_t launch_relax(const RunArgs &a, int tpv, int kind, int grid, size_t lds_bytes,

@@ -5,6 +5,7 @@
 
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "device.hpp"
 #include "eat.h"
@@ -18,6 +19,7 @@ struct eat_graph {
   std::mutex mu;                   // guards the single-query scratch
   eat_query_stats *d_stats = nullptr;
   int32_t *d_failed = nullptr;
+  std::vector<int32_t> rank;       // position of each stop in the layout order
 };
 
 namespace eat {
@@ -37,6 +39,7 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct DeviceLimits {
   int cus = 0;
+  int xccs = 1;  // L2 domains (XCDs) that work-groups are dealt to in turn
   size_t lds = 0;
   int64_t ns_per_tick = 10 << 10;  // wall clock period in ns, fixed point x 1024
 };
@@ -58,5 +61,12 @@ struct Plan {
 eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan *pl);
 // RunArgs fields that come from a plan.
 void apply_plan(const Plan &pl, RunArgs *a);
+
+// Orders queries for a launch: larger graphs first, then by the layout
+// position of the source (nearby sources touch nearby data), and splits them
+// into n_buckets contiguous buckets of nearly equal size; off receives
+// n_buckets + 1 offsets.
+void order_queries(const std::vector<const eat_graph *> &graphs, std::vector<QueryDev> &qs,
+                   int n_buckets, std::vector<int32_t> &off);
 
 }  // namespace eat

@@ -336,8 +336,9 @@ __device__ __forceinline__ bool mark_improved(const GraphDev &G, const Store &S,
   const uint32_t bit = 1u << (it & 31);
   const bool first = !(atomicOr(&S.bits[it >> 5], bit) & bit);
   if (first) {
-    beg = G.vt_off[v];
-    cnt = G.vt_off[v + 1] - beg;
+    const int2 r = G.vt[v];
+    beg = r.x;
+    cnt = r.y;
   }
   return first;
 }
@@ -496,9 +497,9 @@ __device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, c
         d = cur.cnt[e];
         if (d < 0) {  // staged by a sweep: load the stop's type range
           const int32_t u = S.stop(item);
-          const int32_t b = G.vt_off[u];
-          d = G.vt_off[u + 1] - b;
-          cur.beg[e] = b;
+          const int2 r = G.vt[u];
+          d = r.y;
+          cur.beg[e] = r.x;
         }
         c.act++;
       }
@@ -538,9 +539,9 @@ __device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, c
       if (clear) atomicAnd(&S.bits[item >> 5], ~(1u << (item & 31)));
       if (cur.cnt[e] < 0) {
         const int32_t u = S.stop(item);
-        const int32_t b = G.vt_off[u];
-        cur.beg[e] = b;
-        cur.cnt[e] = G.vt_off[u + 1] - b;
+        const int2 r = G.vt[u];
+        cur.beg[e] = r.x;
+        cur.cnt[e] = r.y;
       }
     }
     __syncthreads();
@@ -648,9 +649,26 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
   const int32_t F = a.fcap;
 
   for (int iter = 0;; ++iter) {
-    if (tid == 0)
-      sh.q = batch ? __hip_atomic_fetch_add(a.work, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                   : (iter == 0 ? 0 : a.nq);
+    if (tid == 0) {
+      int32_t q = a.nq;
+      if (batch) {
+        const int32_t nb = a.n_buckets;
+        int32_t b = (int32_t)(blockIdx.x % (uint32_t)nb);
+        for (int32_t k = 0; k < nb; ++k, b = (b + 1 == nb) ? 0 : b + 1) {
+          const int32_t lo = a.buckets[b], cnt = a.buckets[b + 1] - lo;
+          int32_t *cursor = a.work + 4 + b;
+          if (__hip_atomic_load(cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= cnt) continue;
+          const int32_t i = __hip_atomic_fetch_add(cursor, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (i < cnt) {
+            q = lo + i;
+            break;
+          }
+        }
+      } else if (iter == 0) {
+        q = 0;
+      }
+      sh.q = q;
+    }
     if (tid < 5) sh.acc[tid] = 0ull;
     if (tid == 0) {
       sh.count = 0;
@@ -663,11 +681,12 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       // The last work-group to leave re-arms the shared counters for the next
       // launch of the same batch, so a run is a single kernel launch.
       if (batch && tid == 0) {
-        const int32_t left = __hip_atomic_fetch_add(a.work + 1, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const int32_t left = __hip_atomic_fetch_add(a.work, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (left == (int32_t)gridDim.x - 1) {
-          const int32_t failed = __hip_atomic_exchange(a.work + 2, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(a.work + 3, failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(a.work + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const int32_t failed = __hip_atomic_exchange(a.work + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(a.work + 2, failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          for (int32_t b = 0; b < a.n_buckets; ++b)
+            __hip_atomic_store(a.work + 4 + b, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           __hip_atomic_store(a.work, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
       }

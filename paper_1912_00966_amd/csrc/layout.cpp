@@ -5,9 +5,10 @@
 // the clusters of departures that fall in the same hour (Section II-D), and per
 // cluster the arithmetic-progression tuples that cover its departures (Section
 // II-C).  Here:
-//   * types are ordered by tail so that one active stop's types are contiguous
-//     (vt_off), and by (v, lam) inside a stop, which also keeps the types of one
-//     edge (u, v) of Section II-E adjacent;
+//   * one active stop's types are contiguous (vt: first type and count per
+//     stop) and ordered by (v, lam), which also keeps the types of one edge
+//     (u, v) of Section II-E adjacent; the stops' blocks follow a breadth-first
+//     order of the stop graph, so stops close in the graph sit close in memory;
 //   * only non-empty clusters get a header; a 64-bit occupancy mask per type
 //     plus a population count finds the header of any cluster in O(1);
 //   * a cluster whose sorted departures form one progression is stored as that
@@ -85,6 +86,69 @@ void for_each_cluster(const Rec *d, int64_t n, int32_t cw, Emit &&emit) {
     emit(k, ap, d[i].t, h, cnt, i);
     i = j;
   }
+}
+
+// Stop order for the layout: breadth-first over the stop graph (edges in both
+// directions), each connected component started from a pseudo-peripheral stop
+// (the last stop reached by a first sweep).  Stops that are close in the
+// graph get close positions, so one query's stops share cache lines, and a
+// contiguous range of positions is a connected region.
+std::vector<int32_t> locality_order(int32_t nv, const std::vector<int64_t> &out_off,
+                                    const std::vector<int32_t> &out_v) {
+  std::vector<int64_t> nb_off((size_t)nv + 1, 0);
+  for (int32_t u = 0; u < nv; ++u) {
+    nb_off[(size_t)u + 1] += out_off[(size_t)u + 1] - out_off[(size_t)u];
+    for (int64_t k = out_off[(size_t)u]; k < out_off[(size_t)u + 1]; ++k) nb_off[(size_t)out_v[(size_t)k] + 1]++;
+  }
+  for (int32_t u = 0; u < nv; ++u) nb_off[(size_t)u + 1] += nb_off[(size_t)u];
+  std::vector<int32_t> nb((size_t)nb_off[(size_t)nv]);
+  std::vector<int64_t> fill(nb_off.begin(), nb_off.end() - 1);
+  for (int32_t u = 0; u < nv; ++u)
+    for (int64_t k = out_off[(size_t)u]; k < out_off[(size_t)u + 1]; ++k) {
+      const int32_t v = out_v[(size_t)k];
+      nb[(size_t)fill[(size_t)u]++] = v;
+      nb[(size_t)fill[(size_t)v]++] = u;
+    }
+  std::vector<int32_t> order;
+  order.reserve((size_t)nv);
+  std::vector<int32_t> seen((size_t)nv, -1);  // component stamp of the first sweep
+  std::vector<char> placed((size_t)nv, 0);
+  std::vector<int32_t> queue((size_t)nv);
+  for (int32_t start = 0; start < nv; ++start) {
+    if (placed[(size_t)start]) continue;
+    // first sweep: the last stop reached is far from `start`
+    size_t qh = 0, qt = 0;
+    queue[qt++] = start;
+    seen[(size_t)start] = start;
+    int32_t last = start;
+    while (qh < qt) {
+      const int32_t u = queue[qh++];
+      last = u;
+      for (int64_t k = nb_off[(size_t)u]; k < nb_off[(size_t)u + 1]; ++k) {
+        const int32_t v = nb[(size_t)k];
+        if (seen[(size_t)v] != start) {
+          seen[(size_t)v] = start;
+          queue[qt++] = v;
+        }
+      }
+    }
+    // second sweep from there fixes the order of the component
+    qh = qt = 0;
+    queue[qt++] = last;
+    placed[(size_t)last] = 1;
+    while (qh < qt) {
+      const int32_t u = queue[qh++];
+      order.push_back(u);
+      for (int64_t k = nb_off[(size_t)u]; k < nb_off[(size_t)u + 1]; ++k) {
+        const int32_t v = nb[(size_t)k];
+        if (!placed[(size_t)v]) {
+          placed[(size_t)v] = 1;
+          queue[qt++] = v;
+        }
+      }
+    }
+  }
+  return order;
 }
 
 }  // namespace
@@ -241,14 +305,42 @@ eat_status build_layout(const int32_t *u, const int32_t *v, const int32_t *t,
       }
     }
   });
-  for (int32_t a = 0; a < nv; ++a) {
-    n_ty_u[(size_t)a + 1] += n_ty_u[(size_t)a];
-    n_hd_u[(size_t)a + 1] += n_hd_u[(size_t)a];
-    n_pl_u[(size_t)a + 1] += n_pl_u[(size_t)a];
+  // ---- 3b. layout order of the stops ------------------------------------------
+  {
+    std::vector<int64_t> out_off((size_t)nv + 1, 0);
+    for (int32_t a = 0; a < nv; ++a) {
+      const Rec *b = rec.data() + boff[(size_t)a];
+      int64_t ne = 0;
+      for (int64_t i = 0; i < blen[(size_t)a]; ++i) ne += (i == 0 || b[i].v != b[i - 1].v);
+      out_off[(size_t)a + 1] = out_off[(size_t)a] + ne;
+    }
+    std::vector<int32_t> out_v((size_t)out_off[(size_t)nv]);
+    for (int32_t a = 0; a < nv; ++a) {
+      const Rec *b = rec.data() + boff[(size_t)a];
+      int64_t k = out_off[(size_t)a];
+      for (int64_t i = 0; i < blen[(size_t)a]; ++i)
+        if (i == 0 || b[i].v != b[i - 1].v) out_v[(size_t)k++] = b[i].v;
+    }
+    L.order = locality_order(nv, out_off, out_v);
   }
-  L.n_types = n_ty_u[(size_t)nv];
-  L.n_headers = n_hd_u[(size_t)nv];
-  const int64_t npool = n_pl_u[(size_t)nv];
+  // offsets of every stop's block, in layout order
+  std::vector<int64_t> ty_at((size_t)nv), hd_at((size_t)nv), pl_at((size_t)nv);
+  {
+    int64_t t0 = 0, h0 = 0, p0 = 0;
+    for (int32_t r = 0; r < nv; ++r) {
+      const int32_t a = L.order[(size_t)r];
+      ty_at[(size_t)a] = t0;
+      hd_at[(size_t)a] = h0;
+      pl_at[(size_t)a] = p0;
+      t0 += n_ty_u[(size_t)a + 1];
+      h0 += n_hd_u[(size_t)a + 1];
+      p0 += n_pl_u[(size_t)a + 1];
+    }
+    L.n_types = t0;
+    L.n_headers = h0;
+  }
+  int64_t npool = 0;
+  for (int32_t a = 0; a < nv; ++a) npool += n_pl_u[(size_t)a + 1];
   for (int c = 0; c < nth; ++c) {
     L.n_edges += edges_c[(size_t)c];
     L.n_ap += ap_c[(size_t)c];
@@ -262,7 +354,7 @@ eat_status build_layout(const int32_t *u, const int32_t *v, const int32_t *t,
 
   // ---- 4. fill the arrays ----------------------------------------------------
   try {
-    L.vt_off.assign((size_t)nv + 1, 0);
+    L.vt.assign((size_t)nv * 2, 0);
     L.ty.assign((size_t)(4 * std::max<int64_t>(L.n_types, 1)), 0);
     if (hybrid) {
       L.mask_hi.assign((size_t)std::max<int64_t>(L.n_types, 1), 0u);
@@ -274,15 +366,18 @@ eat_status build_layout(const int32_t *u, const int32_t *v, const int32_t *t,
   } catch (const std::bad_alloc &) {
     return fail(EAT_ERR_OUT_OF_MEMORY, "host allocation failed");
   }
-  for (int32_t a = 0; a <= nv; ++a) L.vt_off[(size_t)a] = (int32_t)n_ty_u[(size_t)a];
+  for (int32_t a = 0; a < nv; ++a) {
+    L.vt[(size_t)2 * a] = (int32_t)ty_at[(size_t)a];
+    L.vt[(size_t)2 * a + 1] = (int32_t)n_ty_u[(size_t)a + 1];
+  }
   std::vector<int32_t> maxdeg((size_t)nth, 0);
   parallel_for_chunks(nth, nth, [&](int, int64_t cb, int64_t ce) {
     for (int64_t c = cb; c < ce; ++c) {
       for (int32_t a = split[(size_t)c]; a < split[(size_t)c + 1]; ++a) {
         const Rec *b = rec.data() + boff[(size_t)a];
         int64_t w = blen[(size_t)a];
-        int64_t ti = n_ty_u[(size_t)a], hi = n_hd_u[(size_t)a], pi = n_pl_u[(size_t)a];
-        maxdeg[(size_t)c] = std::max<int32_t>(maxdeg[(size_t)c], (int32_t)(n_ty_u[(size_t)a + 1] - ti));
+        int64_t ti = ty_at[(size_t)a], hi = hd_at[(size_t)a], pi = pl_at[(size_t)a];
+        maxdeg[(size_t)c] = std::max<int32_t>(maxdeg[(size_t)c], (int32_t)n_ty_u[(size_t)a + 1]);
         int64_t i = 0;
         while (i < w) {
           int64_t j = i + 1;

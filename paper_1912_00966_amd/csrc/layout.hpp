@@ -16,7 +16,8 @@ struct eat_layout {
   int32_t max_types_per_vertex = 0;
   int64_t n_conn_input = 0, n_self_loops = 0, n_duplicates = 0, n_conn = 0;
   int64_t n_edges = 0, n_types = 0, n_headers = 0, n_ap = 0, n_array = 0;
-  std::vector<int32_t> vt_off;    // [V+1]
+  std::vector<int32_t> vt;        // [2V] per stop: first type, type count
+  std::vector<int32_t> order;     // [V] the stops in layout order
   std::vector<int32_t> ty;        // [4*T]
   std::vector<uint32_t> mask_hi;  // [T] (hybrid)
   std::vector<int32_t> hdr;       // [2*K] (hybrid)

@@ -42,7 +42,9 @@ struct StepBlock {
   QueryDev *d_q = nullptr;
   eat_query_stats *d_stats = nullptr;
   int32_t *d_ctr = nullptr;
+  int32_t *d_b = nullptr;               // bucket offsets
   QueryDev *h_q = nullptr;              // pinned
+  int32_t *h_b = nullptr;               // pinned
   eat_query_stats *h_stats = nullptr;   // pinned
   hipEvent_t done = nullptr;
   hipStream_t stream = nullptr;
@@ -60,6 +62,7 @@ struct eat_session {
   GraphDev *d_graphs = nullptr;
   eat::Plan plan;
   int grid_cap = 1;
+  int n_buckets = 1;
   int32_t max_step = 4096;
   int32_t *d_pool = nullptr;
   int64_t pool_words = 0;
@@ -83,6 +86,7 @@ void destroy(eat_session *S) {
     if (b.done) (void)hipEventDestroy(b.done);
     if (b.stream) (void)hipStreamDestroy(b.stream);
     if (b.h_q) (void)hipHostFree(b.h_q);
+    if (b.h_b) (void)hipHostFree(b.h_b);
     if (b.h_stats) (void)hipHostFree(b.h_stats);
     if (b.d_q) (void)hipFree(b.d_q);
   }
@@ -187,6 +191,7 @@ extern "C" eat_status eat_session_create(const eat_graph *const *graphs, int32_t
   S->max_step = max_step;
   const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, kind, pl.lds));
   S->grid_cap = lim.cus * per_cu;
+  S->n_buckets = std::min(lim.xccs, eat::kMaxBuckets);
   S->pool_words = pool_bytes / 4 / kSlotAlignWords * kSlotAlignWords;
   auto fail = [&](eat_status s2, const std::string &m) {
     destroy(S);
@@ -206,12 +211,14 @@ extern "C" eat_status eat_session_create(const eat_graph *const *graphs, int32_t
   const size_t bs = eat::align_up((size_t)max_step * sizeof(eat_query_stats));
   for (auto &b : S->blocks) {
     void *p = nullptr;
-    if (hipMalloc(&p, bq + bs + 256) != hipSuccess) return fail(EAT_ERR_OUT_OF_MEMORY, "step block");
+    if (hipMalloc(&p, bq + bs + 512) != hipSuccess) return fail(EAT_ERR_OUT_OF_MEMORY, "step block");
     b.d_q = static_cast<QueryDev *>(p);
     b.d_stats = reinterpret_cast<eat_query_stats *>(static_cast<char *>(p) + bq);
     b.d_ctr = reinterpret_cast<int32_t *>(static_cast<char *>(p) + bq + bs);
+    b.d_b = reinterpret_cast<int32_t *>(static_cast<char *>(p) + bq + bs + 256);
     if (hipMemset(b.d_ctr, 0, 256) != hipSuccess) return fail(EAT_ERR_DEVICE, "step counters");
-    if (hipHostMalloc((void **)&b.h_q, bq, hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc((void **)&b.h_b, 256, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&b.h_q, bq, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&b.h_stats, bs, hipHostMallocDefault) != hipSuccess)
       return fail(EAT_ERR_OUT_OF_MEMORY, "pinned step staging");
     if (hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) != hipSuccess ||
@@ -281,25 +288,28 @@ extern "C" eat_status eat_session_step(eat_session *S, int32_t *n_launched) {
   const int32_t n = (int32_t)std::min<size_t>(S->admitted.size(), (size_t)S->max_step);
   b.slots.assign(S->admitted.begin(), S->admitted.begin() + n);
   S->admitted.erase(S->admitted.begin(), S->admitted.begin() + n);
-  // larger graphs first (longest queries start first)
-  std::stable_sort(b.slots.begin(), b.slots.end(), [&](int32_t a, int32_t c) {
-    return S->graphs[(size_t)S->slots[(size_t)a].graph]->info.n_vertices >
-           S->graphs[(size_t)S->slots[(size_t)c].graph]->info.n_vertices;
-  });
+  std::vector<QueryDev> qs((size_t)n);
   for (int32_t i = 0; i < n; ++i) {
     Slot &sl = S->slots[(size_t)b.slots[(size_t)i]];
     sl.state = kLaunched;
-    b.h_q[i] = QueryDev{sl.graph, sl.s, sl.ts, i, S->d_pool + sl.off};
+    qs[(size_t)i] = QueryDev{sl.graph, sl.s, sl.ts, i, S->d_pool + sl.off};
   }
+  std::vector<int32_t> boff;
+  eat::order_queries(S->graphs, qs, S->n_buckets, boff);
+  std::copy(qs.begin(), qs.end(), b.h_q);
+  std::copy(boff.begin(), boff.end(), b.h_b);
   HIP_TRY(hipMemcpyAsync(b.d_q, b.h_q, sizeof(QueryDev) * (size_t)n, hipMemcpyHostToDevice, b.stream));
+  HIP_TRY(hipMemcpyAsync(b.d_b, b.h_b, sizeof(int32_t) * boff.size(), hipMemcpyHostToDevice, b.stream));
   RunArgs a{};
   a.graphs = S->d_graphs;
   a.queries = b.d_q;
   a.nq = n;
   eat::apply_plan(S->plan, &a);
+  a.buckets = b.d_b;
+  a.n_buckets = (int32_t)boff.size() - 1;
   a.work = b.d_ctr;
   a.stats = b.d_stats;
-  a.n_failed = b.d_ctr + 2;
+  a.n_failed = b.d_ctr + 1;
   const int grid = std::max(1, std::min(n, S->grid_cap));
   hipError_t e = eat::launch_relax(a, S->plan.tpv, S->graphs[0]->info.layout, grid, S->plan.lds, b.stream);
   if (e != hipSuccess) return hip_err(e, "relaxation launch");

@@ -74,7 +74,7 @@ class LayoutView(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_int32), ("n_vertices", ctypes.c_int32),
                 ("cluster_seconds", ctypes.c_int32), ("n_clusters", ctypes.c_int32),
                 ("n_types", ctypes.c_int64), ("n_headers", ctypes.c_int64),
-                ("n_pool", ctypes.c_int64), ("vt_off", _i32p), ("ty", _i32p),
+                ("n_pool", ctypes.c_int64), ("vt", _i32p), ("order", _i32p), ("ty", _i32p),
                 ("ty_mask_hi", _u32p), ("hdr", _i32p), ("pool", _i32p)]
 
 
@@ -249,7 +249,8 @@ class Layout:
         out = dict(layout=lv.layout, n_vertices=lv.n_vertices, cluster_seconds=lv.cluster_seconds,
                    n_clusters=lv.n_clusters, n_types=lv.n_types, n_headers=lv.n_headers,
                    n_pool=lv.n_pool)
-        out["vt_off"] = take(lv.vt_off, lv.n_vertices + 1)
+        out["vt"] = take(lv.vt, 2 * lv.n_vertices).reshape(-1, 2)
+        out["order"] = take(lv.order, lv.n_vertices)
         out["ty"] = take(lv.ty, 4 * lv.n_types).reshape(-1, 4)
         out["ty_mask_hi"] = take(lv.ty_mask_hi, lv.n_types if lv.ty_mask_hi else 0, np.uint32)
         out["hdr"] = take(lv.hdr, 2 * lv.n_headers if lv.hdr else 0).reshape(-1, 2)

@@ -69,8 +69,10 @@ def _query(g, s, ts, **opt):
 
 def _types_of(view):
     """(u, v, lam) of every layout type, in layout order."""
-    vt = view["vt_off"]
-    u = np.repeat(np.arange(len(vt) - 1), np.diff(vt))
+    vt = view["vt"]
+    u = np.empty(len(view["ty"]), dtype=np.int64)
+    for stop in range(len(vt)):
+        u[vt[stop, 0]: vt[stop, 0] + vt[stop, 1]] = stop
     return u, view["ty"][:, 0], view["ty"][:, 1]
 
 

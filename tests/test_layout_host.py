@@ -66,6 +66,17 @@ def _expand(view, tcol=None):
     return out
 
 
+def _check_order(view):
+    """order is a permutation of the stops and the type blocks follow it."""
+    order, vt = view["order"], view["vt"]
+    assert sorted(order.tolist()) == list(range(len(vt)))
+    pos = 0
+    for stop in order:
+        assert vt[stop, 0] == pos
+        pos += vt[stop, 1]
+    assert pos == len(view["ty"])
+
+
 def _reference_types(tt):
     """{(u, v, lam): sorted distinct departures}, self-loops dropped."""
     keep = tt.u != tt.v
@@ -86,14 +97,15 @@ def test_layout_keeps_exactly_the_input_departures(layout, cw):
     info = lay.info()
     ref = _reference_types(tt)
     got = _expand(view)
-    ty, vt = view["ty"], view["vt_off"]
-    assert vt[0] == 0 and vt[-1] == len(ty) == info.n_types == len(ref)
+    ty, vt = view["ty"], view["vt"]
+    assert len(ty) == info.n_types == len(ref) == int(vt[:, 1].sum())
+    _check_order(view)
     seen = {}
     for uu in range(tt.n_vertices):
-        rows = ty[vt[uu]:vt[uu + 1]]
+        rows = ty[vt[uu, 0]:vt[uu, 0] + vt[uu, 1]]
         keys = [(int(r[0]), int(r[1])) for r in rows]
         assert keys == sorted(keys) and len(set(keys)) == len(keys)
-        for j in range(vt[uu], vt[uu + 1]):
+        for j in range(vt[uu, 0], vt[uu, 0] + vt[uu, 1]):
             seen[(uu, int(ty[j, 0]), int(ty[j, 1]))] = got[j]
     assert seen == ref
     assert info.n_conn == sum(len(d) for d in ref.values())
@@ -126,10 +138,11 @@ def test_layout_on_random_tiny_timetables_with_duplicates_and_loops():
             view = lay.view()
             got = _expand(view)
             ref = _reference_types(tt)
-            vt, ty = view["vt_off"], view["ty"]
+            vt, ty = view["vt"], view["ty"]
+            _check_order(view)
             seen = {}
             for uu in range(tt.n_vertices):
-                for j in range(vt[uu], vt[uu + 1]):
+                for j in range(vt[uu, 0], vt[uu, 0] + vt[uu, 1]):
                     seen[(uu, int(ty[j, 0]), int(ty[j, 1]))] = got[j]
             assert seen == ref
             info = lay.info()
