@@ -186,13 +186,12 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, eat_graph **out) {
   const bool need_hi = hybrid && L->n_clusters > 32;
   const int64_t T = L->n_types;
   const size_t b_vt = align_up(L->vt.size() * 4);
-  const size_t b_ty = align_up((size_t)std::max<int64_t>(T, 1) * 16);
-  const size_t b_hi = need_hi ? align_up((size_t)std::max<int64_t>(T, 1) * 4) : 0;
+  const size_t b_ty = align_up((size_t)std::max<int64_t>(T, 1) * 32);
   const size_t b_hdr = hybrid ? align_up((size_t)(L->n_headers + 1) * 8) : 0;
   const size_t b_pool = align_up(std::max<size_t>(L->pool.size(), 1) * 4);
   const size_t b_desc = align_up(sizeof(GraphDev));
   const size_t b_stats = align_up(sizeof(eat_query_stats)) + align_up(4);
-  const size_t total = b_vt + b_ty + b_hi + b_hdr + b_pool + b_desc + b_stats;
+  const size_t total = b_vt + b_ty + b_hdr + b_pool + b_desc + b_stats;
   hipError_t e = hipMalloc(&g->d_buf, total);
   if (e != hipSuccess) {
     delete g;
@@ -206,7 +205,6 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, eat_graph **out) {
   };
   g->desc.vt = reinterpret_cast<const int2 *>(take(b_vt));
   g->desc.ty = reinterpret_cast<const int4 *>(take(b_ty));
-  g->desc.mask_hi = need_hi ? reinterpret_cast<const uint32_t *>(take(b_hi)) : nullptr;
   g->desc.hdr = hybrid ? reinterpret_cast<const int2 *>(take(b_hdr)) : nullptr;
   g->desc.pool = reinterpret_cast<const int32_t *>(take(b_pool));
   g->d_desc = reinterpret_cast<GraphDev *>(take(b_desc));
@@ -225,8 +223,29 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, eat_graph **out) {
   };
   hipError_t ue = hipSuccess;
   if (ue == hipSuccess) ue = up(g->desc.vt, L->vt.data(), L->vt.size() * 4);
-  if (ue == hipSuccess) ue = up(g->desc.ty, L->ty.data(), (size_t)T * 16);
-  if (ue == hipSuccess && need_hi) ue = up(g->desc.mask_hi, L->mask_hi.data(), (size_t)T * 4);
+  if (ue == hipSuccess && T > 0) {
+    std::vector<int32_t> ty2;
+    try {
+      ty2.resize((size_t)T * 8);
+    } catch (const std::bad_alloc &) {
+      ue = hipErrorOutOfMemory;
+    }
+    if (ue == hipSuccess) {
+      for (int64_t j = 0; j < T; ++j) {
+        const int32_t *r = &L->ty[(size_t)(4 * j)];
+        int32_t *o = &ty2[(size_t)(8 * j)];
+        o[0] = r[0];
+        o[1] = r[1];
+        o[2] = r[2];
+        o[3] = r[3];
+        o[4] = L->vt[(size_t)2 * r[0]];
+        o[5] = L->vt[(size_t)2 * r[0] + 1];
+        o[6] = need_hi ? (int32_t)L->mask_hi[(size_t)j] : 0;
+        o[7] = 0;
+      }
+      ue = up(g->desc.ty, ty2.data(), (size_t)T * 32);
+    }
+  }
   if (ue == hipSuccess && hybrid) {
     ue = up(g->desc.hdr, L->hdr.data(), (size_t)L->n_headers * 8);
     if (ue == hipSuccess) ue = hipMemset(const_cast<int2 *>(g->desc.hdr) + L->n_headers, 0, 8);

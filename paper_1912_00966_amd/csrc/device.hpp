@@ -12,8 +12,10 @@ namespace eat {
 // One device-resident timetable (see eat_layout_view in eat.h for the arrays).
 struct GraphDev {
   const int2 *vt;          // [V] per stop: first type, type count
-  const int4 *ty;          // [T] {v, lam, a, b}
-  const uint32_t *mask_hi; // [T] hybrid, or nullptr when every cluster index < 32
+  // [2T] per type two int4: {v, lam, a, b} as in the host layout, then
+  // {first type of v, type count of v, cluster-occupancy bits 32..63, 0}.  The
+  // second half lets a lane that improves v push it without another read.
+  const int4 *ty;
   const int2 *hdr;         // [K + 1] hybrid (one padding entry)
   const int32_t *pool;     // departures
   int64_t n_types;

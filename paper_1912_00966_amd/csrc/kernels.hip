@@ -215,7 +215,7 @@ __device__ __forceinline__ void count_fetch(const int4 r, const Look &L, Ctr &c)
 template <int KIND>
 __device__ __forceinline__ int32_t next_departure(const GraphDev &G, const int4 r, int64_t j, int32_t x, Ctr &c) {
   Look L;
-  const uint32_t mhi = (KIND == EAT_LAYOUT_HYBRID && G.mask_hi) ? G.mask_hi[j] : 0u;
+  const uint32_t mhi = (KIND == EAT_LAYOUT_HYBRID && G.n_clusters > 32) ? (uint32_t)G.ty[2 * j + 1].z : 0u;
   look_locate<KIND>(G, r, mhi, x, L);
   if (L.mode == 0) return INF;
   look_fetch_headers<KIND>(G, r, L);
@@ -327,32 +327,25 @@ struct TableStore {
   __device__ __forceinline__ int32_t lower(int32_t item, int32_t cand) const { return atomicMin(vals + item, cand); }
 };
 
-// After a successful atomic minimum on item (stop v): set the item's bit; the
-// lane that sets it pushes the item with v's type range, whose load is issued
-// here so that it overlaps the push.
+// After a successful atomic minimum on item: set the item's bit; the lane that
+// sets it pushes the item (the caller holds the stop's type range).
 template <class Store>
-__device__ __forceinline__ bool mark_improved(const GraphDev &G, const Store &S, int32_t it, int32_t v,
-                                              int32_t &beg, int32_t &cnt) {
+__device__ __forceinline__ bool mark_improved(const Store &S, int32_t it) {
   const uint32_t bit = 1u << (it & 31);
-  const bool first = !(atomicOr(&S.bits[it >> 5], bit) & bit);
-  if (first) {
-    const int2 r = G.vt[v];
-    beg = r.x;
-    cnt = r.y;
-  }
-  return first;
+  return !(atomicOr(&S.bits[it >> 5], bit) & bit);
 }
 
 // Relax (Algorithm 3) the best connection of type j for a tail reached at x.
 template <int KIND, class Store>
 __device__ __forceinline__ void relax(const GraphDev &G, const Store &S, int64_t j, int32_t x,
                                       const FList &nxt, int32_t fcap, bool append, int32_t *nn, Ctr &c) {
-  const int4 r = G.ty[j];
+  const int4 r = G.ty[2 * j];
+  const int4 r2 = G.ty[2 * j + 1];
   const int32_t v = r.x, lam = r.y;
   c.tev++;
   const int32_t av = S.find(v);
   bool want = false;
-  int32_t item = 0, beg = 0, cnt = 0;
+  int32_t item = 0;
   // Any departure of this type leaves at t_c >= x, so it arrives at >= x + lam:
   // skip the lookup when that cannot beat arr[v] (early termination, Section
   // III-D, in its strongest exact form).
@@ -366,13 +359,13 @@ __device__ __forceinline__ void relax(const GraphDev &G, const Store &S, int64_t
           const int32_t old = S.lower(item, cand);
           if (cand < old) {
             c.imp++;
-            want = mark_improved(G, S, item, v, beg, cnt);
+            want = mark_improved(S, item);
           }
         }
       }
     }
   }
-  push(want, item, beg, cnt, nxt, fcap, append, nn);
+  push(want, item, r2.x, r2.y, nxt, fcap, append, nn);
 }
 
 // Relax U connection types per lane with their memory reads overlapped: all
@@ -382,18 +375,17 @@ template <int KIND, int U, class Store>
 __device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, const int64_t *j,
                                             const int32_t *x, const bool *ok, const FList &nxt, int32_t fcap,
                                             bool append, int32_t *nn, Ctr &c) {
-  int4 r[U];
-  uint32_t mhi[U];
+  int4 r[U], r2[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int64_t jj = ok[u] ? j[u] : 0;  // type 0 always exists when any item does
-    r[u] = G.ty[jj];
-    mhi[u] = (KIND == EAT_LAYOUT_HYBRID && G.mask_hi) ? G.mask_hi[jj] : 0u;
+    r[u] = G.ty[2 * jj];
+    r2[u] = G.ty[2 * jj + 1];
   }
   Look L[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    look_locate<KIND>(G, r[u], mhi[u], x[u], L[u]);
+    look_locate<KIND>(G, r[u], KIND == EAT_LAYOUT_HYBRID ? (uint32_t)r2[u].z : 0u, x[u], L[u]);
     if (!ok[u]) L[u].mode = 0;
     look_fetch_headers<KIND>(G, r[u], L[u]);
   }
@@ -412,11 +404,11 @@ __device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, c
     }
   }
   bool want[U];
-  int32_t item[U], beg[U], cnt[U];
+  int32_t item[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     want[u] = false;
-    item[u] = beg[u] = cnt[u] = 0;
+    item[u] = 0;
     if (live[u]) {
       const int32_t tc = look_finish<KIND>(G, r[u], x[u], L[u], c);
       if (tc != INF) {
@@ -427,7 +419,7 @@ __device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, c
             const int32_t old = S.lower(it, cand);
             if (cand < old) {
               c.imp++;
-              want[u] = mark_improved(G, S, it, r[u].x, beg[u], cnt[u]);
+              want[u] = mark_improved(S, it);
               item[u] = it;
             }
           }
@@ -436,7 +428,7 @@ __device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, c
     }
   }
 #pragma unroll
-  for (int u = 0; u < U; ++u) push(want[u], item[u], beg[u], cnt[u], nxt, fcap, append, nn);
+  for (int u = 0; u < U; ++u) push(want[u], item[u], r2[u].x, r2[u].y, nxt, fcap, append, nn);
 }
 
 struct Shared {
@@ -788,11 +780,17 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
 
     // ---- per-query statistics --------------------------------------------------
     if (a.stats || (qs.status != EAT_OK && a.n_failed)) {
-      atomicAdd(&sh.acc[0], (unsigned long long)c.act);
-      atomicAdd(&sh.acc[1], (unsigned long long)c.tev);
-      atomicAdd(&sh.acc[2], (unsigned long long)c.hdr);
-      atomicAdd(&sh.acc[3], (unsigned long long)c.pool);
-      atomicAdd(&sh.acc[4], (unsigned long long)c.imp);
+      // wave sums first, then one LDS atomic per wave and counter
+      uint32_t v5[5] = {c.act, c.tev, c.hdr, c.pool, c.imp};
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) v5[k] += __shfl_xor(v5[k], d);
+      }
+      if (__lane_id() == 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) atomicAdd(&sh.acc[k], (unsigned long long)v5[k]);
+      }
       __syncthreads();
       if (tid == 0) {
         if (a.stats) {
@@ -835,7 +833,7 @@ __global__ void k_next_departure(const GraphDev *gd, const int32_t *ids, const i
     return;
   }
   Ctr c;
-  out[i] = next_departure<KIND>(G, G.ty[j], j, x, c);
+  out[i] = next_departure<KIND>(G, G.ty[2 * (int64_t)j], j, x, c);
 }
 
 using RelaxFn = void (*)(RunArgs);

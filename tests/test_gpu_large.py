@@ -1,0 +1,99 @@
+"""Parity at full size: the 500,000-stop region (about 120M connections, 64
+queries) and the mixed batch of eight cities (2k..500k stops, 4,096 queries in
+one launch).  The oracle's connection scan needs a global sort of all
+connections, so most answers are checked with the exact O(|C|) certificate
+(source, closure, witness), which the oracle tests pin against the scan; the
+small graphs of the mixed batch are checked against the scan itself."""
+import functools
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_00966_amd import eat, synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    eat.lib()
+
+
+def _say(m):
+    print(m, flush=True)
+
+
+@functools.lru_cache(maxsize=None)
+def _region():
+    t0 = time.time()
+    tt, q = synth.workload("region-500k")
+    _say(f"region-500k generated in {time.time() - t0:.0f}s: {tt.n_conn} connections")
+    g = eat.graph_from_timetable(tt)
+    return tt, q, g
+
+
+def _certify(tt, s, ts, arr):
+    return oracle.certify(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices, int(s), int(ts), arr)
+
+
+def test_region_500k_batch_certified():
+    tt, q, g = _region()
+    V = tt.n_vertices
+    slab = torch.full((len(q), V), -7, dtype=torch.int32, device="cuda")
+    b = eat.Batch([g], np.zeros(len(q), np.int32), q.s, q.ts, [slab[i] for i in range(len(q))])
+    b.run()
+    st = b.wait(stats=True)
+    got = slab.cpu().numpy()
+    assert all(x["status"] == 0 for x in st)
+    _say(f"region-500k: spilled {sum(x['spilled'] for x in st)} of {len(q)}, "
+         f"max reached {max(x['reached'] for x in st)}")
+    for i in range(len(q)):
+        assert (got[i] >= 0).all()
+        assert _certify(tt, q.s[i], q.ts[i], got[i]) == 0, i
+        assert st[i]["reached"] == int((got[i] < oracle.INF).sum())
+
+
+def test_region_500k_modes_agree():
+    """Frontier vs topology rounds, on-chip table vs slab, on sampled queries."""
+    tt, q, g = _region()
+    for i in (0, 7, 33):
+        ref = g.query(int(q.s[i]), int(q.ts[i])).cpu().numpy()
+        for opts in ({"mode": eat.EAT_MODE_TOPOLOGY}, {"table_cap": -1}, {"threads_per_vertex": 16}):
+            alt = g.query(int(q.s[i]), int(q.ts[i]), options=opts).cpu().numpy()
+            assert np.array_equal(ref, alt), (i, opts)
+        assert _certify(tt, q.s[i], q.ts[i], ref) == 0
+
+
+def test_mixed_batch_4096_queries_one_launch():
+    t0 = time.time()
+    graphs_tt, qsets = synth.mixed_batch()
+    _say(f"mixed batch generated in {time.time() - t0:.0f}s")
+    graphs = [eat.graph_from_timetable(t) for t in graphs_tt]
+    qg = np.concatenate([np.full(len(qs), i, np.int32) for i, qs in enumerate(qsets)])
+    qsrc = np.concatenate([qs.s for qs in qsets])
+    qts = np.concatenate([qs.ts for qs in qsets])
+    perm = np.random.default_rng(4).permutation(len(qg))  # interleave the graphs
+    qg, qsrc, qts = qg[perm], qsrc[perm], qts[perm]
+    outs = [torch.full((graphs[gi].n_vertices,), -7, dtype=torch.int32, device="cuda") for gi in qg]
+    st = eat.eat_query_batch(graphs, qg, qsrc, qts, outs, stats=True)
+    torch.cuda.synchronize()
+    assert len(st) == 4096 and all(x["status"] == 0 for x in st)
+    small = {gi: oracle.Csa(t.u, t.v, t.t, t.lam, t.n_vertices)
+             for gi, t in enumerate(graphs_tt) if t.n_vertices <= 10_000}
+    checked = {gi: 0 for gi in range(len(graphs))}
+    for k in range(len(qg)):
+        gi = int(qg[k])
+        if gi in small:
+            got = outs[k].cpu().numpy()
+            assert np.array_equal(got, small[gi].query(qsrc[k], qts[k])), (k, gi)
+            checked[gi] += 1
+        elif checked[gi] < 4:
+            got = outs[k].cpu().numpy()
+            assert _certify(graphs_tt[gi], qsrc[k], qts[k], got) == 0, (k, gi)
+            checked[gi] += 1
+    assert all(v >= 4 for v in checked.values())
