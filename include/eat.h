@@ -169,7 +169,9 @@ typedef struct {
   int32_t frontier_cap;       /* frontier list entries kept on chip; 0 = auto */
   int32_t table_cap;          /* on-chip arrival-table slots (power of two); 0 = auto,
                                  -1 = keep arrivals in the result slab (HBM) only */
-  int32_t reserved[3];        /* must be zero */
+  int32_t types_per_lane;     /* load-balanced expansion: connection types each lane
+                                 keeps in flight, 1..3; 0 = 2 */
+  int32_t reserved[2];        /* must be zero */
 } eat_run_options;
 
 typedef struct {

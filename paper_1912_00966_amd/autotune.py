@@ -1,0 +1,96 @@
+"""Autotuner for batched earliest-arrival-time launches.
+
+Runs a prepared batch under each candidate set of run options, times the
+launches with HIP events on the launch stream, checks that every candidate
+gives the same arrival arrays (the answer is unique, so any difference is a
+bug), and returns the fastest options.  Results are cached in a JSON file keyed
+by the graphs' shape, the batch size and the device name, so a later call
+with the same key returns at once.
+
+Knobs (all exact; they change only speed):
+  threads_per_vertex  0 = load-balanced expansion (one connection type per
+                      lane), or 8/16/32 lanes per active stop (virtual warps)
+  table_cap           0 = arrivals in the on-chip table (auto size), -1 = in
+                      the result slab (HBM)
+  mode                frontier-driven rounds, or a topology sweep every round
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import eat
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "eat_autotune.json")
+
+
+def candidates():
+    for tpv, table, mode in itertools.product((0, 8, 16, 32), (0, -1),
+                                              (eat.EAT_MODE_FRONTIER, eat.EAT_MODE_TOPOLOGY)):
+        yield {"threads_per_vertex": tpv, "table_cap": table, "mode": mode}
+
+
+def cache_key(graphs: Sequence[eat.Graph], n_queries: int) -> str:
+    import torch
+    shape = [(g.info.n_vertices, g.info.n_types, g.info.n_headers, g.info.n_conn, g.info.layout)
+             for g in graphs]
+    return json.dumps({"graphs": shape, "queries": int(n_queries),
+                       "device": torch.cuda.get_device_name()}, sort_keys=True)
+
+
+def tune(graphs: Sequence[eat.Graph], q_graph, q_src, q_ts, reps: int = 5,
+         cache_path: Optional[str] = DEFAULT_CACHE, cands=None, verbose: bool = False):
+    """Returns (best options dict, [(options, mean ms), ...])."""
+    import torch
+
+    key = cache_key(graphs, len(q_src))
+    if cache_path and os.path.exists(cache_path):
+        try:
+            cached = json.load(open(cache_path)).get(key)
+        except (OSError, ValueError):
+            cached = None
+        if cached:
+            return cached["best"], [(r["options"], r["ms"]) for r in cached["results"]]
+
+    n = len(q_src)
+    outs = [torch.empty(graphs[int(gi)].n_vertices, dtype=torch.int32, device="cuda") for gi in q_graph]
+    stream = torch.cuda.current_stream()
+    results = []
+    reference = None
+    for opts in (cands or candidates()):
+        b = eat.Batch(graphs, q_graph, q_src, q_ts, outs, options=opts)
+        b.run(stream)
+        b.wait()
+        got = [o.cpu().numpy() for o in outs] if reference is None else [o.cpu().numpy() for o in outs[::7]]
+        if reference is None:
+            reference = got
+        elif not all(np.array_equal(a, r) for a, r in zip(got, reference[::7])):
+            raise RuntimeError(f"autotune: options {opts} changed the answers")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            b.run(stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        b.free()
+        results.append((dict(opts), ms))
+        if verbose:
+            print(f"[autotune] {opts} {ms:.4f} ms", flush=True)
+    best = min(results, key=lambda r: r[1])[0]
+    if cache_path:
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        try:
+            data = json.load(open(cache_path)) if os.path.exists(cache_path) else {}
+        except (OSError, ValueError):
+            data = {}
+        data[key] = {"best": best, "results": [{"options": o, "ms": m} for o, m in results]}
+        tmp = cache_path + ".tmp"
+        json.dump(data, open(tmp, "w"), indent=1)
+        os.replace(tmp, cache_path)
+    return best, results

@@ -64,7 +64,7 @@ using eat::make_plan;
 struct eat_batch {
   int device = 0;
   int32_t n_q = 0;
-  int tpv = 0, kind = 0, grid = 0;
+  int tpv = 0, ub = 2, kind = 0, grid = 0;
   size_t lds = 0;
   RunArgs args{};
   void *d_buf = nullptr;
@@ -318,6 +318,9 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
     return set_err(EAT_ERR_INVALID_ARGUMENT, "table_cap must be 0, -1 or a power of two >= 64");
   // 0 = load-balanced expansion (one connection type per lane)
   pl->tpv = o.threads_per_vertex;
+  if (o.types_per_lane < 0 || o.types_per_lane > 3)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "types_per_lane must be 0..3");
+  pl->ub = o.types_per_lane ? o.types_per_lane : 2;
   pl->mode = o.mode;
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;
@@ -410,14 +413,14 @@ extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32
   if (!stats) {
     a.stats = nullptr;
     a.n_failed = nullptr;
-    hipError_t e = eat::launch_relax(a, pl.tpv, g->info.layout, 1, pl.lds, hs);
+    hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, g->info.layout, 1, pl.lds, hs);
     if (e != hipSuccess) return hip_err(e, "relaxation launch");
     return EAT_OK;
   }
   std::lock_guard<std::mutex> lk(gm->mu);
   a.stats = gm->d_stats;
   a.n_failed = nullptr;
-  hipError_t e = eat::launch_relax(a, pl.tpv, g->info.layout, 1, pl.lds, hs);
+  hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, g->info.layout, 1, pl.lds, hs);
   if (e != hipSuccess) return hip_err(e, "relaxation launch");
   HIP_TRY(hipMemcpyAsync(stats, gm->d_stats, sizeof(eat_query_stats), hipMemcpyDeviceToHost, hs));
   HIP_TRY(hipStreamSynchronize(hs));
@@ -478,6 +481,7 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   b->device = dev;
   b->n_q = n_q;
   b->tpv = pl.tpv;
+  b->ub = pl.ub;
   b->kind = kind;
   b->lds = pl.lds;
   const size_t b_g = align_up((size_t)n_graphs * sizeof(GraphDev));
@@ -508,7 +512,7 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
     delete b;
     return hip_err(e, "batch upload");
   }
-  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, kind, pl.lds));
+  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, pl.ub, kind, pl.lds));
   b->grid = std::max(1, std::min<int>(n_q, lim.cus * per_cu));
   RunArgs &a = b->args;
   a.graphs = d_g;
@@ -528,7 +532,7 @@ extern "C" eat_status eat_batch_run(eat_batch *b, void *stream) {
   if (!b) return set_err(EAT_ERR_INVALID_ARGUMENT, "batch is NULL");
   if (b->n_q == 0) return EAT_OK;
   hipStream_t hs = static_cast<hipStream_t>(stream);
-  hipError_t e = eat::launch_relax(b->args, b->tpv, b->kind, b->grid, b->lds, hs);
+  hipError_t e = eat::launch_relax(b->args, b->tpv, b->ub, b->kind, b->grid, b->lds, hs);
   if (e != hipSuccess) return hip_err(e, "relaxation launch");
   HIP_TRY(hipEventRecord(b->done, hs));
   b->ran = true;

@@ -69,12 +69,12 @@ constexpr int kMaxBuckets = 32;
 constexpr int kCounterWords = 4 + kMaxBuckets;
 
 // Host-side launchers (kernels.hip).
-hipError_t launch_relax(const RunArgs &a, int tpv, int kind, int grid, size_t lds_bytes,
+hipError_t launch_relax(const RunArgs &a, int tpv, int ub, int kind, int grid, size_t lds_bytes,
                         hipStream_t stream);
 hipError_t launch_zero(int32_t *p, int n, hipStream_t stream);
 hipError_t launch_next_departure(const GraphDev *g_dev, int kind, const int32_t *type_ids,
                                  const int32_t *x, int32_t *out, int32_t n, hipStream_t stream);
 // Work-groups of the relaxation kernel that fit on one CU with lds_bytes of LDS.
-int relax_blocks_per_cu(int tpv, int kind, size_t lds_bytes);
+int relax_blocks_per_cu(int tpv, int ub, int kind, size_t lds_bytes);
 
 }  // namespace eat

@@ -473,7 +473,7 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, Shared &sh, i
 //   the prefix sums.
 // TPV > 0: virtual warps (Section IV-B) -- groups of TPV lanes, one stop per
 //   group, lane i of a group takes the stop's types i, i + TPV, ...
-template <int TPV, int KIND, class Store>
+template <int TPV, int KIND, int U, class Store>
 __device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, const FList &cur, int32_t n,
                                             bool clear, const FList &nxt, int32_t fcap, bool append,
                                             int32_t *nn, Shared &sh, int32_t *poff, int32_t &scan_call,
@@ -502,7 +502,6 @@ __device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, c
     }
     __syncthreads();  // offsets and type ranges visible to every lane
     const int32_t total = carry;
-    constexpr int U = 2;
     for (int32_t k0 = threadIdx.x; k0 < total; k0 += kBlock * U) {
       int64_t jj[U];
       int32_t xx[U];
@@ -559,7 +558,7 @@ struct QState {
 // is list0 entry 0 with its bit set (frontier mode), or only its bit is set
 // (topology mode); every other bit is clear.  Returns false if the store
 // overflowed.
-template <int TPV, int KIND, class Store>
+template <int TPV, int KIND, int U, class Store>
 __device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, int32_t n_items,
                            const FList &list0, const FList &list1, int32_t *poff, bool topo,
                            int32_t max_rounds, Shared &sh, QState &qs, Ctr &c) {
@@ -583,7 +582,7 @@ __device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, 
     // the barrier that ended round rounds - 1: safe to reset for the next round
     if (tid == 0) sh.nn[(rounds + 1) % 3] = 0;
     if (!sweep) {
-      expand_list<TPV, KIND>(G, S, cur, nf, true, nxt, a.fcap, !topo, nn, sh, poff, scan_call, c);
+      expand_list<TPV, KIND, U>(G, S, cur, nf, true, nxt, a.fcap, !topo, nn, sh, poff, scan_call, c);
     } else {
       ++qs.sweeps;
       for (int32_t w0 = 0; w0 < nwords; w0 += chunk_words) {
@@ -606,7 +605,7 @@ __device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, 
         }
         __syncthreads();
         const int32_t cnt = sh.cnt;
-        if (cnt) expand_list<TPV, KIND>(G, S, cur, cnt, false, nxt, a.fcap, !topo, nn, sh, poff, scan_call, c);
+        if (cnt) expand_list<TPV, KIND, U>(G, S, cur, cnt, false, nxt, a.fcap, !topo, nn, sh, poff, scan_call, c);
         __syncthreads();
       }
     }
@@ -630,7 +629,7 @@ __device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, 
   return true;
 }
 
-template <int TPV, int KIND>
+template <int TPV, int KIND, int U>
 __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
   extern __shared__ uint32_t lds[];
   __shared__ Shared sh;
@@ -736,7 +735,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
         l0.cnt[0] = -1;
       }
       __syncthreads();
-      if (run_rounds<TPV, KIND>(a, G, T, H, l0, l1, poff, topo, max_rounds, sh, qs, c)) {
+      if (run_rounds<TPV, KIND, U>(a, G, T, H, l0, l1, poff, topo, max_rounds, sh, qs, c)) {
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the infinity fill has landed
         __syncthreads();
         for (int32_t p = tid; p < H; p += kBlock) {
@@ -771,7 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       }
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
-      run_rounds<TPV, KIND>(a, G, S, V, l0, l1, poff, topo, max_rounds, sh, qs, c);
+      run_rounds<TPV, KIND, U>(a, G, S, V, l0, l1, poff, topo, max_rounds, sh, qs, c);
       // reached stops
       int32_t mine = 0;
       for (int32_t i = tid; i < V; i += kBlock) mine += ld_arr(arr + i) != INF;
@@ -838,23 +837,25 @@ __global__ void k_next_departure(const GraphDev *gd, const int32_t *ids, const i
 
 using RelaxFn = void (*)(RunArgs);
 
+// TPV = 0: load-balanced expansion with ub connection types in flight per lane
+// (1..3); TPV > 0: virtual warps of TPV lanes.
 template <int KIND>
-RelaxFn relax_fn(int tpv) {
+RelaxFn relax_fn(int tpv, int ub) {
   switch (tpv) {
-    case 0: return k_relax<0, KIND>;
-    case 1: return k_relax<1, KIND>;
-    case 2: return k_relax<2, KIND>;
-    case 4: return k_relax<4, KIND>;
-    case 8: return k_relax<8, KIND>;
-    case 16: return k_relax<16, KIND>;
-    case 32: return k_relax<32, KIND>;
-    case 64: return k_relax<64, KIND>;
+    case 0: return ub == 1 ? k_relax<0, KIND, 1> : ub == 3 ? k_relax<0, KIND, 3> : k_relax<0, KIND, 2>;
+    case 1: return k_relax<1, KIND, 1>;
+    case 2: return k_relax<2, KIND, 1>;
+    case 4: return k_relax<4, KIND, 1>;
+    case 8: return k_relax<8, KIND, 1>;
+    case 16: return k_relax<16, KIND, 1>;
+    case 32: return k_relax<32, KIND, 1>;
+    case 64: return k_relax<64, KIND, 1>;
     default: return nullptr;
   }
 }
 
-RelaxFn pick(int tpv, int kind) {
-  return kind == EAT_LAYOUT_FLAT ? relax_fn<EAT_LAYOUT_FLAT>(tpv) : relax_fn<EAT_LAYOUT_HYBRID>(tpv);
+RelaxFn pick(int tpv, int ub, int kind) {
+  return kind == EAT_LAYOUT_FLAT ? relax_fn<EAT_LAYOUT_FLAT>(tpv, ub) : relax_fn<EAT_LAYOUT_HYBRID>(tpv, ub);
 }
 
 // Raises a kernel's dynamic-LDS limit when a launch needs more than any earlier
@@ -873,9 +874,9 @@ hipError_t allow_lds(RelaxFn f, size_t bytes) {
 
 }  // namespace
 
-hipError_t launch_relax(const RunArgs &a, int tpv, int kind, int grid, size_t lds_bytes,
+hipError_t launch_relax(const RunArgs &a, int tpv, int ub, int kind, int grid, size_t lds_bytes,
                         hipStream_t stream) {
-  RelaxFn f = pick(tpv, kind);
+  RelaxFn f = pick(tpv, ub, kind);
   if (!f) return hipErrorInvalidValue;
   hipError_t e = allow_lds(f, lds_bytes);
   if (e != hipSuccess) return e;
@@ -883,8 +884,8 @@ hipError_t launch_relax(const RunArgs &a, int tpv, int kind, int grid, size_t ld
   return hipGetLastError();
 }
 
-int relax_blocks_per_cu(int tpv, int kind, size_t lds_bytes) {
-  RelaxFn f = pick(tpv, kind);
+int relax_blocks_per_cu(int tpv, int ub, int kind, size_t lds_bytes) {
+  RelaxFn f = pick(tpv, ub, kind);
   if (!f) return 0;
   if (allow_lds(f, lds_bytes) != hipSuccess) return 0;
   int nb = 0;

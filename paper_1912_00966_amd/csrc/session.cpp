@@ -189,7 +189,7 @@ extern "C" eat_status eat_session_create(const eat_graph *const *graphs, int32_t
   S->graphs.assign(graphs, graphs + n_graphs);
   S->plan = pl;
   S->max_step = max_step;
-  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, kind, pl.lds));
+  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, pl.ub, kind, pl.lds));
   S->grid_cap = lim.cus * per_cu;
   S->n_buckets = std::min(lim.xccs, eat::kMaxBuckets);
   S->pool_words = pool_bytes / 4 / kSlotAlignWords * kSlotAlignWords;
@@ -311,7 +311,7 @@ extern "C" eat_status eat_session_step(eat_session *S, int32_t *n_launched) {
   a.stats = b.d_stats;
   a.n_failed = b.d_ctr + 1;
   const int grid = std::max(1, std::min(n, S->grid_cap));
-  hipError_t e = eat::launch_relax(a, S->plan.tpv, S->graphs[0]->info.layout, grid, S->plan.lds, b.stream);
+  hipError_t e = eat::launch_relax(a, S->plan.tpv, S->plan.ub, S->graphs[0]->info.layout, grid, S->plan.lds, b.stream);
   if (e != hipSuccess) return hip_err(e, "relaxation launch");
   HIP_TRY(hipMemcpyAsync(b.h_stats, b.d_stats, sizeof(eat_query_stats) * (size_t)n, hipMemcpyDeviceToHost,
                          b.stream));
