@@ -170,7 +170,7 @@ typedef struct {
   int32_t table_cap;          /* on-chip arrival-table slots (power of two); 0 = auto,
                                  -1 = keep arrivals in the result slab (HBM) only */
   int32_t types_per_lane;     /* load-balanced expansion: connection types each lane
-                                 keeps in flight, 1..3; 0 = 2 */
+                                 keeps in flight, 1..3; 0 = 1 */
   int32_t reserved[2];        /* must be zero */
 } eat_run_options;
 

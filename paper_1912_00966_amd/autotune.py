@@ -8,8 +8,10 @@ by the graphs' shape, the batch size and the device name, so a later call
 with the same key returns at once.
 
 Knobs (all exact; they change only speed):
-  threads_per_vertex  0 = load-balanced expansion (one connection type per
-                      lane), or 8/16/32 lanes per active stop (virtual warps)
+  threads_per_vertex  0 = load-balanced expansion, or 8/16/32 lanes per active
+                      stop (virtual warps)
+  types_per_lane      load-balanced expansion: connection types each lane keeps
+                      in flight (1..3)
   table_cap           0 = arrivals in the on-chip table (auto size), -1 = in
                       the result slab (HBM)
   mode                frontier-driven rounds, or a topology sweep every round
@@ -29,9 +31,11 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "eat_autotune.js
 
 
 def candidates():
-    for tpv, table, mode in itertools.product((0, 8, 16, 32), (0, -1),
-                                              (eat.EAT_MODE_FRONTIER, eat.EAT_MODE_TOPOLOGY)):
-        yield {"threads_per_vertex": tpv, "table_cap": table, "mode": mode}
+    for tpv, table in itertools.product((0, 8, 16, 32), (0, -1)):
+        for ub in ((1, 2, 3) if tpv == 0 else (0,)):
+            yield {"threads_per_vertex": tpv, "types_per_lane": ub, "table_cap": table,
+                   "mode": eat.EAT_MODE_FRONTIER}
+    yield {"mode": eat.EAT_MODE_TOPOLOGY}
 
 
 def cache_key(graphs: Sequence[eat.Graph], n_queries: int) -> str:

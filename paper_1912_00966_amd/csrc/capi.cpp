@@ -64,7 +64,7 @@ using eat::make_plan;
 struct eat_batch {
   int device = 0;
   int32_t n_q = 0;
-  int tpv = 0, ub = 2, kind = 0, grid = 0;
+  int tpv = 0, ub = 1, kind = 0, grid = 0;
   size_t lds = 0;
   RunArgs args{};
   void *d_buf = nullptr;
@@ -320,7 +320,7 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   pl->tpv = o.threads_per_vertex;
   if (o.types_per_lane < 0 || o.types_per_lane > 3)
     return set_err(EAT_ERR_INVALID_ARGUMENT, "types_per_lane must be 0..3");
-  pl->ub = o.types_per_lane ? o.types_per_lane : 2;
+  pl->ub = o.types_per_lane ? o.types_per_lane : 1;
   pl->mode = o.mode;
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;

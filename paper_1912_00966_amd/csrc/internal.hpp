@@ -48,7 +48,7 @@ eat_status device_limits(int dev, DeviceLimits *out);
 // Launch plan of the relaxation kernel for a set of graphs.
 struct Plan {
   int tpv = 0;
-  int ub = 2;  // connection types in flight per lane (load-balanced expansion)
+  int ub = 1;  // connection types in flight per lane (load-balanced expansion)
   int mode = EAT_MODE_AUTO;
   int max_rounds = 0;
   int fcap = 0;

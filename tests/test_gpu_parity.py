@@ -188,6 +188,9 @@ def test_repeated_runs_are_identical():
         for _ in range(5):
             again, _ = _query(g, s, ts, threads_per_vertex=tpv)
             assert np.array_equal(first, again)
+    for ub in (1, 2, 3):
+        again, _ = _query(g, s, ts, types_per_lane=ub)
+        assert np.array_equal(first, again)
 
 
 # ------------------------------------------------------------- batches
@@ -329,3 +332,19 @@ def test_invalid_query_arguments_leave_arr_untouched():
         eat.eat_query(g, 0, 0, out, options={"threads_per_vertex": 3})
     torch.cuda.synchronize()
     assert (out.cpu().numpy() == -7).all()
+
+
+def test_autotuner_picks_an_exact_configuration(tmp_path):
+    from paper_1912_00966_amd import autotune
+    tt, q = _workload("city-1k")
+    g = _graph("city-1k", "hybrid")
+    cands = [{"threads_per_vertex": 0, "types_per_lane": 1}, {"threads_per_vertex": 16},
+             {"table_cap": -1}, {"mode": eat.EAT_MODE_TOPOLOGY}]
+    cache = str(tmp_path / "tune.json")
+    best, results = autotune.tune([g], np.zeros(len(q), np.int32), q.s, q.ts, reps=2,
+                                  cache_path=cache, cands=cands)
+    assert best in cands and len(results) == len(cands)
+    best2, _ = autotune.tune([g], np.zeros(len(q), np.int32), q.s, q.ts, cache_path=cache, cands=cands)
+    assert best2 == best  # served from the cache
+    got, _ = _query(g, int(q.s[3]), int(q.ts[3]), **best)
+    assert np.array_equal(got, _expected("city-1k")[3])
