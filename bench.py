@@ -60,9 +60,10 @@ def profiled_traffic(path, kernel_source):
         return None
     fields = {}
     for line in open(path):
-        if ":" in line and line.strip().startswith(("traffic_bytes_per_launch", "kernel_source_sha256")):
+        line = line.strip().lstrip("-* ").strip()
+        if ":" in line and line.startswith(("traffic_bytes_per_launch", "kernel_source_sha256")):
             k, v = line.split(":", 1)
-            fields[k.strip().strip("`- ")] = v.strip().strip("` ")
+            fields[k.strip().strip("`")] = v.strip().strip("` ")
     digest = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
     if fields.get("kernel_source_sha256") != digest or "traffic_bytes_per_launch" not in fields:
         return None
