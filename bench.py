@@ -27,15 +27,16 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
 
-def algorithmic_bytes(stats, n_vertices, slab_only=False):
+def algorithmic_bytes(stats, n_vertices, slab_only=False, grid=False):
     """HBM bytes the relaxation must move per launch, from its operation counts.
 
     per query      : 4 * V (result slab written with infinity) + 4 * reached
                      (final arrival times scattered from the on-chip table)
     per activation : 8 (the stop's type range, vt_off[u] and vt_off[u+1])
     per type eval  : 16 (type record)
-    per header     : 8 (cluster header; a second one only when the next
-                     cluster is needed)
+    per header     : 8 (compact cluster header; a second one only when the
+                     next cluster is needed), or 12 (header-grid entry: the
+                     cluster's header and the next cluster's first departure)
     per pool word  : 4 (array-cluster chunks, flat departures)
     A query whose arrivals live in the slab (table overflow, or no table) also
     moves 4 (arr[u]) per activation, 4 (arr[v]) per type eval and 8 (atomic
@@ -44,12 +45,16 @@ def algorithmic_bytes(stats, n_vertices, slab_only=False):
     total = 0
     for st in stats:
         total += 4 * n_vertices + 8 * st["activations"] + 16 * st["type_evals"]
-        total += 8 * st["header_loads"] + 4 * st["pool_loads"]
+        total += (12 if grid else 8) * st["header_loads"] + 4 * st["pool_loads"]
         if slab_only or st["spilled"]:
             total += 4 * st["activations"] + 4 * st["type_evals"] + 8 * st["improvements"]
         else:
             total += 4 * st["reached"]
     return total
+
+
+MODES = {"auto": 0, "topology": 2}  # eat_mode values
+HEADERS = {"auto": 0, "grid": 1, "compact": 2}  # eat_headers values
 
 
 def profiled_traffic(path, kernel_source):
@@ -81,6 +86,10 @@ def main():
     ap.add_argument("--tpv", type=int, default=0, help="threads per active stop (0 = auto)")
     ap.add_argument("--table", type=int, default=0,
                     help="on-chip arrival-table slots (0 = auto, -1 = arrivals in HBM only)")
+    ap.add_argument("--mode", default="auto", choices=sorted(MODES),
+                    help="relaxation schedule: frontier rounds (auto) or topology sweeps")
+    ap.add_argument("--headers", default="auto", choices=sorted(HEADERS),
+                    help="hybrid layout on the device: header grid (auto when built) or compact headers")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-query comparison")
     ap.add_argument("--no-verify", action="store_true")
@@ -135,7 +144,9 @@ def main():
 
     V, Q = tt.n_vertices, len(q)
     slab = torch.empty((Q, V), dtype=torch.int32, device=dev)
-    opts = {"threads_per_vertex": args.tpv, "table_cap": args.table}
+    opts = {"threads_per_vertex": args.tpv, "table_cap": args.table, "mode": MODES[args.mode],
+            "headers": HEADERS[args.headers]}
+    grid = args.layout == "hybrid" and args.headers != "compact" and info.n_grid_entries > 0
     batch = eat.Batch([g], np.zeros(Q, np.int32), q.s, q.ts, [slab[i] for i in range(Q)], options=opts)
     stream = torch.cuda.current_stream()
 
@@ -184,10 +195,11 @@ def main():
             plain["bit_exact"] = bool(np.array_equal(slab.cpu().numpy(), exp))
 
     # ---- roofline of the relaxation kernel ---------------------------------------------
-    bytes_per_launch = algorithmic_bytes(stats, V, slab_only=args.table == -1)
+    bytes_per_launch = algorithmic_bytes(stats, V, slab_only=args.table == -1, grid=grid)
     achieved = bytes_per_launch / (kernel_ms / 1e3) / 1e9
     traffic = None
-    if args.workload == "city-50k" and args.layout == "hybrid" and args.table == 0:
+    if (args.workload == "city-50k" and args.layout == "hybrid" and args.table == 0 and args.mode == "auto"
+            and args.headers == "auto"):
         traffic = profiled_traffic(os.path.join(ROOT, "profiles", "k_relax_city-50k.md"),
                                    os.path.join(ROOT, "paper_1912_00966_amd", "csrc", "kernels.hip"))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -199,13 +211,22 @@ def main():
     cpu = None
     if not args.no_cpu:
         import oracle
+        from concurrent.futures import ThreadPoolExecutor
         c = oracle.Csa(tt.u, tt.v, tt.t, tt.lam, V)
         c0 = time.perf_counter()
         c.query_many(q.s, q.ts)
-        c_s = time.perf_counter() - c0
-        cpu = {"value": round(Q / c_s, 2), "unit": "queries/s", "cores": 1, "kind": "oracle",
-               "sample": f"all {Q} queries of the timed batch, connection scan, one thread "
-                         f"({os.cpu_count()} host cores visible)"}
+        one_s = time.perf_counter() - c0
+        # the same queries spread over the host cores this process may use (each
+        # query is one native call that releases the interpreter lock)
+        n_thr = max(1, min(len(os.sched_getaffinity(0)), 16))
+        with ThreadPoolExecutor(n_thr) as ex:
+            c0 = time.perf_counter()
+            list(ex.map(lambda i: c.query(q.s[i], q.ts[i]), range(Q)))
+            all_s = time.perf_counter() - c0
+        cpu = {"value": round(Q / all_s, 2), "unit": "queries/s", "cores": n_thr, "kind": "oracle",
+               "sample": f"all {Q} queries of the timed batch, connection scan, one query per "
+                         f"thread at a time over {n_thr} threads ({os.cpu_count()} host cores visible)",
+               "single_thread": round(Q / one_s, 2)}
 
     per_q = {k: float(np.mean([s[k] for s in stats])) for k in
              ("rounds", "activations", "type_evals", "header_loads", "pool_loads", "improvements",
@@ -227,6 +248,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload} ({args.reading} reading)", "stops": V,
                    "connections": tt.n_conn, "queries_per_step": Q, "layout": args.layout,
+                   "headers": ("grid" if grid else "compact") if args.layout == "hybrid" else None,
+                   "mode": args.mode,
                    "graphs": 1, "digest": tt.digest()},
         "bit_exact": bit_exact,
         "plain": plain,

@@ -63,7 +63,9 @@ typedef struct {
   int32_t layout;          /* eat_layout_kind; default EAT_LAYOUT_HYBRID */
   int32_t cluster_seconds; /* cluster width in seconds, 1..32767; 0 = 3600 (one hour) */
   int32_t n_threads;       /* host threads for preprocessing; 0 = all cores */
-  int32_t reserved[5];     /* must be zero */
+  int32_t header_grid;     /* hybrid layout on the device: 0 = also build the header
+                              grid (default), -1 = compact headers only (see below) */
+  int32_t reserved[4];     /* must be zero */
 } eat_build_options;
 
 typedef struct {
@@ -84,6 +86,7 @@ typedef struct {
   int64_t n_array_clusters;  /* ... stored as a sorted array */
   int64_t n_pool;            /* int32 words of the departure pool */
   int64_t device_bytes;      /* device memory held by the graph */
+  int64_t n_grid_entries;    /* header-grid entries on the device (0: no grid) */
 } eat_graph_info_t;
 
 /* ---------------------------------------------------------------------------
@@ -148,8 +151,23 @@ typedef struct eat_graph eat_graph;
 eat_status eat_graph_build(const int32_t *u, const int32_t *v, const int32_t *t,
                            const int32_t *lam, int64_t n_conn, int32_t n_vertices,
                            const eat_build_options *opt, eat_graph **out);
-/* Uploads an existing host layout (the layout may be freed afterwards). */
-eat_status eat_graph_upload(const eat_layout *layout, eat_graph **out);
+/* Uploads an existing host layout (the layout may be freed afterwards).  Of
+ * opt (nullable) only header_grid is used.
+ *
+ * Header grid (hybrid layout, device side).  Besides the compact headers, the
+ * device holds one 16-byte entry per (type, cluster) -- empty clusters
+ * included -- so that the entry a lookup needs has an address computable from
+ * the type index, the cluster index k = x / width and the tail stop's type
+ * range, without reading the type record first.  The entries of stop u (types
+ * b .. b+n-1) form one block ordered by cluster, then type:
+ *   grid[b * n_clusters + k * n + (j - b)] = {t0, c, next, 0}
+ * where {t0, c} is the cluster's header (same encoding as hdr below) and next
+ * is the type's first departure in a later cluster (EAT_INF if none).  An
+ * empty cluster holds {next, (1 << 16) | 1, next, 0}: a one-term progression
+ * at the next departure, which is the answer of Section II-D for any x inside
+ * that cluster.  Lanes that expand the types of one stop at one cluster read
+ * consecutive entries.  Costs 16 * n_types * n_clusters bytes of HBM. */
+eat_status eat_graph_upload(const eat_layout *layout, const eat_build_options *opt, eat_graph **out);
 void eat_graph_free(eat_graph *g); /* NULL-safe; waits for the device */
 eat_status eat_graph_info(const eat_graph *g, eat_graph_info_t *out);
 
@@ -162,6 +180,12 @@ typedef enum {
   EAT_MODE_TOPOLOGY = 2  /* every round sweeps the activity bitmap of all stops */
 } eat_mode;
 
+typedef enum {
+  EAT_HEADERS_AUTO = 0,    /* the header grid when every graph of the call has one */
+  EAT_HEADERS_GRID = 1,    /* the header grid; EAT_ERR_UNSUPPORTED if a graph has none */
+  EAT_HEADERS_COMPACT = 2  /* the compact headers (one per non-empty cluster) */
+} eat_headers;
+
 typedef struct {
   int32_t threads_per_vertex; /* lanes sharing one active stop's types: 1,2,4,..,64; 0 = auto */
   int32_t mode;               /* eat_mode */
@@ -171,7 +195,8 @@ typedef struct {
                                  -1 = keep arrivals in the result slab (HBM) only */
   int32_t types_per_lane;     /* load-balanced expansion: connection types each lane
                                  keeps in flight, 1..3; 0 = 1 */
-  int32_t reserved[2];        /* must be zero */
+  int32_t headers;            /* eat_headers: which form of the hybrid headers to read */
+  int32_t reserved[1];        /* must be zero */
 } eat_run_options;
 
 typedef struct {
@@ -281,9 +306,11 @@ void eat_session_free(eat_session *sess); /* NULL-safe; waits for the device */
  * ------------------------------------------------------------------------- */
 /* For each probe i: out[i] = the first departure >= x[i] of connection type
  * type_ids[i] (Section II-B), or EAT_INF, computed on the GPU by the same
- * device function the relaxation uses.  All three arrays are device arrays of
- * n int32.  Asynchronous on stream. */
-eat_status eat_next_departure(const eat_graph *g, const int32_t *type_ids,
+ * device function the relaxation uses, reading the header form `headers`
+ * (eat_headers; ignored for the flat layout).  All three arrays are device
+ * arrays of n int32 (type ids must lie in [0, n_types)).  Asynchronous on
+ * stream. */
+eat_status eat_next_departure(const eat_graph *g, int32_t headers, const int32_t *type_ids,
                               const int32_t *x, int32_t *out, int32_t n, void *stream);
 
 const char *eat_status_string(eat_status s);

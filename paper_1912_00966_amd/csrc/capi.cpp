@@ -169,9 +169,37 @@ extern "C" eat_status eat_layout_view_get(const eat_layout *L, eat_layout_view *
 // ---------------------------------------------------------------------------
 // device graph
 // ---------------------------------------------------------------------------
-extern "C" eat_status eat_graph_upload(const eat_layout *L, eat_graph **out) {
+namespace {
+
+// Device buffer sizes of one graph.
+struct GraphBytes {
+  size_t vt, ty, hdr, pool, side, tail, grid, desc, stats, total;
+};
+
+GraphBytes graph_bytes(const eat_layout &L, bool with_grid) {
+  const bool hybrid = L.kind == EAT_LAYOUT_HYBRID;
+  const size_t T = (size_t)std::max<int64_t>(L.n_types, 1);
+  GraphBytes b{};
+  b.vt = align_up(L.vt.size() * 4);
+  b.ty = align_up(T * 32);
+  b.hdr = hybrid ? align_up((size_t)(L.n_headers + 1) * 8) : 0;
+  b.pool = align_up(std::max<size_t>(L.pool.size(), 1) * 4);
+  b.side = with_grid ? align_up(T * 16) : 0;
+  b.tail = with_grid ? align_up(T * 4) : 0;
+  b.grid = with_grid ? align_up(T * (size_t)L.n_clusters * 16) : 0;
+  b.desc = align_up(sizeof(GraphDev));
+  b.stats = align_up(sizeof(eat_query_stats)) + align_up(4);
+  b.total = b.vt + b.ty + b.hdr + b.pool + b.side + b.tail + b.grid + b.desc + b.stats;
+  return b;
+}
+
+}  // namespace
+
+extern "C" eat_status eat_graph_upload(const eat_layout *L, const eat_build_options *opt, eat_graph **out) {
   if (!L || !out) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL argument");
   *out = nullptr;
+  const int32_t header_grid = opt ? opt->header_grid : 0;
+  if (header_grid != 0 && header_grid != -1) return set_err(EAT_ERR_INVALID_ARGUMENT, "header_grid must be 0 or -1");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
     return set_err(EAT_ERR_DEVICE, "no HIP device available");
@@ -185,29 +213,33 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, eat_graph **out) {
   const bool hybrid = L->kind == EAT_LAYOUT_HYBRID;
   const bool need_hi = hybrid && L->n_clusters > 32;
   const int64_t T = L->n_types;
-  const size_t b_vt = align_up(L->vt.size() * 4);
-  const size_t b_ty = align_up((size_t)std::max<int64_t>(T, 1) * 32);
-  const size_t b_hdr = hybrid ? align_up((size_t)(L->n_headers + 1) * 8) : 0;
-  const size_t b_pool = align_up(std::max<size_t>(L->pool.size(), 1) * 4);
-  const size_t b_desc = align_up(sizeof(GraphDev));
-  const size_t b_stats = align_up(sizeof(eat_query_stats)) + align_up(4);
-  const size_t total = b_vt + b_ty + b_hdr + b_pool + b_desc + b_stats;
-  hipError_t e = hipMalloc(&g->d_buf, total);
+  bool with_grid = hybrid && header_grid == 0 && T > 0;
+  GraphBytes b = graph_bytes(*L, with_grid);
+  hipError_t e = hipMalloc(&g->d_buf, b.total);
+  if (e != hipSuccess && with_grid) {  // the grid is an accelerator: go without it
+    (void)hipGetLastError();
+    with_grid = false;
+    b = graph_bytes(*L, false);
+    e = hipMalloc(&g->d_buf, b.total);
+  }
   if (e != hipSuccess) {
     delete g;
     return set_err(EAT_ERR_OUT_OF_MEMORY, std::string("hipMalloc of the graph failed: ") + hipGetErrorString(e));
   }
   char *p = static_cast<char *>(g->d_buf);
-  auto take = [&](size_t b) {
+  auto take = [&](size_t n) {
     char *q = p;
-    p += b;
+    p += n;
     return q;
   };
-  g->desc.vt = reinterpret_cast<const int2 *>(take(b_vt));
-  g->desc.ty = reinterpret_cast<const int4 *>(take(b_ty));
-  g->desc.hdr = hybrid ? reinterpret_cast<const int2 *>(take(b_hdr)) : nullptr;
-  g->desc.pool = reinterpret_cast<const int32_t *>(take(b_pool));
-  g->d_desc = reinterpret_cast<GraphDev *>(take(b_desc));
+  g->desc.vt = reinterpret_cast<const int2 *>(take(b.vt));
+  g->desc.ty = reinterpret_cast<const int4 *>(take(b.ty));
+  g->desc.hdr = hybrid ? reinterpret_cast<const int2 *>(take(b.hdr)) : nullptr;
+  g->desc.pool = reinterpret_cast<const int32_t *>(take(b.pool));
+  g->desc.side = with_grid ? reinterpret_cast<const int4 *>(take(b.side)) : nullptr;
+  g->desc.tail = with_grid ? reinterpret_cast<const int32_t *>(take(b.tail)) : nullptr;
+  g->desc.grid = with_grid ? reinterpret_cast<const int4 *>(take(b.grid)) : nullptr;
+  g->d_desc = reinterpret_cast<GraphDev *>(take(b.desc));
   g->d_stats = reinterpret_cast<eat_query_stats *>(take(align_up(sizeof(eat_query_stats))));
   g->d_failed = reinterpret_cast<int32_t *>(take(align_up(4)));
   g->desc.n_types = T;
@@ -215,7 +247,8 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, eat_graph **out) {
   g->desc.cluster_seconds = L->cluster_seconds;
   g->desc.n_clusters = L->n_clusters;
   g->desc.kind = L->kind;
-  g->info.device_bytes = (int64_t)total;
+  g->info.device_bytes = (int64_t)b.total;
+  g->info.n_grid_entries = with_grid ? T * (int64_t)L->n_clusters : 0;
 
   auto up = [&](const void *dst, const void *src, size_t bytes) -> hipError_t {
     if (bytes == 0) return hipSuccess;
@@ -224,9 +257,15 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, eat_graph **out) {
   hipError_t ue = hipSuccess;
   if (ue == hipSuccess) ue = up(g->desc.vt, L->vt.data(), L->vt.size() * 4);
   if (ue == hipSuccess && T > 0) {
-    std::vector<int32_t> ty2;
+    // 32-byte type records; with the grid also the 16-byte side records and
+    // the tail stop of every type
+    std::vector<int32_t> ty2, side, tail;
     try {
       ty2.resize((size_t)T * 8);
+      if (with_grid) {
+        side.resize((size_t)T * 4);
+        tail.resize((size_t)T);
+      }
     } catch (const std::bad_alloc &) {
       ue = hipErrorOutOfMemory;
     }
@@ -242,8 +281,22 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, eat_graph **out) {
         o[5] = L->vt[(size_t)2 * r[0] + 1];
         o[6] = need_hi ? (int32_t)L->mask_hi[(size_t)j] : 0;
         o[7] = 0;
+        if (with_grid) {
+          int32_t *sd = &side[(size_t)(4 * j)];
+          sd[0] = r[0];
+          sd[1] = r[1];
+          sd[2] = o[4];
+          sd[3] = o[5];
+        }
       }
+      if (with_grid)
+        for (int32_t u = 0; u < L->n_vertices; ++u) {
+          const int32_t b0 = L->vt[(size_t)2 * u], n = L->vt[(size_t)2 * u + 1];
+          for (int32_t j = b0; j < b0 + n; ++j) tail[(size_t)j] = u;
+        }
       ue = up(g->desc.ty, ty2.data(), (size_t)T * 32);
+      if (ue == hipSuccess && with_grid) ue = up(g->desc.side, side.data(), (size_t)T * 16);
+      if (ue == hipSuccess && with_grid) ue = up(g->desc.tail, tail.data(), (size_t)T * 4);
     }
   }
   if (ue == hipSuccess && hybrid) {
@@ -252,6 +305,7 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, eat_graph **out) {
   }
   if (ue == hipSuccess) ue = up(g->desc.pool, L->pool.data(), L->pool.size() * 4);
   if (ue == hipSuccess) ue = up(g->d_desc, &g->desc, sizeof(GraphDev));
+  if (ue == hipSuccess && with_grid) ue = eat::launch_build_grid(g->desc, nullptr);
   if (ue == hipSuccess) ue = hipDeviceSynchronize();
   if (ue != hipSuccess) {
     (void)hipFree(g->d_buf);
@@ -270,7 +324,7 @@ extern "C" eat_status eat_graph_build(const int32_t *u, const int32_t *v, const 
   eat_layout *L = nullptr;
   eat_status s = eat_layout_build(u, v, t, lam, n_conn, n_vertices, opt, &L);
   if (s != EAT_OK) return s;
-  s = eat_graph_upload(L, out);
+  s = eat_graph_upload(L, opt, out);
   eat_layout_free(L);
   return s;
 }
@@ -303,6 +357,26 @@ namespace eat {
 static size_t lists_lds(int fcap) { return (size_t)fcap * 28; }
 static size_t table_lds(int H, int fcap) { return (size_t)H * 8 + (size_t)(H / 32) * 4 + lists_lds(fcap); }
 
+eat_status exec_kind(const eat_graph *const *g, int32_t n, int headers, int *kind) {
+  if (headers < EAT_HEADERS_AUTO || headers > EAT_HEADERS_COMPACT)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "unknown header form");
+  const int layout = g[0]->info.layout;
+  bool all_grid = true;
+  for (int32_t i = 0; i < n; ++i) {
+    if (g[i]->info.layout != layout)
+      return set_err(EAT_ERR_UNSUPPORTED, "all graphs of one call must share a layout kind");
+    all_grid = all_grid && g[i]->desc.grid != nullptr;
+  }
+  if (layout == EAT_LAYOUT_FLAT) {
+    *kind = kKindFlat;
+    return EAT_OK;
+  }
+  if (headers == EAT_HEADERS_GRID && !all_grid)
+    return set_err(EAT_ERR_UNSUPPORTED, "the header grid was requested but a graph was built without one");
+  *kind = (headers != EAT_HEADERS_COMPACT && all_grid) ? kKindGrid : kKindCompact;
+  return EAT_OK;
+}
+
 eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan *pl) {
   eat_run_options o{};
   if (ro) o = *ro;
@@ -322,6 +396,9 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
     return set_err(EAT_ERR_INVALID_ARGUMENT, "types_per_lane must be 0..3");
   pl->ub = o.types_per_lane ? o.types_per_lane : 1;
   pl->mode = o.mode;
+  if (o.headers < EAT_HEADERS_AUTO || o.headers > EAT_HEADERS_COMPACT)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "unknown header form");
+  pl->headers = o.headers;
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;
   int fcap = o.frontier_cap ? o.frontier_cap : 1024;
@@ -340,16 +417,16 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   const int items = std::max(32, (std::max(max_v, H) + 31) / 32 * 32);
   fcap = std::min(fcap, items);
   const size_t slab_lds = (size_t)pl->bm_words * 4 + lists_lds(fcap);
-  while (table_auto && H >= 64 && std::max(table_lds(H, fcap), slab_lds) > lim.lds) H >>= 1;
+  auto need = [&](int h) { return std::max(table_lds(h, fcap), slab_lds); };
+  while (table_auto && H >= 64 && need(H) > lim.lds) H >>= 1;
   if (H < 64) H = 0;
-  if (H && std::max(table_lds(H, fcap), slab_lds) > lim.lds)
-    return set_err(EAT_ERR_UNSUPPORTED, "table_cap too large for the device's LDS");
+  if (H && need(H) > lim.lds) return set_err(EAT_ERR_UNSUPPORTED, "table_cap too large for the device's LDS");
   pl->table_cap = H;
   pl->ns_per_tick = lim.ns_per_tick;
   pl->table_bits = 0;
   while (H && (1 << pl->table_bits) < H) ++pl->table_bits;
   pl->fcap = fcap;
-  pl->lds = std::max(H ? table_lds(H, fcap) : 0, slab_lds);
+  pl->lds = H ? need(H) : slab_lds;
   if (pl->lds > lim.lds)
     return set_err(EAT_ERR_UNSUPPORTED, "graph too large for the on-chip activity bitmap (" +
                                             std::to_string(pl->lds) + " bytes of LDS needed, " +
@@ -399,6 +476,9 @@ extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32
   Plan pl;
   eat_status st = make_plan(ro, g->info.n_vertices, g->device, &pl);
   if (st != EAT_OK) return st;
+  int kind = 0;
+  st = eat::exec_kind(&g, 1, pl.headers, &kind);
+  if (st != EAT_OK) return st;
   RunArgs a{};
   a.graphs = g->d_desc;
   a.queries = nullptr;
@@ -413,14 +493,14 @@ extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32
   if (!stats) {
     a.stats = nullptr;
     a.n_failed = nullptr;
-    hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, g->info.layout, 1, pl.lds, hs);
+    hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, kind, 1, pl.lds, hs);
     if (e != hipSuccess) return hip_err(e, "relaxation launch");
     return EAT_OK;
   }
   std::lock_guard<std::mutex> lk(gm->mu);
   a.stats = gm->d_stats;
   a.n_failed = nullptr;
-  hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, g->info.layout, 1, pl.lds, hs);
+  hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, kind, 1, pl.lds, hs);
   if (e != hipSuccess) return hip_err(e, "relaxation launch");
   HIP_TRY(hipMemcpyAsync(stats, gm->d_stats, sizeof(eat_query_stats), hipMemcpyDeviceToHost, hs));
   HIP_TRY(hipStreamSynchronize(hs));
@@ -443,15 +523,11 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
     return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL query array");
   int dev = -1;
   HIP_TRY(hipGetDevice(&dev));
-  int kind = -1;
   int32_t max_v = 1;
   for (int32_t i = 0; i < n_graphs; ++i) {
     if (!graphs[i]) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph " + std::to_string(i) + " is NULL");
     if (graphs[i]->device != dev)
       return set_err(EAT_ERR_INVALID_ARGUMENT, "graph " + std::to_string(i) + " lives on another device");
-    if (kind < 0) kind = graphs[i]->info.layout;
-    if (graphs[i]->info.layout != kind)
-      return set_err(EAT_ERR_UNSUPPORTED, "all graphs of one batch must share a layout kind");
   }
   std::vector<QueryDev> qs((size_t)n_q);
   for (int32_t i = 0; i < n_q; ++i) {
@@ -467,6 +543,9 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   }
   Plan pl;
   eat_status st = make_plan(ro, max_v, dev, &pl);
+  if (st != EAT_OK) return st;
+  int kind = 0;
+  st = eat::exec_kind(graphs, n_graphs, pl.headers, &kind);
   if (st != EAT_OK) return st;
   DeviceLimits lim;
   st = device_limits(dev, &lim);
@@ -581,12 +660,15 @@ extern "C" eat_status eat_query_batch(const eat_graph *const *graphs, int32_t n_
 // ---------------------------------------------------------------------------
 // diagnostics
 // ---------------------------------------------------------------------------
-extern "C" eat_status eat_next_departure(const eat_graph *g, const int32_t *type_ids, const int32_t *x,
-                                         int32_t *out, int32_t n, void *stream) {
+extern "C" eat_status eat_next_departure(const eat_graph *g, int32_t headers, const int32_t *type_ids,
+                                         const int32_t *x, int32_t *out, int32_t n, void *stream) {
   if (!g) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph is NULL");
   if (n < 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "n must be >= 0");
   if (n > 0 && (!type_ids || !x || !out)) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL array");
-  hipError_t e = eat::launch_next_departure(g->d_desc, g->info.layout, type_ids, x, out, n,
+  int kind = 0;
+  const eat_status st = eat::exec_kind(&g, 1, headers, &kind);
+  if (st != EAT_OK) return st;
+  hipError_t e = eat::launch_next_departure(g->d_desc, kind, type_ids, x, out, n,
                                             static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_err(e, "next-departure launch");
   return EAT_OK;

@@ -18,6 +18,14 @@ struct GraphDev {
   const int4 *ty;
   const int2 *hdr;         // [K + 1] hybrid (one padding entry)
   const int32_t *pool;     // departures
+  // Hybrid header grid (nullptr when not built): side[T] per type
+  // {v, lam, first type of v, type count of v}; grid[T * n_clusters] entries
+  // {t0, c, next, 0} of every (type, cluster), stop-blocked and cluster-major
+  // (the layout is spelled out at eat_graph_upload in eat.h); tail[T] the
+  // tail stop of each type (diagnostics only).
+  const int4 *side;
+  const int4 *grid;
+  const int32_t *tail;
   int64_t n_types;
   int32_t n_vertices;
   int32_t cluster_seconds;
@@ -25,6 +33,12 @@ struct GraphDev {
   int32_t kind;            // eat_layout_kind
   int32_t pad_;
 };
+
+// Kernel variants by the timetable form they read: the hybrid layout's
+// compact headers, the flat layout, the hybrid layout's header grid.
+constexpr int kKindCompact = EAT_LAYOUT_HYBRID;
+constexpr int kKindFlat = EAT_LAYOUT_FLAT;
+constexpr int kKindGrid = 2;
 
 // One query: the graph index, the source, the departure time, the caller's
 // result slab, and the query's index in the caller's order (for its stats).
@@ -74,6 +88,8 @@ hipError_t launch_relax(const RunArgs &a, int tpv, int ub, int kind, int grid, s
 hipError_t launch_zero(int32_t *p, int n, hipStream_t stream);
 hipError_t launch_next_departure(const GraphDev *g_dev, int kind, const int32_t *type_ids,
                                  const int32_t *x, int32_t *out, int32_t n, hipStream_t stream);
+// Fills g.grid from the compact headers (g as on the host: device pointers).
+hipError_t launch_build_grid(const GraphDev &g, hipStream_t stream);
 // Work-groups of the relaxation kernel that fit on one CU with lds_bytes of LDS.
 int relax_blocks_per_cu(int tpv, int ub, int kind, size_t lds_bytes);
 

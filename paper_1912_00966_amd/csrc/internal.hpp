@@ -55,9 +55,14 @@ struct Plan {
   int bm_words = 0;
   int table_cap = 0;
   int table_bits = 0;
+  int headers = EAT_HEADERS_AUTO;
   int64_t ns_per_tick = 0;
   size_t lds = 0;
 };
+
+// Kernel variant (kKindCompact / kKindFlat / kKindGrid) for graphs g[0..n)
+// and a requested eat_headers form; all graphs must share one layout kind.
+eat_status exec_kind(const eat_graph *const *g, int32_t n, int headers, int *kind);
 // max_v: the largest graph the kernel will see.
 eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan *pl);
 // RunArgs fields that come from a plan.

@@ -32,8 +32,9 @@
 // value read after that improvement.
 #include <hip/hip_runtime.h>
 
-#include <mutex>
+#include <algorithm>
 #include <map>
+#include <mutex>
 
 #include "device.hpp"
 
@@ -89,14 +90,31 @@ __device__ __forceinline__ int32_t first_at_or_after(const int32_t *d, int32_t n
 // which is the next header because only non-empty clusters have one.  The
 // next header is fetched together with the first; arrays of <= 7 departures
 // (the common case) are read as two independent 16-byte chunks.
+//
+// Header grid (hybrid layout): the entry of (type j, cluster k) sits at an
+// address computed from j, k and the tail stop's type range [b, b + n), so it
+// is read at the same time as the type's record instead of after it.  Empty
+// clusters hold the next departure as a one-term progression, and every entry
+// carries the next cluster's first departure: one read answers the lookup,
+// except inside an array cluster (one more read of its departures).
 struct Look {
   int32_t idx;    // header index (hybrid)
   int32_t mode;   // 0: no departure >= x; 1: the first departure of header idx; 2: search in header idx
   bool has_next;  // another non-empty cluster follows cluster idx
   int2 h, hn;     // header idx and idx + 1 (hybrid)
+  int64_t gidx;   // grid entry index (grid)
+  int4 e;         // grid entry {t0, c, next, 0}
   int4 c0, c1;    // first chunks of an array cluster (hybrid) or departures 0..7 (flat)
   int4 c2, c3;    // departures 8..15 (flat)
 };
+
+// Grid: entry of type j (tail stop's types [b, b + n)) in the cluster of x.
+__device__ __forceinline__ void look_locate_grid(const GraphDev &G, int64_t j, int32_t b, int32_t n, int32_t x,
+                                                 Look &L) {
+  const uint32_t k = (uint32_t)x / (uint32_t)G.cluster_seconds;
+  L.mode = k < (uint32_t)G.n_clusters ? 2 : 0;  // else: after the last departure of the timetable
+  L.gidx = (int64_t)b * G.n_clusters + (int64_t)k * n + (j - b);
+}
 
 template <int KIND>
 __device__ __forceinline__ void look_locate(const GraphDev &G, const int4 r, uint32_t mhi, int32_t x, Look &L) {
@@ -112,7 +130,7 @@ __device__ __forceinline__ void look_locate(const GraphDev &G, const int4 r, uin
     L.idx = r.z + __popcll(m & ((1ull << k) - 1ull));
     L.mode = (ahead & 1ull) ? 2 : 1;
     L.has_next = (ahead >> 1) != 0;
-  } else {
+  } else if constexpr (KIND == EAT_LAYOUT_FLAT) {
     L.mode = r.w > 0 ? 2 : 0;
   }
 }
@@ -124,6 +142,8 @@ __device__ __forceinline__ void look_fetch_headers(const GraphDev &G, const int4
     // header idx + 1 exists: the header array carries one padding entry
     L.h = G.hdr[L.idx];
     L.hn = G.hdr[L.idx + 1];
+  } else if constexpr (KIND == kKindGrid) {
+    if (L.mode != 0) L.e = G.grid[L.gidx];
   } else {
     if (L.mode != 0 && r.w <= 16) {
       const int4 *p4 = reinterpret_cast<const int4 *>(G.pool + r.z);
@@ -145,7 +165,36 @@ __device__ __forceinline__ void look_fetch_chunks(const GraphDev &G, int32_t x, 
       L.c1 = p4[1];
       c.pool += 8;
     }
+  } else if constexpr (KIND == kKindGrid) {
+    if (L.mode == 2 && L.e.y < 0 && x > L.e.x) {
+      const int4 *p4 = reinterpret_cast<const int4 *>(G.pool + (~L.e.y));
+      L.c0 = p4[0];
+      L.c1 = p4[1];
+      c.pool += 8;
+    }
   }
+}
+
+// First departure >= x of the array cluster at pool[off] (pool[off] = n, then
+// n sorted departures, the first < x); L.c0, L.c1 hold its first 8 words.
+__device__ __forceinline__ int32_t array_next(const GraphDev &G, int32_t off, int32_t x, const Look &L, Ctr &c) {
+  const int32_t n = L.c0.x;
+  int32_t t = INF;
+  if (n <= 7) {
+    const int32_t d7[7] = {L.c0.y, L.c0.z, L.c0.w, L.c1.x, L.c1.y, L.c1.z, L.c1.w};
+#pragma unroll
+    for (int i = 0; i < 7; ++i) t = (i < n && d7[i] >= x && d7[i] < t) ? d7[i] : t;
+  } else {
+    const int32_t *p = G.pool + off;
+    int32_t lo = 2, hi = n + 1;
+    while (lo < hi) {
+      const int32_t mid = (lo + hi) >> 1;
+      c.pool++;
+      if (p[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    if (lo <= n) t = p[lo];
+  }
+  return t;
 }
 
 template <int KIND>
@@ -159,27 +208,26 @@ __device__ __forceinline__ int32_t look_finish(const GraphDev &G, const int4 r, 
       const int32_t i = (x - h.x - 1) / d + 1;  // ceil((x - t0) / d), x > t0
       if (i < n) return h.x + i * d;
     } else {  // sorted array p[1..n], p[0] = n, p[1] = t0 < x
-      const int32_t n = L.c0.x;
-      int32_t t = INF;
-      if (n <= 7) {
-        const int32_t d7[7] = {L.c0.y, L.c0.z, L.c0.w, L.c1.x, L.c1.y, L.c1.z, L.c1.w};
-#pragma unroll
-        for (int i = 0; i < 7; ++i) t = (i < n && d7[i] >= x && d7[i] < t) ? d7[i] : t;
-      } else {
-        const int32_t *p = G.pool + (~h.y);
-        int32_t lo = 2, hi = n + 1;
-        while (lo < hi) {
-          const int32_t mid = (lo + hi) >> 1;
-          c.pool++;
-          if (p[mid] < x) lo = mid + 1; else hi = mid;
-        }
-        if (lo <= n) t = p[lo];
-      }
+      const int32_t t = array_next(G, ~h.y, x, L, c);
       if (t != INF) return t;
     }
     if (!L.has_next) return INF;
     c.hdr++;
     return L.hn.x;
+  } else if constexpr (KIND == kKindGrid) {
+    const int4 e = L.e;
+    if (x <= e.x) return e.x;  // also every empty cluster: e.x is the next departure
+    if (e.y >= 0) {            // one progression t0 + i*d, i < n
+      const int32_t d = e.y & 0xffff, n = e.y >> 16;
+      if (n > 1) {
+        const int32_t i = (x - e.x - 1) / d + 1;  // ceil((x - t0) / d), x > t0
+        if (i < n) return e.x + i * d;
+      }
+    } else {
+      const int32_t t = array_next(G, ~e.y, x, L, c);
+      if (t != INF) return t;
+    }
+    return e.z;  // first departure of a later cluster
   } else {
     const int32_t n = r.w;
     if (n <= 16) {
@@ -207,16 +255,25 @@ __device__ __forceinline__ int32_t look_finish(const GraphDev &G, const int4 r, 
 template <int KIND>
 __device__ __forceinline__ void count_fetch(const int4 r, const Look &L, Ctr &c) {
   if constexpr (KIND == EAT_LAYOUT_HYBRID) c.hdr += 1;  // +1 more if the next cluster is needed
+  else if constexpr (KIND == kKindGrid) c.hdr += 1;    // one grid entry
   else if (L.mode != 0 && r.w <= 16) c.pool += 16;
 }
 
 // Next departure of connection type j at or after x (Section II-B:
-// t_c = min{t in C_{u,v,lam} : t >= x}); INF when there is none.
+// t_c = min{t in C_{u,v,lam} : t >= x}); INF when there is none.  [b, b + n)
+// is the type range of j's tail stop (read by the grid form only).
 template <int KIND>
-__device__ __forceinline__ int32_t next_departure(const GraphDev &G, const int4 r, int64_t j, int32_t x, Ctr &c) {
+__device__ __forceinline__ int32_t next_departure(const GraphDev &G, int64_t j, int32_t b, int32_t n, int32_t x,
+                                                  Ctr &c) {
   Look L;
-  const uint32_t mhi = (KIND == EAT_LAYOUT_HYBRID && G.n_clusters > 32) ? (uint32_t)G.ty[2 * j + 1].z : 0u;
-  look_locate<KIND>(G, r, mhi, x, L);
+  int4 r = make_int4(0, 0, 0, 0);
+  if constexpr (KIND == kKindGrid) {
+    look_locate_grid(G, j, b, n, x, L);
+  } else {
+    r = G.ty[2 * j];
+    const uint32_t mhi = (KIND == EAT_LAYOUT_HYBRID && G.n_clusters > 32) ? (uint32_t)G.ty[2 * j + 1].z : 0u;
+    look_locate<KIND>(G, r, mhi, x, L);
+  }
   if (L.mode == 0) return INF;
   look_fetch_headers<KIND>(G, r, L);
   count_fetch<KIND>(r, L, c);
@@ -255,6 +312,17 @@ __device__ __forceinline__ void push(bool want, int32_t item, int32_t beg, int32
     }
   }
 }
+
+// Pushes into the next round's list (bulk-synchronous rounds).
+struct ListPush {
+  FList nxt;
+  int32_t fcap;
+  bool append;
+  int32_t *nn;
+  __device__ __forceinline__ void operator()(bool want, int32_t item, int32_t beg, int32_t cnt) const {
+    push(want, item, beg, cnt, nxt, fcap, append, nn);
+  }
+};
 
 __device__ __forceinline__ int32_t lds_ld(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -335,59 +403,38 @@ __device__ __forceinline__ bool mark_improved(const Store &S, int32_t it) {
   return !(atomicOr(&S.bits[it >> 5], bit) & bit);
 }
 
-// Relax (Algorithm 3) the best connection of type j for a tail reached at x.
-template <int KIND, class Store>
-__device__ __forceinline__ void relax(const GraphDev &G, const Store &S, int64_t j, int32_t x,
-                                      const FList &nxt, int32_t fcap, bool append, int32_t *nn, Ctr &c) {
-  const int4 r = G.ty[2 * j];
-  const int4 r2 = G.ty[2 * j + 1];
-  const int32_t v = r.x, lam = r.y;
-  c.tev++;
-  const int32_t av = S.find(v);
-  bool want = false;
-  int32_t item = 0;
-  // Any departure of this type leaves at t_c >= x, so it arrives at >= x + lam:
-  // skip the lookup when that cannot beat arr[v] (early termination, Section
-  // III-D, in its strongest exact form).
-  if (x < av - lam) {
-    const int32_t tc = next_departure<KIND>(G, r, j, x, c);
-    if (tc != INF) {
-      const int32_t cand = tc + lam;
-      if (cand < av) {
-        item = S.slot(v);
-        if (item >= 0) {
-          const int32_t old = S.lower(item, cand);
-          if (cand < old) {
-            c.imp++;
-            want = mark_improved(S, item);
-          }
-        }
-      }
-    }
-  }
-  push(want, item, r2.x, r2.y, nxt, fcap, append, nn);
-}
-
-// Relax U connection types per lane with their memory reads overlapped: all
-// type records, then all (speculative) cluster headers, then the on-chip
-// arrival lookups, then the rare array chunks, then the updates.
-template <int KIND, int U, class Store>
+// Relax (Algorithm 3) U connection types per lane, with their memory reads
+// overlapped: all type records (and, for the grid, the grid entries, whose
+// addresses need no record), then the (speculative) cluster headers, then the
+// on-chip arrival lookups, then the rare array chunks, then the updates.
+// Lane type u: j[u] of a tail stop with types [tb[u], tb[u] + tn[u]) reached
+// at x[u]; ok[u] false = no type.
+template <int KIND, int U, class Store, class Push>
 __device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, const int64_t *j,
-                                            const int32_t *x, const bool *ok, const FList &nxt, int32_t fcap,
-                                            bool append, int32_t *nn, Ctr &c) {
+                                            const int32_t *tb, const int32_t *tn, const int32_t *x,
+                                            const bool *ok, const Push &P, Ctr &c) {
   int4 r[U], r2[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int64_t jj = ok[u] ? j[u] : 0;  // type 0 always exists when any item does
-    r[u] = G.ty[2 * jj];
-    r2[u] = G.ty[2 * jj + 1];
-  }
   Look L[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    look_locate<KIND>(G, r[u], KIND == EAT_LAYOUT_HYBRID ? (uint32_t)r2[u].z : 0u, x[u], L[u]);
-    if (!ok[u]) L[u].mode = 0;
-    look_fetch_headers<KIND>(G, r[u], L[u]);
+    const int64_t jj = ok[u] ? j[u] : 0;  // type 0 always exists when any item does
+    if constexpr (KIND == kKindGrid) {
+      r[u] = G.side[jj];  // {v, lam, first type of v, type count of v}
+      look_locate_grid(G, jj, tb[u], tn[u], x[u], L[u]);
+      if (!ok[u]) L[u].mode = 0;
+      look_fetch_headers<KIND>(G, r[u], L[u]);
+    } else {
+      r[u] = G.ty[2 * jj];
+      r2[u] = G.ty[2 * jj + 1];
+    }
+  }
+  if constexpr (KIND != kKindGrid) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      look_locate<KIND>(G, r[u], KIND == EAT_LAYOUT_HYBRID ? (uint32_t)r2[u].z : 0u, x[u], L[u]);
+      if (!ok[u]) L[u].mode = 0;
+      look_fetch_headers<KIND>(G, r[u], L[u]);
+    }
   }
   int32_t av[U];
   bool live[U];
@@ -428,7 +475,18 @@ __device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, c
     }
   }
 #pragma unroll
-  for (int u = 0; u < U; ++u) push(want[u], item[u], r2[u].x, r2[u].y, nxt, fcap, append, nn);
+  for (int u = 0; u < U; ++u) {
+    if constexpr (KIND == kKindGrid) P(want[u], item[u], r[u].z, r[u].w);
+    else P(want[u], item[u], r2[u].x, r2[u].y);
+  }
+}
+
+// One connection type per lane.
+template <int KIND, class Store, class Push>
+__device__ __forceinline__ void relax(const GraphDev &G, const Store &S, int64_t j, int32_t b, int32_t n, int32_t x,
+                                      const Push &P, Ctr &c) {
+  const bool ok = true;
+  relax_batch<KIND, 1>(G, S, &j, &b, &n, &x, &ok, P, c);
 }
 
 struct Shared {
@@ -492,6 +550,7 @@ __device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, c
           const int2 r = G.vt[u];
           d = r.y;
           cur.beg[e] = r.x;
+          cur.cnt[e] = r.y;
         }
         c.act++;
       }
@@ -504,7 +563,7 @@ __device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, c
     const int32_t total = carry;
     for (int32_t k0 = threadIdx.x; k0 < total; k0 += kBlock * U) {
       int64_t jj[U];
-      int32_t xx[U];
+      int32_t tb[U], tn[U], xx[U];
       bool ok[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -516,10 +575,12 @@ __device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, c
           if (poff[mid] <= k) lo = mid + 1; else hi = mid;
         }
         const int32_t i = ok[u] ? lo - 1 : 0;
-        jj[u] = ok[u] ? (int64_t)cur.beg[i] + (k - poff[i]) : 0;
+        tb[u] = ok[u] ? cur.beg[i] : 0;
+        tn[u] = ok[u] ? cur.cnt[i] : 0;
+        jj[u] = ok[u] ? (int64_t)tb[u] + (k - poff[i]) : 0;
         xx[u] = ok[u] ? S.value(cur.item[i]) : 0;
       }
-      relax_batch<KIND, U>(G, S, jj, xx, ok, nxt, fcap, append, nn, c);
+      relax_batch<KIND, U>(G, S, jj, tb, tn, xx, ok, ListPush{nxt, fcap, append, nn}, c);
     }
   } else {
     constexpr int kGroups = kBlock / TPV;
@@ -541,9 +602,10 @@ __device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, c
       if (i < n) {
         const int32_t item = cur.item[i];
         const int32_t x = S.value(item);
-        const int32_t b = cur.beg[i], e = b + cur.cnt[i];
+        const int32_t b = cur.beg[i], cn = cur.cnt[i], e = b + cn;
         if (lane == 0) c.act++;
-        for (int32_t j = b + lane; j < e; j += TPV) relax<KIND>(G, S, j, x, nxt, fcap, append, nn, c);
+        const ListPush P{nxt, fcap, append, nn};
+        for (int32_t j = b + lane; j < e; j += TPV) relax<KIND>(G, S, j, b, cn, x, P, c);
       }
     }
   }
@@ -631,7 +693,7 @@ __device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, 
 
 template <int TPV, int KIND, int U>
 __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   __shared__ Shared sh;
 
   const int tid = threadIdx.x;
@@ -831,8 +893,41 @@ __global__ void k_next_departure(const GraphDev *gd, const int32_t *ids, const i
     out[i] = -1;
     return;
   }
+  int32_t b = 0, cnt = 0;
+  if constexpr (KIND == kKindGrid) {
+    const int2 r = G.vt[G.tail[j]];
+    b = r.x;
+    cnt = r.y;
+  }
   Ctr c;
-  out[i] = next_departure<KIND>(G, G.ty[2 * (int64_t)j], j, x, c);
+  out[i] = next_departure<KIND>(G, j, b, cnt, x, c);
+}
+
+// One thread per connection type: writes the type's n_clusters grid entries
+// from its compact headers, from the last cluster down, carrying the first
+// departure of the clusters after the current one.
+__global__ void k_build_grid(GraphDev G) {
+  int4 *grid = const_cast<int4 *>(G.grid);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < G.n_types; j += stride) {
+    const int4 r = G.ty[2 * j], r2 = G.ty[2 * j + 1];
+    const uint64_t m = (uint64_t)(uint32_t)r.w | ((uint64_t)(uint32_t)r2.z << 32);
+    const int2 rng = G.vt[G.tail[j]];
+    const int64_t base = (int64_t)rng.x * G.n_clusters + (j - rng.x);
+    int32_t idx = r.z + __popcll(m) - 1;  // header of the last non-empty cluster
+    int32_t next = INF;
+    for (int32_t k = G.n_clusters - 1; k >= 0; --k) {
+      int4 e;
+      if ((m >> k) & 1ull) {
+        const int2 h = G.hdr[idx--];
+        e = make_int4(h.x, h.y, next, 0);
+        next = h.x;
+      } else {
+        e = make_int4(next, (1 << 16) | 1, next, 0);
+      }
+      grid[base + (int64_t)k * rng.y] = e;
+    }
+  }
 }
 
 using RelaxFn = void (*)(RunArgs);
@@ -855,7 +950,12 @@ RelaxFn relax_fn(int tpv, int ub) {
 }
 
 RelaxFn pick(int tpv, int ub, int kind) {
-  return kind == EAT_LAYOUT_FLAT ? relax_fn<EAT_LAYOUT_FLAT>(tpv, ub) : relax_fn<EAT_LAYOUT_HYBRID>(tpv, ub);
+  switch (kind) {
+    case kKindCompact: return relax_fn<kKindCompact>(tpv, ub);
+    case kKindFlat: return relax_fn<kKindFlat>(tpv, ub);
+    case kKindGrid: return relax_fn<kKindGrid>(tpv, ub);
+    default: return nullptr;
+  }
 }
 
 // Raises a kernel's dynamic-LDS limit when a launch needs more than any earlier
@@ -905,12 +1005,25 @@ hipError_t launch_next_departure(const GraphDev *g_dev, int kind, const int32_t 
                                  const int32_t *x, int32_t *out, int32_t n, hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   const int grid = (n + 255) / 256;
-  if (kind == EAT_LAYOUT_FLAT)
-    hipLaunchKernelGGL(k_next_departure<EAT_LAYOUT_FLAT>, dim3(grid), dim3(256), 0, stream, g_dev,
+  if (kind == kKindFlat)
+    hipLaunchKernelGGL(k_next_departure<kKindFlat>, dim3(grid), dim3(256), 0, stream, g_dev,
+                       type_ids, x, out, n);
+  else if (kind == kKindGrid)
+    hipLaunchKernelGGL(k_next_departure<kKindGrid>, dim3(grid), dim3(256), 0, stream, g_dev,
+                       type_ids, x, out, n);
+  else if (kind == kKindCompact)
+    hipLaunchKernelGGL(k_next_departure<kKindCompact>, dim3(grid), dim3(256), 0, stream, g_dev,
                        type_ids, x, out, n);
   else
-    hipLaunchKernelGGL(k_next_departure<EAT_LAYOUT_HYBRID>, dim3(grid), dim3(256), 0, stream, g_dev,
-                       type_ids, x, out, n);
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_build_grid(const GraphDev &g, hipStream_t stream) {
+  if (g.n_types <= 0) return hipSuccess;
+  if (!g.grid || !g.tail || !g.hdr || !g.vt || !g.ty) return hipErrorInvalidValue;
+  const int64_t blocks = std::min<int64_t>((g.n_types + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_build_grid, dim3((unsigned)blocks), dim3(256), 0, stream, g);
   return hipGetLastError();
 }
 

@@ -167,6 +167,8 @@ eat_status build_layout(const int32_t *u, const int32_t *v, const int32_t *t,
     return fail(EAT_ERR_INVALID_ARGUMENT, "unknown layout kind");
   int32_t cw = opt.cluster_seconds == 0 ? 3600 : opt.cluster_seconds;
   if (cw < 1 || cw > 32767) return fail(EAT_ERR_INVALID_ARGUMENT, "cluster_seconds must be in 1..32767");
+  if (opt.header_grid != 0 && opt.header_grid != -1)
+    return fail(EAT_ERR_INVALID_ARGUMENT, "header_grid must be 0 or -1");
   for (int r : opt.reserved)
     if (r != 0) return fail(EAT_ERR_INVALID_ARGUMENT, "reserved build options must be zero");
   const int nth = resolve_threads(opt.n_threads);

@@ -61,6 +61,7 @@ struct eat_session {
   std::vector<const eat_graph *> graphs;
   GraphDev *d_graphs = nullptr;
   eat::Plan plan;
+  int kind = 0;  // kernel variant
   int grid_cap = 1;
   int n_buckets = 1;
   int32_t max_step = 4096;
@@ -166,18 +167,17 @@ extern "C" eat_status eat_session_create(const eat_graph *const *graphs, int32_t
   const int32_t max_step = o.max_step_queries ? o.max_step_queries : 4096;
   int dev = -1;
   HIP_TRY(hipGetDevice(&dev));
-  int kind = -1;
   int32_t max_v = 1;
   for (int32_t i = 0; i < n_graphs; ++i) {
     if (!graphs[i]) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph " + std::to_string(i) + " is NULL");
     if (graphs[i]->device != dev) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph on another device");
-    if (kind < 0) kind = graphs[i]->info.layout;
-    if (graphs[i]->info.layout != kind)
-      return set_err(EAT_ERR_UNSUPPORTED, "all graphs of one session must share a layout kind");
     max_v = std::max(max_v, graphs[i]->info.n_vertices);
   }
   eat::Plan pl;
   eat_status st = eat::make_plan(&o.run, max_v, dev, &pl);
+  if (st != EAT_OK) return st;
+  int kind = 0;
+  st = eat::exec_kind(graphs, n_graphs, pl.headers, &kind);
   if (st != EAT_OK) return st;
   eat::DeviceLimits lim;
   st = eat::device_limits(dev, &lim);
@@ -188,6 +188,7 @@ extern "C" eat_status eat_session_create(const eat_graph *const *graphs, int32_t
   S->device = dev;
   S->graphs.assign(graphs, graphs + n_graphs);
   S->plan = pl;
+  S->kind = kind;
   S->max_step = max_step;
   const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, pl.ub, kind, pl.lds));
   S->grid_cap = lim.cus * per_cu;
@@ -311,7 +312,7 @@ extern "C" eat_status eat_session_step(eat_session *S, int32_t *n_launched) {
   a.stats = b.d_stats;
   a.n_failed = b.d_ctr + 1;
   const int grid = std::max(1, std::min(n, S->grid_cap));
-  hipError_t e = eat::launch_relax(a, S->plan.tpv, S->plan.ub, S->graphs[0]->info.layout, grid, S->plan.lds, b.stream);
+  hipError_t e = eat::launch_relax(a, S->plan.tpv, S->plan.ub, S->kind, grid, S->plan.lds, b.stream);
   if (e != hipSuccess) return hip_err(e, "relaxation launch");
   HIP_TRY(hipMemcpyAsync(b.h_stats, b.d_stats, sizeof(eat_query_stats) * (size_t)n, hipMemcpyDeviceToHost,
                          b.stream));

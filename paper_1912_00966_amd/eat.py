@@ -32,6 +32,9 @@ EAT_LAYOUT_FLAT = 1
 EAT_MODE_AUTO = 0
 EAT_MODE_FRONTIER = 1
 EAT_MODE_TOPOLOGY = 2
+EAT_HEADERS_AUTO = 0
+EAT_HEADERS_GRID = 1
+EAT_HEADERS_COMPACT = 2
 
 # every function include/eat.h declares
 EXPORTS = (
@@ -52,7 +55,8 @@ _vp = ctypes.c_void_p
 
 class BuildOptions(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_int32), ("cluster_seconds", ctypes.c_int32),
-                ("n_threads", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("n_threads", ctypes.c_int32), ("header_grid", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -64,7 +68,7 @@ class GraphInfo(ctypes.Structure):
                 ("n_edges", ctypes.c_int64), ("n_types", ctypes.c_int64),
                 ("n_headers", ctypes.c_int64), ("n_ap_clusters", ctypes.c_int64),
                 ("n_array_clusters", ctypes.c_int64), ("n_pool", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("n_grid_entries", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -82,7 +86,7 @@ class RunOptions(ctypes.Structure):
     _fields_ = [("threads_per_vertex", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("frontier_cap", ctypes.c_int32),
                 ("table_cap", ctypes.c_int32), ("types_per_lane", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("headers", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class QueryStats(ctypes.Structure):
@@ -128,7 +132,7 @@ def lib():
     L.eat_layout_info.argtypes = [_vp, ctypes.POINTER(GraphInfo)]
     L.eat_layout_view_get.argtypes = [_vp, ctypes.POINTER(LayoutView)]
     L.eat_graph_build.argtypes = conn + [ctypes.POINTER(_vp)]
-    L.eat_graph_upload.argtypes = [_vp, ctypes.POINTER(_vp)]
+    L.eat_graph_upload.argtypes = [_vp, ctypes.POINTER(BuildOptions), ctypes.POINTER(_vp)]
     L.eat_graph_free.argtypes = [_vp]
     L.eat_graph_free.restype = None
     L.eat_graph_info.argtypes = [_vp, ctypes.POINTER(GraphInfo)]
@@ -144,7 +148,7 @@ def lib():
     L.eat_query_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, _i32p, _i32p, _i32p,
                                   ctypes.c_int32, ctypes.POINTER(_vp), _vp,
                                   ctypes.POINTER(RunOptions), ctypes.POINTER(QueryStats)]
-    L.eat_next_departure.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, _vp]
+    L.eat_next_departure.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, _vp]
     L.eat_status_string.argtypes = [ctypes.c_int]
     L.eat_status_string.restype = ctypes.c_char_p
     L.eat_last_error.argtypes = []
@@ -186,11 +190,12 @@ def _ptr32(a):
     return a.ctypes.data_as(_i32p)
 
 
-def _build_opts(layout, cluster_seconds, n_threads):
+def _build_opts(layout, cluster_seconds, n_threads, header_grid=0):
     o = BuildOptions()
     o.layout = int(layout)
     o.cluster_seconds = int(cluster_seconds)
     o.n_threads = int(n_threads)
+    o.header_grid = int(header_grid)
     return o
 
 
@@ -319,24 +324,27 @@ class Graph:
 
 
 def eat_graph_build(u, v, t, lam, n_vertices, layout=EAT_LAYOUT_HYBRID, cluster_seconds=0,
-                    n_threads=0) -> Graph:
+                    n_threads=0, header_grid=0) -> Graph:
+    """header_grid: 0 = also build the device header grid (hybrid), -1 = compact headers only."""
     u, v, t, lam = (_i32(x) for x in (u, v, t, lam))
     h = _vp()
-    o = _build_opts(layout, cluster_seconds, n_threads)
+    o = _build_opts(layout, cluster_seconds, n_threads, header_grid)
     _check(lib().eat_graph_build(_ptr32(u), _ptr32(v), _ptr32(t), _ptr32(lam), len(u),
                                  int(n_vertices), ctypes.byref(o), ctypes.byref(h)))
     return Graph(h)
 
 
-def eat_graph_upload(layout: Layout) -> Graph:
+def eat_graph_upload(layout: Layout, header_grid: int = 0) -> Graph:
     h = _vp()
-    _check(lib().eat_graph_upload(layout._h, ctypes.byref(h)))
+    o = BuildOptions()
+    o.header_grid = int(header_grid)
+    _check(lib().eat_graph_upload(layout._h, ctypes.byref(o), ctypes.byref(h)))
     return Graph(h)
 
 
-def graph_from_timetable(tt, layout=EAT_LAYOUT_HYBRID, cluster_seconds=0) -> Graph:
+def graph_from_timetable(tt, layout=EAT_LAYOUT_HYBRID, cluster_seconds=0, header_grid=0) -> Graph:
     return eat_graph_build(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices, layout=layout,
-                           cluster_seconds=cluster_seconds)
+                           cluster_seconds=cluster_seconds, header_grid=header_grid)
 
 
 def eat_query(g: Graph, s: int, ts: int, arr, stream=None, options=None, stats: bool = False):
@@ -412,10 +420,11 @@ def eat_query_batch(graphs: Sequence[Graph], q_graph, q_src, q_ts, outs, stream=
     return [st[i].as_dict() for i in range(n)] if stats else None
 
 
-def eat_next_departure(g: Graph, type_ids, x, out, stream=None):
+def eat_next_departure(g: Graph, type_ids, x, out, headers=EAT_HEADERS_AUTO, stream=None):
     n = int(type_ids.numel())
-    _check(lib().eat_next_departure(g.handle, _dev_ptr(type_ids, n, "type_ids"), _dev_ptr(x, n, "x"),
-                                    _dev_ptr(out, n, "out"), n, _stream_handle(stream)))
+    _check(lib().eat_next_departure(g.handle, int(headers), _dev_ptr(type_ids, n, "type_ids"),
+                                    _dev_ptr(x, n, "x"), _dev_ptr(out, n, "out"), n,
+                                    _stream_handle(stream)))
 
 
 class Session:

@@ -76,13 +76,19 @@ def _types_of(view):
     return u, view["ty"][:, 0], view["ty"][:, 1]
 
 
-@pytest.mark.parametrize("layout", ["hybrid", "flat"])
-def test_next_departure_matches_definition(layout):
+@pytest.mark.parametrize("layout,cw,headers", [
+    ("hybrid", 0, eat.EAT_HEADERS_GRID), ("hybrid", 0, eat.EAT_HEADERS_COMPACT),
+    ("hybrid", 1800, eat.EAT_HEADERS_GRID), ("hybrid", 1800, eat.EAT_HEADERS_COMPACT),
+    ("flat", 0, eat.EAT_HEADERS_AUTO)])
+def test_next_departure_matches_definition(layout, cw, headers):
     """Per-type lookup (Sections II-B..II-D, Algorithm 6) vs min{t >= x} computed
-    from the raw connection list (P6)."""
+    from the raw connection list, for both device forms of the hybrid layout
+    (header grid, compact headers) and the flat layout; 1800-s clusters give 48
+    clusters per type (occupancy bits above 32)."""
     tt, _ = _workload("city-1k")
-    _say(f"next_departure city-1k {layout}")
-    lay = eat.eat_layout_build(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices, layout=LAYOUTS[layout])
+    _say(f"next_departure city-1k {layout} cw={cw} headers={headers}")
+    lay = eat.eat_layout_build(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices, layout=LAYOUTS[layout],
+                               cluster_seconds=cw)
     view = lay.view()
     tu, tv, tl = _types_of(view)
     # departures of every (u, v, lam) from the raw input
@@ -92,7 +98,9 @@ def test_next_departure_matches_definition(layout):
     bounds = np.r_[starts, len(order)]
     index = {tuple(key[s]): (bounds[i], bounds[i + 1]) for i, s in enumerate(starts)}
     rng = np.random.default_rng(11)
-    g = _graph("city-1k", layout)
+    g = _graph("city-1k", layout, cw)
+    if layout == "hybrid":
+        assert g.info.n_grid_entries == g.info.n_types * g.info.n_clusters
     picks = rng.choice(len(tu), size=600, replace=False)
     ids, xs = [], []
     offs, deps = [0], []
@@ -112,7 +120,8 @@ def test_next_departure_matches_definition(layout):
     ids = np.concatenate(ids).astype(np.int32)
     xs = np.concatenate(xs).astype(np.int32)
     out = torch.empty(len(ids), dtype=torch.int32, device="cuda")
-    eat.eat_next_departure(g, torch.from_numpy(ids).cuda(), torch.from_numpy(xs).cuda(), out)
+    eat.eat_next_departure(g, torch.from_numpy(ids).cuda(), torch.from_numpy(xs).cuda(), out,
+                           headers=headers)
     torch.cuda.synchronize()
     got = out.cpu().numpy()
     # expected: definition on the raw departures of each probed type
@@ -144,6 +153,38 @@ def test_single_queries_city_1k_bit_exact(layout, tpv):
         got, st = _query(g, s, ts, threads_per_vertex=tpv)
         assert st["status"] == 0
         assert np.array_equal(got, exp[i]), (i, s, ts, np.flatnonzero(got != exp[i])[:10])
+
+
+@pytest.mark.parametrize("tpv", [0, 8])
+@pytest.mark.parametrize("cw", [0, 1800])
+def test_compact_headers_are_exact(tpv, cw):
+    """The hybrid layout's compact headers (one per non-empty cluster) give the
+    same answers as the header grid, which AUTO picks when the graph has one."""
+    tt, q = _workload("city-1k")
+    exp = _expected("city-1k")
+    g = _graph("city-1k", "hybrid", cw)
+    _say(f"compact headers city-1k tpv={tpv} cw={cw}")
+    for i, (s, ts) in enumerate(zip(q.s, q.ts)):
+        got, st = _query(g, s, ts, threads_per_vertex=tpv, headers=eat.EAT_HEADERS_COMPACT)
+        assert np.array_equal(got, exp[i]), (i, s, ts)
+        got2, st2 = _query(g, s, ts, threads_per_vertex=tpv, headers=eat.EAT_HEADERS_GRID)
+        assert np.array_equal(got2, exp[i]), (i, s, ts)
+
+
+def test_graph_without_grid_uses_compact_headers():
+    tt, q = _workload("city-1k")
+    exp = _expected("city-1k")
+    g = eat.graph_from_timetable(tt, header_grid=-1)
+    assert g.info.n_grid_entries == 0
+    got, _ = _query(g, int(q.s[0]), int(q.ts[0]))
+    assert np.array_equal(got, exp[0])
+    out = torch.empty(g.n_vertices, dtype=torch.int32, device="cuda")
+    with pytest.raises(eat.EatError) as ei:
+        eat.eat_query(g, 0, 0, out, options={"headers": eat.EAT_HEADERS_GRID})
+    assert ei.value.status == eat.EAT_ERR_UNSUPPORTED
+    with pytest.raises(eat.EatError) as ei:
+        eat.eat_query(g, 0, 0, out, options={"headers": 7})
+    assert ei.value.status == eat.EAT_ERR_INVALID_ARGUMENT
 
 
 @pytest.mark.parametrize("mode", [eat.EAT_MODE_TOPOLOGY, eat.EAT_MODE_FRONTIER])
@@ -214,15 +255,18 @@ def test_batch_city_1k_equals_oracle(layout):
         assert np.array_equal(outs[i], exp[i]), i
 
 
-@pytest.mark.parametrize("layout", ["hybrid", "flat"])
-def test_batch_city_50k_all_256_queries_bit_exact(layout):
+@pytest.mark.parametrize("layout,headers", [("hybrid", eat.EAT_HEADERS_GRID),
+                                            ("hybrid", eat.EAT_HEADERS_COMPACT),
+                                            ("flat", eat.EAT_HEADERS_AUTO)])
+def test_batch_city_50k_all_256_queries_bit_exact(layout, headers):
     tt, q = _workload("city-50k")
-    _say(f"batch city-50k {layout}: building graph")
+    _say(f"batch city-50k {layout} headers={headers}: building graph")
     g = _graph("city-50k", layout)
     _say("  running batch")
     V = tt.n_vertices
     slab = torch.full((len(q), V), -7, dtype=torch.int32, device="cuda")
-    b = eat.Batch([g], np.zeros(len(q), np.int32), q.s, q.ts, [slab[i] for i in range(len(q))])
+    b = eat.Batch([g], np.zeros(len(q), np.int32), q.s, q.ts, [slab[i] for i in range(len(q))],
+                  options={"headers": headers})
     b.run()
     st = b.wait(stats=True)
     got = slab.cpu().numpy()
