@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-query comparison")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--dump-stats", default="", metavar="PATH",
+                    help="write the per-query statistics of the last timed launch as JSON")
     ap.add_argument("--serve", action="store_true",
                     help="serving mode: Poisson arrivals over resident 10k/50k/500k-stop cities, "
                          "p50/p99 latency and sustained queries/s per rate (prints its own JSON line)")
@@ -154,6 +156,9 @@ def main():
         batch.run(stream)
     stats = batch.wait(stats=True)
     torch.cuda.synchronize()
+    if args.dump_stats:
+        with open(args.dump_stats, "w") as f:
+            json.dump([dict(st, s=int(q.s[i]), ts=int(q.ts[i])) for i, st in enumerate(stats)], f)
 
     # ---- timed region: K batched steps ------------------------------------------------
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]

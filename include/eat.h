@@ -160,13 +160,15 @@ eat_status eat_graph_build(const int32_t *u, const int32_t *v, const int32_t *t,
  * the type index, the cluster index k = x / width and the tail stop's type
  * range, without reading the type record first.  The entries of stop u (types
  * b .. b+n-1) form one block ordered by cluster, then type:
- *   grid[b * n_clusters + k * n + (j - b)] = {t0, c, next, 0}
- * where {t0, c} is the cluster's header (same encoding as hdr below) and next
- * is the type's first departure in a later cluster (EAT_INF if none).  An
- * empty cluster holds {next, (1 << 16) | 1, next, 0}: a one-term progression
+ *   grid[b * n_clusters + k * n + (j - b)] = {t0, c, next, m}
+ * where {t0, c} is the cluster's header (same encoding as hdr below), next is
+ * the type's first departure in a later cluster (EAT_INF if none) and m a
+ * multiplier that replaces the division by the progression step.  An empty
+ * cluster holds {next, (1 << 16) | 1, next, 0}: a one-term progression
  * at the next departure, which is the answer of Section II-D for any x inside
  * that cluster.  Lanes that expand the types of one stop at one cluster read
- * consecutive entries.  Costs 16 * n_types * n_clusters bytes of HBM. */
+ * consecutive entries.  Costs 16 * n_types * n_clusters bytes of HBM; built
+ * only when n_types * n_clusters < 2^31. */
 eat_status eat_graph_upload(const eat_layout *layout, const eat_build_options *opt, eat_graph **out);
 void eat_graph_free(eat_graph *g); /* NULL-safe; waits for the device */
 eat_status eat_graph_info(const eat_graph *g, eat_graph_info_t *out);

@@ -213,7 +213,7 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, const eat_build_opti
   const bool hybrid = L->kind == EAT_LAYOUT_HYBRID;
   const bool need_hi = hybrid && L->n_clusters > 32;
   const int64_t T = L->n_types;
-  bool with_grid = hybrid && header_grid == 0 && T > 0;
+  bool with_grid = hybrid && header_grid == 0 && T > 0 && T * (int64_t)L->n_clusters < ((int64_t)1 << 31);
   GraphBytes b = graph_bytes(*L, with_grid);
   hipError_t e = hipMalloc(&g->d_buf, b.total);
   if (e != hipSuccess && with_grid) {  // the grid is an accelerator: go without it
@@ -247,6 +247,8 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, const eat_build_opti
   g->desc.cluster_seconds = L->cluster_seconds;
   g->desc.n_clusters = L->n_clusters;
   g->desc.kind = L->kind;
+  g->desc.horizon = (int32_t)std::min<int64_t>((int64_t)L->n_clusters * L->cluster_seconds, INT32_MAX);
+  g->desc.inv_cw = 1.0f / (float)L->cluster_seconds;
   g->info.device_bytes = (int64_t)b.total;
   g->info.n_grid_entries = with_grid ? T * (int64_t)L->n_clusters : 0;
 

@@ -20,9 +20,10 @@ struct GraphDev {
   const int32_t *pool;     // departures
   // Hybrid header grid (nullptr when not built): side[T] per type
   // {v, lam, first type of v, type count of v}; grid[T * n_clusters] entries
-  // {t0, c, next, 0} of every (type, cluster), stop-blocked and cluster-major
-  // (the layout is spelled out at eat_graph_upload in eat.h); tail[T] the
-  // tail stop of each type (diagnostics only).
+  // {t0, c, next, m} of every (type, cluster), stop-blocked and cluster-major
+  // (the layout is spelled out at eat_graph_upload in eat.h; m is the
+  // division multiplier of the progression step, see k_build_grid); tail[T]
+  // the tail stop of each type (diagnostics only).
   const int4 *side;
   const int4 *grid;
   const int32_t *tail;
@@ -31,7 +32,8 @@ struct GraphDev {
   int32_t cluster_seconds;
   int32_t n_clusters;
   int32_t kind;            // eat_layout_kind
-  int32_t pad_;
+  int32_t horizon;         // n_clusters * cluster_seconds (< 2^24)
+  float inv_cw;            // 1 / cluster_seconds, for the cluster index of a time
 };
 
 // Kernel variants by the timetable form they read: the hybrid layout's

@@ -102,18 +102,31 @@ struct Look {
   int32_t mode;   // 0: no departure >= x; 1: the first departure of header idx; 2: search in header idx
   bool has_next;  // another non-empty cluster follows cluster idx
   int2 h, hn;     // header idx and idx + 1 (hybrid)
-  int64_t gidx;   // grid entry index (grid)
-  int4 e;         // grid entry {t0, c, next, 0}
+  int32_t gidx;   // grid entry index (grid)
+  int4 e;         // grid entry {t0, c, next, m}
   int4 c0, c1;    // first chunks of an array cluster (hybrid) or departures 0..7 (flat)
   int4 c2, c3;    // departures 8..15 (flat)
 };
 
+// Cluster index floor(x / width) of a time x < horizon (< 2^24, so x is exact
+// in float): a float product is within one of it, and one step fixes that.
+__device__ __forceinline__ int32_t cluster_of(const GraphDev &G, int32_t x) {
+  int32_t k = (int32_t)((float)x * G.inv_cw);
+  k += ((k + 1) * G.cluster_seconds <= x) ? 1 : 0;
+  k -= (k * G.cluster_seconds > x) ? 1 : 0;
+  return k;
+}
+
 // Grid: entry of type j (tail stop's types [b, b + n)) in the cluster of x.
+// Grids have fewer than 2^31 entries.
 __device__ __forceinline__ void look_locate_grid(const GraphDev &G, int64_t j, int32_t b, int32_t n, int32_t x,
                                                  Look &L) {
-  const uint32_t k = (uint32_t)x / (uint32_t)G.cluster_seconds;
-  L.mode = k < (uint32_t)G.n_clusters ? 2 : 0;  // else: after the last departure of the timetable
-  L.gidx = (int64_t)b * G.n_clusters + (int64_t)k * n + (j - b);
+  L.mode = 0;  // x at or after the horizon: no departure
+  L.gidx = 0;
+  if (x < G.horizon) {
+    L.mode = 2;
+    L.gidx = b * G.n_clusters + cluster_of(G, x) * n + ((int32_t)j - b);
+  }
 }
 
 template <int KIND>
@@ -122,8 +135,8 @@ __device__ __forceinline__ void look_locate(const GraphDev &G, const int4 r, uin
     L.mode = 0;
     L.idx = 0;
     L.has_next = false;
-    const uint32_t k = (uint32_t)x / (uint32_t)G.cluster_seconds;
-    if (k >= (uint32_t)G.n_clusters) return;  // after the last departure of the timetable
+    if (x >= G.horizon) return;  // after the last departure of the timetable
+    const uint32_t k = (uint32_t)cluster_of(G, x);
     const uint64_t m = (uint64_t)(uint32_t)r.w | ((uint64_t)mhi << 32);
     const uint64_t ahead = m >> k;  // bit 0: cluster k itself
     if (ahead == 0) return;         // no departure in cluster k or later
@@ -219,10 +232,12 @@ __device__ __forceinline__ int32_t look_finish(const GraphDev &G, const int4 r, 
     if (x <= e.x) return e.x;  // also every empty cluster: e.x is the next departure
     if (e.y >= 0) {            // one progression t0 + i*d, i < n
       const int32_t d = e.y & 0xffff, n = e.y >> 16;
-      if (n > 1) {
-        const int32_t i = (x - e.x - 1) / d + 1;  // ceil((x - t0) / d), x > t0
-        if (i < n) return e.x + i * d;
-      }
+      // i = ceil((x - t0) / d) = floor((x - t0 - 1) / d) + 1 with x - t0 - 1 <
+      // width < 2^15: the high half of the product with m = ceil(2^32 / d) is
+      // that quotient exactly (m = 0 stands for d = 1)
+      const uint32_t r = (uint32_t)(x - e.x - 1);
+      const int32_t i = (int32_t)(e.w ? __umulhi(r, (uint32_t)e.w) : r) + 1;
+      if (i < n) return e.x + i * d;
     } else {
       const int32_t t = array_next(G, ~e.y, x, L, c);
       if (t != INF) return t;
@@ -920,7 +935,11 @@ __global__ void k_build_grid(GraphDev G) {
       int4 e;
       if ((m >> k) & 1ull) {
         const int2 h = G.hdr[idx--];
-        e = make_int4(h.x, h.y, next, 0);
+        // progression step d >= 2: m = ceil(2^32 / d) <= 2^31; d = 1 (or no
+        // step: arrays, single terms): 0
+        const uint32_t d = h.y >= 0 ? (uint32_t)(h.y & 0xffff) : 0u;
+        const uint32_t mul = d >= 2 ? (uint32_t)((((uint64_t)1 << 32) + d - 1) / d) : 0u;
+        e = make_int4(h.x, h.y, next, (int32_t)mul);
         next = h.x;
       } else {
         e = make_int4(next, (1 << 16) | 1, next, 0);

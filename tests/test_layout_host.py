@@ -231,3 +231,33 @@ def test_empty_timetable_is_valid():
     lay = eat.eat_layout_build([], [], [], [], 3)
     info = lay.info()
     assert info.n_types == 0 and info.n_conn == 0 and info.n_vertices == 3
+
+
+# ---------------------------------------------------------------- division-free forms
+
+def test_cluster_index_from_float_reciprocal_is_exact():
+    """The kernels take the cluster index floor(x / width) of a time below the
+    horizon (n_clusters * width < 2^24) as int(float(x) * float(1 / width)),
+    corrected by one step; checked here for every x below the horizon."""
+    rng = np.random.default_rng(5)
+    widths = np.r_[1, 2, 3, 7, 60, 600, 1800, 3600, 7200, 32767, rng.integers(1, 32768, 40)]
+    for cw in widths:
+        horizon = min(64 * int(cw), 2**24 - 1)
+        x = np.arange(horizon, dtype=np.int64)
+        k = (x.astype(np.float32) * np.float32(1.0 / np.float32(cw))).astype(np.int64)
+        k += ((k + 1) * cw <= x)
+        k -= (k * cw > x)
+        assert np.array_equal(k, x // cw), cw
+
+
+def test_progression_step_by_multiplier_is_exact():
+    """ceil((x - t0) / d) for 0 < x - t0 <= width (< 2^15) as the high half of
+    (x - t0 - 1) * ceil(2^32 / d), plus one, for every step d of the header
+    encoding (2 .. 65535) and every x - t0 (d = 1 needs no multiplier)."""
+    r = np.arange(32767, dtype=np.uint64)
+    for d in range(2, 65536):
+        m = np.uint64(((1 << 32) + d - 1) // d)
+        assert m <= 2**31
+        q = (r * m) >> np.uint64(32)
+        if not np.array_equal(q, r // np.uint64(d)):
+            raise AssertionError(d)
