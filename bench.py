@@ -80,10 +80,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="city-50k")
+    ap.add_argument("--workload", default="city-50k",
+                    help="city-1k, city-50k, region-500k (one graph), or mixed (eight graphs, 4,096 queries)")
     ap.add_argument("--layout", default="hybrid", choices=["hybrid", "flat"])
     ap.add_argument("--reading", default="S", choices=["S", "F"])
     ap.add_argument("--tpv", type=int, default=0, help="threads per active stop (0 = auto)")
+    ap.add_argument("--window", type=int, default=0,
+                    help="arrival window of a round in seconds (0 = auto, -1 = none)")
+    ap.add_argument("--types-per-lane", type=int, default=0,
+                    help="load-balanced expansion: connection types in flight per lane (0 = auto)")
     ap.add_argument("--table", type=int, default=0,
                     help="on-chip arrival-table slots (0 = auto, -1 = arrivals in HBM only)")
     ap.add_argument("--mode", default="auto", choices=sorted(MODES),
@@ -101,6 +106,10 @@ def main():
     ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000")
     ap.add_argument("--requests", type=int, default=20000, help="requests per rate (serving mode)")
     ap.add_argument("--serve-sizes", default="10000,50000,500000")
+    ap.add_argument("--serve-checks", type=int, default=200,
+                    help="serving: answers per rate and graph (<= 100k stops) checked against the oracle")
+    ap.add_argument("--serve-certs", type=int, default=8,
+                    help="serving: answers per rate and graph (> 100k stops) certified")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, run one device-to-device copy of MIB MiB "
                          "(a kernel of known traffic, to scale profiler byte counters)")
@@ -122,6 +131,8 @@ def main():
     log = lambda m: print(m, file=sys.stderr, flush=True)
     if args.serve:
         return run_serving(args, log)
+    if args.workload == "mixed":
+        return run_mixed(args, log)
 
     t0 = time.time()
     tt, q = synth.workload(args.workload, reading=args.reading)
@@ -146,7 +157,9 @@ def main():
 
     V, Q = tt.n_vertices, len(q)
     slab = torch.empty((Q, V), dtype=torch.int32, device=dev)
-    opts = {"threads_per_vertex": args.tpv, "table_cap": args.table, "mode": MODES[args.mode],
+    opts = {"threads_per_vertex": args.tpv, "types_per_lane": args.types_per_lane,
+            "time_window": args.window,
+            "table_cap": args.table, "mode": MODES[args.mode],
             "headers": HEADERS[args.headers]}
     grid = args.layout == "hybrid" and args.headers != "compact" and info.n_grid_entries > 0
     batch = eat.Batch([g], np.zeros(Q, np.int32), q.s, q.ts, [slab[i] for i in range(Q)], options=opts)
@@ -204,7 +217,7 @@ def main():
     achieved = bytes_per_launch / (kernel_ms / 1e3) / 1e9
     traffic = None
     if (args.workload == "city-50k" and args.layout == "hybrid" and args.table == 0 and args.mode == "auto"
-            and args.headers == "auto"):
+            and args.headers == "auto" and args.window == 0 and args.tpv == 0 and args.types_per_lane == 0):
         traffic = profiled_traffic(os.path.join(ROOT, "profiles", "k_relax_city-50k.md"),
                                    os.path.join(ROOT, "paper_1912_00966_amd", "csrc", "kernels.hip"))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -254,7 +267,7 @@ def main():
         "config": {"workload": f"{args.workload} ({args.reading} reading)", "stops": V,
                    "connections": tt.n_conn, "queries_per_step": Q, "layout": args.layout,
                    "headers": ("grid" if grid else "compact") if args.layout == "hybrid" else None,
-                   "mode": args.mode,
+                   "mode": args.mode, "time_window": args.window,
                    "graphs": 1, "digest": tt.digest()},
         "bit_exact": bit_exact,
         "plain": plain,
@@ -262,6 +275,106 @@ def main():
         "cpu_baseline": cpu,
         "per_query_mean": per_q,
         "preprocess_s": round(prep_s, 3),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _opts(args):
+    return {"threads_per_vertex": args.tpv, "types_per_lane": args.types_per_lane,
+            "time_window": args.window, "table_cap": args.table, "mode": MODES[args.mode],
+            "headers": HEADERS[args.headers]}
+
+
+def run_mixed(args, log):
+    """Batched mode over eight cities of 2k..500k stops: 4,096 queries (512 per
+    graph, interleaved) in one launch, against the same queries as 4,096
+    sequential single-query launches."""
+    import torch
+
+    import oracle
+    from paper_1912_00966_amd import eat, synth
+
+    t0 = time.time()
+    tts, qsets = synth.mixed_batch(reading=args.reading)
+    graphs = [eat.graph_from_timetable(t) for t in tts]
+    log(f"[bench] mixed: {len(tts)} graphs, sum C={sum(t.n_conn for t in tts)} built in {time.time() - t0:.0f}s")
+    qg = np.concatenate([np.full(len(qs), i, np.int32) for i, qs in enumerate(qsets)])
+    qs_ = np.concatenate([qs.s for qs in qsets])
+    qt = np.concatenate([qs.ts for qs in qsets])
+    perm = np.random.default_rng(4).permutation(len(qg))
+    qg, qs_, qt = qg[perm], qs_[perm], qt[perm]
+    Q = len(qg)
+    outs = [torch.empty(graphs[gi].n_vertices, dtype=torch.int32, device="cuda") for gi in qg]
+    batch = eat.Batch(graphs, qg, qs_, qt, outs, options=_opts(args))
+    stream = torch.cuda.current_stream()
+    for _ in range(max(args.warmup, 1)):
+        batch.run(stream)
+    stats = batch.wait(stats=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        batch.run(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_per_step = wall * 1e3 / args.steps
+    kernel_ms = e0.elapsed_time(e1) / args.steps
+    # the same queries, one launch each
+    plain = None
+    if not args.no_plain:
+        p0 = time.perf_counter()
+        for i in range(Q):
+            eat.eat_query(graphs[int(qg[i])], int(qs_[i]), int(qt[i]), outs[i], stream=stream,
+                          options=_opts(args))
+        torch.cuda.synchronize()
+        p_s = time.perf_counter() - p0
+        plain = {"value": round(Q / p_s, 1), "unit": "queries/s", "ms_per_query": round(p_s * 1e3 / Q, 4)}
+    # checks: every answer on the graphs up to 10k stops against the scan, a
+    # sample of the others against the certificate
+    checked = certified = 0
+    exact = True
+    if not args.no_verify:
+        csa = {}
+        per_graph = {gi: 0 for gi in range(len(graphs))}
+        for k in range(Q):
+            gi = int(qg[k])
+            t = tts[gi]
+            if t.n_vertices <= 10_000:
+                if gi not in csa:
+                    csa[gi] = oracle.Csa(t.u, t.v, t.t, t.lam, t.n_vertices)
+                exact &= bool(np.array_equal(outs[k].cpu().numpy(), csa[gi].query(qs_[k], qt[k])))
+                checked += 1
+            elif per_graph[gi] < 4:
+                got = outs[k].cpu().numpy()
+                exact &= oracle.certify(t.u, t.v, t.t, t.lam, t.n_vertices, qs_[k], qt[k], got) == 0
+                per_graph[gi] += 1
+                certified += 1
+        log(f"[bench] mixed: {checked} answers vs the scan, {certified} certified: "
+            f"{'bit-exact' if exact else 'MISMATCH'}")
+    V = {gi: g.n_vertices for gi, g in enumerate(graphs)}
+    grid = args.headers != "compact" and all(g.info.n_grid_entries > 0 for g in graphs)
+    total = 0
+    for k, st in enumerate(stats):
+        total += algorithmic_bytes([st], V[int(qg[k])], slab_only=args.table == -1, grid=grid)
+    achieved = total / (kernel_ms / 1e3) / 1e9
+    out = {
+        "metric": "EAT queries/sec, batched (8 graphs, one launch) vs plain",
+        "value": round(Q / (ms_per_step / 1e3), 1), "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"mixed batch ({args.reading} reading)",
+                   "graphs": [t.n_vertices for t in tts], "queries_per_step": Q,
+                   "connections": int(sum(t.n_conn for t in tts)), "time_window": args.window},
+        "bit_exact": exact if not args.no_verify else None, "checked_vs_scan": checked,
+        "certified": certified, "plain": plain,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_relax",
+                     "kernel_ms": round(kernel_ms, 4), "algorithmic_bytes_per_launch": int(total)},
+        "per_query_mean": {k: float(np.mean([st[k] for st in stats]))
+                           for k in ("rounds", "activations", "type_evals", "reached", "spilled")},
     }
     print(json.dumps(out), flush=True)
 
@@ -296,21 +409,43 @@ def run_serving(args, log):
                 kept[r.id] = sess.result(slot).cpu().numpy()
 
         rep = serve.serve(sess, reqs, on_done=on_done, min_batch=64, max_delay_s=50e-6)
-        # spot checks: served == alone on the GPU; a few also against the oracle
+        # spot checks of the timed run: served == alone on the GPU
         ok_alone = all(np.array_equal(kept[i], graphs[reqs[i].graph].query(reqs[i].s, reqs[i].ts).cpu().numpy())
                        for i in kept)
-        n_oracle = 0
+        # checking run (untimed, same arrivals and batching): every result of a
+        # sample is copied out as it completes and checked against the oracle --
+        # the connection scan on the smaller graphs, the certificate (source,
+        # closure, witness) on graphs above 100k stops
+        per_graph = {gi: (args.serve_checks if graphs[gi].n_vertices <= 100_000 else args.serve_certs)
+                     for gi in range(len(graphs))}
+        want, seen = set(), {gi: 0 for gi in per_graph}
+        for r in reqs:
+            if seen[r.graph] < per_graph[r.graph]:
+                want.add(r.id)
+                seen[r.graph] += 1
+        got = {}
+
+        def keep_all(r, slot):
+            if r.id in want:
+                got[r.id] = sess.result(slot).cpu().numpy()
+
+        serve.serve(sess, reqs, on_done=keep_all, min_batch=64, max_delay_s=50e-6)
+        n_csa = n_cert = 0
         ok_oracle = True
-        for i in sorted(kept)[:4]:
+        for i in sorted(got):
             r = reqs[i]
-            if r.graph not in csa:
-                t = tts[r.graph]
-                csa[r.graph] = oracle.Csa(t.u, t.v, t.t, t.lam, t.n_vertices)
-            ok_oracle &= bool(np.array_equal(kept[i], csa[r.graph].query(r.s, r.ts)))
-            n_oracle += 1
+            t = tts[r.graph]
+            if graphs[r.graph].n_vertices <= 100_000:
+                if r.graph not in csa:
+                    csa[r.graph] = oracle.Csa(t.u, t.v, t.t, t.lam, t.n_vertices)
+                ok_oracle &= bool(np.array_equal(got[i], csa[r.graph].query(r.s, r.ts)))
+                n_csa += 1
+            else:
+                ok_oracle &= oracle.certify(t.u, t.v, t.t, t.lam, t.n_vertices, r.s, r.ts, got[i]) == 0
+                n_cert += 1
         row = {"offered_qps": rate, **rep.as_dict(), "checked_vs_alone": len(kept),
-               "bit_exact_vs_alone": bool(ok_alone), "checked_vs_oracle": n_oracle,
-               "bit_exact_vs_oracle": bool(ok_oracle)}
+               "bit_exact_vs_alone": bool(ok_alone), "checked_vs_oracle_scan": n_csa,
+               "certified": n_cert, "bit_exact_vs_oracle": bool(ok_oracle)}
         log(f"[serve] {row}")
         out["rates"].append(row)
     sess.free()

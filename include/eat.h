@@ -191,14 +191,22 @@ typedef enum {
 typedef struct {
   int32_t threads_per_vertex; /* lanes sharing one active stop's types: 1,2,4,..,64; 0 = auto */
   int32_t mode;               /* eat_mode */
-  int32_t max_rounds;         /* round limit per query; 0 = n_vertices + 2 */
+  int32_t max_rounds;         /* round limit per query; 0 = n_vertices + 2 without a time
+                                 window, 8 * n_vertices + 64 with one */
   int32_t frontier_cap;       /* frontier list entries kept on chip; 0 = auto */
   int32_t table_cap;          /* on-chip arrival-table slots (power of two); 0 = auto,
                                  -1 = keep arrivals in the result slab (HBM) only */
   int32_t types_per_lane;     /* load-balanced expansion: connection types each lane
                                  keeps in flight, 1..3; 0 = 1 */
   int32_t headers;            /* eat_headers: which form of the hybrid headers to read */
-  int32_t reserved[1];        /* must be zero */
+  int32_t time_window;        /* frontier rounds expand only the listed stops whose arrival
+                                 is below (smallest arrival pushed for the round) + this
+                                 many seconds; the others stay listed for a later round.
+                                 0 = auto (7200), -1 = no window (every listed stop every
+                                 round, the schedule of Section III-B).  The answer is the
+                                 same either way; the window trades a few more rounds for
+                                 fewer re-expansions of stops whose arrival improves */
+  int32_t reserved[2];        /* must be zero */
 } eat_run_options;
 
 typedef struct {

@@ -8,12 +8,14 @@ by the graphs' shape, the batch size and the device name, so a later call
 with the same key returns at once.
 
 Knobs (all exact; they change only speed):
-  threads_per_vertex  0 = load-balanced expansion, or 8/16/32 lanes per active
+  threads_per_vertex  0 = load-balanced expansion, or 16/32 lanes per active
                       stop (virtual warps)
+  time_window         arrival window of a round (seconds; -1 = none)
   types_per_lane      load-balanced expansion: connection types each lane keeps
-                      in flight (1..3)
+                      in flight
   table_cap           0 = arrivals in the on-chip table (auto size), -1 = in
                       the result slab (HBM)
+  headers             header grid or compact headers (hybrid layout)
   mode                frontier-driven rounds, or a topology sweep every round
 """
 from __future__ import annotations
@@ -31,10 +33,11 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "eat_autotune.js
 
 
 def candidates():
-    for tpv, table in itertools.product((0, 8, 16, 32), (0, -1)):
-        for ub in ((1, 2, 3) if tpv == 0 else (0,)):
-            yield {"threads_per_vertex": tpv, "types_per_lane": ub, "table_cap": table,
-                   "mode": eat.EAT_MODE_FRONTIER}
+    for tpv, window in itertools.product((0, 16, 32), (3600, 7200, -1)):
+        yield {"threads_per_vertex": tpv, "time_window": window, "mode": eat.EAT_MODE_FRONTIER}
+    yield {"threads_per_vertex": 0, "types_per_lane": 2, "mode": eat.EAT_MODE_FRONTIER}
+    yield {"table_cap": -1}
+    yield {"headers": eat.EAT_HEADERS_COMPACT}
     yield {"mode": eat.EAT_MODE_TOPOLOGY}
 
 

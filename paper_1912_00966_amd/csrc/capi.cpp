@@ -401,6 +401,8 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   if (o.headers < EAT_HEADERS_AUTO || o.headers > EAT_HEADERS_COMPACT)
     return set_err(EAT_ERR_INVALID_ARGUMENT, "unknown header form");
   pl->headers = o.headers;
+  if (o.time_window < -1) return set_err(EAT_ERR_INVALID_ARGUMENT, "time_window must be >= -1");
+  pl->window = o.time_window == 0 ? 7200 : (o.time_window < 0 ? 0 : o.time_window);
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;
   int fcap = o.frontier_cap ? o.frontier_cap : 1024;
@@ -452,6 +454,7 @@ void order_queries(const std::vector<const eat_graph *> &graphs, std::vector<Que
 
 void apply_plan(const Plan &pl, RunArgs *a) {
   a->max_rounds = pl.max_rounds;
+  a->window = pl.window;
   a->mode = pl.mode;
   a->fcap = pl.fcap;
   a->bm_words = pl.bm_words;

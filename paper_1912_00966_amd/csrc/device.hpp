@@ -58,12 +58,13 @@ struct RunArgs {
   const QueryDev *queries;   // device array of nq, or nullptr: use `single`
   QueryDev single;           // the one query when queries == nullptr
   int32_t nq;
-  int32_t max_rounds;        // 0: n_vertices + 2 of the query's graph
+  int32_t max_rounds;        // 0: n_vertices + 2 (8 * n_vertices + 64 with a window)
   int32_t mode;              // eat_mode
   int32_t fcap;              // frontier list capacity (entries, multiple of 32)
   int32_t bm_words;          // activity bitmap words (>= ceil(V / 32) of every graph)
   int32_t table_cap;         // on-chip arrival table slots (power of two), 0 = none
   int32_t table_bits;        // log2(table_cap)
+  int32_t window;            // arrival window of a round in seconds, 0 = none
   // Queries are split into n_buckets contiguous buckets (queries[buckets[b]]
   // .. queries[buckets[b+1]-1]); work-group w takes queries from bucket
   // w % n_buckets first (work-groups are dealt to the XCDs in turn, so a

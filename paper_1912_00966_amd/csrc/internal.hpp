@@ -56,6 +56,7 @@ struct Plan {
   int table_cap = 0;
   int table_bits = 0;
   int headers = EAT_HEADERS_AUTO;
+  int window = 0;  // seconds, 0 = none
   int64_t ns_per_tick = 0;
   size_t lds = 0;
 };

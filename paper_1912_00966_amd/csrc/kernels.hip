@@ -43,16 +43,65 @@ namespace {
 
 constexpr int32_t INF = EAT_INF;
 
+// Pointers into device (global) memory.  The graph descriptor and the query
+// records hold plain pointers; the kernels read through these so that every
+// access compiles to a global (not flat) instruction: flat accesses also count
+// against the LDS wait counter, which would make each on-chip probe wait for
+// the outstanding global reads.
+// (The host pass of this single-source file only parses device code; it sees
+// plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gp = __attribute__((address_space(1))) T *;
+#else
+template <class T>
+using gp = T *;
+#endif
+
+struct GraphG {
+  gp<const int2> vt;
+  gp<const int4> ty;
+  gp<const int2> hdr;
+  gp<const int32_t> pool;
+  gp<const int4> side;
+  gp<const int4> grid;
+  gp<const int32_t> tail;
+  int64_t n_types;
+  int32_t n_vertices;
+  int32_t cluster_seconds;
+  int32_t n_clusters;
+  int32_t horizon;
+  float inv_cw;
+};
+
+__device__ __forceinline__ GraphG graph_g(const GraphDev &g) {
+  GraphG o;
+  o.vt = (gp<const int2>)g.vt;
+  o.ty = (gp<const int4>)g.ty;
+  o.hdr = (gp<const int2>)g.hdr;
+  o.pool = (gp<const int32_t>)g.pool;
+  o.side = (gp<const int4>)g.side;
+  o.grid = (gp<const int4>)g.grid;
+  o.tail = (gp<const int32_t>)g.tail;
+  o.n_types = g.n_types;
+  o.n_vertices = g.n_vertices;
+  o.cluster_seconds = g.cluster_seconds;
+  o.n_clusters = g.n_clusters;
+  o.horizon = g.horizon;
+  o.inv_cw = g.inv_cw;
+  return o;
+}
+
 // arr[] accesses: relaxed atomics at agent scope.  Loads bypass the per-CU
 // vector L1, so a stop's value is never read from a stale L1 line after an
 // atomic minimum (performed in L2) lowered it.
-__device__ __forceinline__ int32_t ld_arr(const int32_t *p) {
+__device__ __forceinline__ int32_t ld_arr(gp<const int32_t> p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ int32_t min_arr(int32_t *p, int32_t v) {
+__device__ __forceinline__ int32_t min_arr(gp<int32_t> p, int32_t v) {
   return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ __forceinline__ void st_arr(int32_t *p, int32_t v) {
+__device__ __forceinline__ void st_arr(gp<int32_t> p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -110,7 +159,7 @@ struct Look {
 
 // Cluster index floor(x / width) of a time x < horizon (< 2^24, so x is exact
 // in float): a float product is within one of it, and one step fixes that.
-__device__ __forceinline__ int32_t cluster_of(const GraphDev &G, int32_t x) {
+__device__ __forceinline__ int32_t cluster_of(const GraphG &G, int32_t x) {
   int32_t k = (int32_t)((float)x * G.inv_cw);
   k += ((k + 1) * G.cluster_seconds <= x) ? 1 : 0;
   k -= (k * G.cluster_seconds > x) ? 1 : 0;
@@ -119,7 +168,7 @@ __device__ __forceinline__ int32_t cluster_of(const GraphDev &G, int32_t x) {
 
 // Grid: entry of type j (tail stop's types [b, b + n)) in the cluster of x.
 // Grids have fewer than 2^31 entries.
-__device__ __forceinline__ void look_locate_grid(const GraphDev &G, int64_t j, int32_t b, int32_t n, int32_t x,
+__device__ __forceinline__ void look_locate_grid(const GraphG &G, int64_t j, int32_t b, int32_t n, int32_t x,
                                                  Look &L) {
   L.mode = 0;  // x at or after the horizon: no departure
   L.gidx = 0;
@@ -130,7 +179,7 @@ __device__ __forceinline__ void look_locate_grid(const GraphDev &G, int64_t j, i
 }
 
 template <int KIND>
-__device__ __forceinline__ void look_locate(const GraphDev &G, const int4 r, uint32_t mhi, int32_t x, Look &L) {
+__device__ __forceinline__ void look_locate(const GraphG &G, const int4 r, uint32_t mhi, int32_t x, Look &L) {
   if constexpr (KIND == EAT_LAYOUT_HYBRID) {
     L.mode = 0;
     L.idx = 0;
@@ -150,7 +199,7 @@ __device__ __forceinline__ void look_locate(const GraphDev &G, const int4 r, uin
 
 // Issues the memory reads of a located lookup (no use of their results).
 template <int KIND>
-__device__ __forceinline__ void look_fetch_headers(const GraphDev &G, const int4 r, Look &L) {
+__device__ __forceinline__ void look_fetch_headers(const GraphG &G, const int4 r, Look &L) {
   if constexpr (KIND == EAT_LAYOUT_HYBRID) {
     // header idx + 1 exists: the header array carries one padding entry
     L.h = G.hdr[L.idx];
@@ -159,7 +208,7 @@ __device__ __forceinline__ void look_fetch_headers(const GraphDev &G, const int4
     if (L.mode != 0) L.e = G.grid[L.gidx];
   } else {
     if (L.mode != 0 && r.w <= 16) {
-      const int4 *p4 = reinterpret_cast<const int4 *>(G.pool + r.z);
+      gp<const int4> p4 = (gp<const int4>)(G.pool + r.z);
       L.c0 = p4[0];
       L.c1 = p4[1];
       L.c2 = p4[2];
@@ -170,17 +219,17 @@ __device__ __forceinline__ void look_fetch_headers(const GraphDev &G, const int4
 
 // Hybrid only: the chunks of an array cluster that x falls into (needs the header).
 template <int KIND>
-__device__ __forceinline__ void look_fetch_chunks(const GraphDev &G, int32_t x, Look &L, Ctr &c) {
+__device__ __forceinline__ void look_fetch_chunks(const GraphG &G, int32_t x, Look &L, Ctr &c) {
   if constexpr (KIND == EAT_LAYOUT_HYBRID) {
     if (L.mode == 2 && L.h.y < 0 && x > L.h.x) {
-      const int4 *p4 = reinterpret_cast<const int4 *>(G.pool + (~L.h.y));
+      gp<const int4> p4 = (gp<const int4>)(G.pool + (~L.h.y));
       L.c0 = p4[0];
       L.c1 = p4[1];
       c.pool += 8;
     }
   } else if constexpr (KIND == kKindGrid) {
     if (L.mode == 2 && L.e.y < 0 && x > L.e.x) {
-      const int4 *p4 = reinterpret_cast<const int4 *>(G.pool + (~L.e.y));
+      gp<const int4> p4 = (gp<const int4>)(G.pool + (~L.e.y));
       L.c0 = p4[0];
       L.c1 = p4[1];
       c.pool += 8;
@@ -190,7 +239,7 @@ __device__ __forceinline__ void look_fetch_chunks(const GraphDev &G, int32_t x, 
 
 // First departure >= x of the array cluster at pool[off] (pool[off] = n, then
 // n sorted departures, the first < x); L.c0, L.c1 hold its first 8 words.
-__device__ __forceinline__ int32_t array_next(const GraphDev &G, int32_t off, int32_t x, const Look &L, Ctr &c) {
+__device__ __forceinline__ int32_t array_next(const GraphG &G, int32_t off, int32_t x, const Look &L, Ctr &c) {
   const int32_t n = L.c0.x;
   int32_t t = INF;
   if (n <= 7) {
@@ -198,7 +247,7 @@ __device__ __forceinline__ int32_t array_next(const GraphDev &G, int32_t off, in
 #pragma unroll
     for (int i = 0; i < 7; ++i) t = (i < n && d7[i] >= x && d7[i] < t) ? d7[i] : t;
   } else {
-    const int32_t *p = G.pool + off;
+    gp<const int32_t> p = G.pool + off;
     int32_t lo = 2, hi = n + 1;
     while (lo < hi) {
       const int32_t mid = (lo + hi) >> 1;
@@ -211,7 +260,7 @@ __device__ __forceinline__ int32_t array_next(const GraphDev &G, int32_t off, in
 }
 
 template <int KIND>
-__device__ __forceinline__ int32_t look_finish(const GraphDev &G, const int4 r, int32_t x, const Look &L, Ctr &c) {
+__device__ __forceinline__ int32_t look_finish(const GraphG &G, const int4 r, int32_t x, const Look &L, Ctr &c) {
   if (L.mode == 0) return INF;
   if constexpr (KIND == EAT_LAYOUT_HYBRID) {
     const int2 h = L.h;
@@ -251,7 +300,7 @@ __device__ __forceinline__ int32_t look_finish(const GraphDev &G, const int4 r, 
       return first_at_or_after(d, n, x);
     }
     // long arrays: bisection
-    const int32_t *p = G.pool + r.z;
+    gp<const int32_t> p = G.pool + r.z;
     int32_t lo = 0, hi = n;
     while (lo < hi) {
       const int32_t mid = (lo + hi) >> 1;
@@ -278,7 +327,7 @@ __device__ __forceinline__ void count_fetch(const int4 r, const Look &L, Ctr &c)
 // t_c = min{t in C_{u,v,lam} : t >= x}); INF when there is none.  [b, b + n)
 // is the type range of j's tail stop (read by the grid form only).
 template <int KIND>
-__device__ __forceinline__ int32_t next_departure(const GraphDev &G, int64_t j, int32_t b, int32_t n, int32_t x,
+__device__ __forceinline__ int32_t next_departure(const GraphG &G, int64_t j, int32_t b, int32_t n, int32_t x,
                                                   Ctr &c) {
   Look L;
   int4 r = make_int4(0, 0, 0, 0);
@@ -309,8 +358,10 @@ struct FList {
 
 // Push: wave64 ballot, one LDS atomic per wave, lane offsets by masked
 // population count.
-__device__ __forceinline__ void push(bool want, int32_t item, int32_t beg, int32_t cnt, const FList &nxt,
-                                     int32_t fcap, bool append, int32_t *nn) {
+__device__ __forceinline__ void push(bool want, int32_t item, int32_t beg, int32_t cnt, int32_t val,
+                                     const FList &nxt, int32_t fcap, bool append, int32_t *nn,
+                                     int32_t *nmin) {
+  if (want) atomicMin(nmin, val);  // smallest arrival pushed for the next round
   const uint64_t m = __ballot(want);
   if (m == 0) return;
   const int lane = __lane_id();
@@ -334,8 +385,10 @@ struct ListPush {
   int32_t fcap;
   bool append;
   int32_t *nn;
-  __device__ __forceinline__ void operator()(bool want, int32_t item, int32_t beg, int32_t cnt) const {
-    push(want, item, beg, cnt, nxt, fcap, append, nn);
+  int32_t *nmin;
+  __device__ __forceinline__ void operator()(bool want, int32_t item, int32_t beg, int32_t cnt,
+                                             int32_t val) const {
+    push(want, item, beg, cnt, val, nxt, fcap, append, nn, nmin);
   }
 };
 
@@ -352,7 +405,7 @@ __device__ __forceinline__ int32_t lds_ld(const int32_t *p) {
 
 // In the caller's result slab (HBM); item = stop id.
 struct SlabStore {
-  int32_t *arr;
+  gp<int32_t> arr;
   uint32_t *bits;
   __device__ __forceinline__ int32_t stop(int32_t item) const { return item; }
   __device__ __forceinline__ int32_t value(int32_t item) const { return ld_arr(arr + item); }
@@ -425,7 +478,7 @@ __device__ __forceinline__ bool mark_improved(const Store &S, int32_t it) {
 // Lane type u: j[u] of a tail stop with types [tb[u], tb[u] + tn[u]) reached
 // at x[u]; ok[u] false = no type.
 template <int KIND, int U, class Store, class Push>
-__device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, const int64_t *j,
+__device__ __forceinline__ void relax_batch(const GraphG &G, const Store &S, const int64_t *j,
                                             const int32_t *tb, const int32_t *tn, const int32_t *x,
                                             const bool *ok, const Push &P, Ctr &c) {
   int4 r[U], r2[U];
@@ -466,11 +519,12 @@ __device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, c
     }
   }
   bool want[U];
-  int32_t item[U];
+  int32_t item[U], val[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     want[u] = false;
     item[u] = 0;
+    val[u] = INF;
     if (live[u]) {
       const int32_t tc = look_finish<KIND>(G, r[u], x[u], L[u], c);
       if (tc != INF) {
@@ -483,6 +537,7 @@ __device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, c
               c.imp++;
               want[u] = mark_improved(S, it);
               item[u] = it;
+              val[u] = cand;
             }
           }
         }
@@ -491,14 +546,14 @@ __device__ __forceinline__ void relax_batch(const GraphDev &G, const Store &S, c
   }
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    if constexpr (KIND == kKindGrid) P(want[u], item[u], r[u].z, r[u].w);
-    else P(want[u], item[u], r2[u].x, r2[u].y);
+    if constexpr (KIND == kKindGrid) P(want[u], item[u], r[u].z, r[u].w, val[u]);
+    else P(want[u], item[u], r2[u].x, r2[u].y, val[u]);
   }
 }
 
 // One connection type per lane.
 template <int KIND, class Store, class Push>
-__device__ __forceinline__ void relax(const GraphDev &G, const Store &S, int64_t j, int32_t b, int32_t n, int32_t x,
+__device__ __forceinline__ void relax(const GraphG &G, const Store &S, int64_t j, int32_t b, int32_t n, int32_t x,
                                       const Push &P, Ctr &c) {
   const bool ok = true;
   relax_batch<KIND, 1>(G, S, &j, &b, &n, &x, &ok, P, c);
@@ -507,6 +562,7 @@ __device__ __forceinline__ void relax(const GraphDev &G, const Store &S, int64_t
 struct Shared {
   int32_t q, cnt, count, over, reached;
   int32_t nn[3];                // pushes of round r go to nn[r % 3]
+  int32_t nmin[3];              // smallest arrival pushed in round r: nmin[r % 3]
   int32_t wsum[2][kBlock / 64]; // wave totals of the prefix sum, alternating per call
   unsigned long long acc[5];
 };
@@ -537,41 +593,64 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, Shared &sh, i
   return base + s - v;
 }
 
-// Expand every entry of list[0..n).  The entries' bits are cleared as they are
-// taken (with `clear`; a sweep has claimed them already) before their arrival
-// times are read, so an improvement that lands later pushes them again.
-// TPV == 0: load-balanced -- the connection types of all listed stops form one
-//   index space (prefix sum of their type counts) and lane k relaxes types
-//   k, k + kBlock, ..., two at a time; a lane finds its stop by bisection of
-//   the prefix sums.
+// Expand the entries of list[0..n) whose arrival is below thr; the others
+// are deferred: they go to the next list unexpanded, with their bit still set
+// (re-set after a sweep, which claimed it), so a later round expands them.
+// An expanded entry's bit is cleared (with `clear`; a sweep has claimed them
+// already) before its arrival time is read, so an improvement that lands
+// later pushes it again.
+// TPV == 0: load-balanced -- the connection types of all expanded stops form
+//   one index space (prefix sum of their type counts) and lane k relaxes
+//   types k, k + kBlock, ..., U at a time; a lane finds its stop by bisection
+//   of the prefix sums.
 // TPV > 0: virtual warps (Section IV-B) -- groups of TPV lanes, one stop per
 //   group, lane i of a group takes the stop's types i, i + TPV, ...
 template <int TPV, int KIND, int U, class Store>
-__device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, const FList &cur, int32_t n,
-                                            bool clear, const FList &nxt, int32_t fcap, bool append,
-                                            int32_t *nn, Shared &sh, int32_t *poff, int32_t &scan_call,
-                                            Ctr &c) {
+__device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, const FList &cur, int32_t n,
+                                            bool clear, int32_t thr, const ListPush &P, Shared &sh,
+                                            int32_t *poff, int32_t &scan_call, Ctr &c) {
+  // Takes entry e (e < n): true if it is expanded this round; a deferred
+  // entry is pushed to the next list (by the caller's wave-wide push).
+  auto take = [&](int32_t e, bool &defer, int32_t &dval) -> bool {
+    const int32_t item = cur.item[e];
+    const int32_t x = S.value(item);
+    defer = thr != INF && x >= thr;
+    dval = x;
+    if (defer) {
+      // list mode: the bit is still set; after a sweep, set it again unless
+      // an improvement of this round has set it (and pushed the item) already
+      if (!clear) defer = mark_improved(S, item);
+      return false;
+    }
+    if (clear) atomicAnd(&S.bits[item >> 5], ~(1u << (item & 31)));
+    if (cur.cnt[e] < 0) {  // staged by a sweep: load the stop's type range
+      const int2 r = G.vt[S.stop(item)];
+      cur.beg[e] = r.x;
+      cur.cnt[e] = r.y;
+    }
+    c.act++;
+    return true;
+  };
   if constexpr (TPV == 0) {
     int32_t carry = 0;
     for (int32_t e0 = 0; e0 < n; e0 += kBlock) {
       const int32_t e = e0 + (int32_t)threadIdx.x;
       int32_t d = 0;
+      bool defer = false;
+      int32_t dval = INF, item = 0, beg = 0, cnt = 0;
       if (e < n) {
-        const int32_t item = cur.item[e];
-        if (clear) atomicAnd(&S.bits[item >> 5], ~(1u << (item & 31)));
-        d = cur.cnt[e];
-        if (d < 0) {  // staged by a sweep: load the stop's type range
-          const int32_t u = S.stop(item);
-          const int2 r = G.vt[u];
-          d = r.y;
-          cur.beg[e] = r.x;
-          cur.cnt[e] = r.y;
-        }
-        c.act++;
+        item = cur.item[e];
+        if (take(e, defer, dval)) d = cur.cnt[e];
+        beg = cur.beg[e];
+        cnt = cur.cnt[e];
       }
+      P(defer, item, beg, cnt, dval);
       int32_t tot;
       const int32_t off = block_exclusive_scan(d, sh, scan_call++, &tot);
-      if (e < n) poff[e] = carry + off;
+      if (e < n) {
+        poff[e] = carry + off;
+        if (d == 0) cur.cnt[e] = 0;  // deferred: no types this round
+      }
       carry += tot;
     }
     __syncthreads();  // offsets and type ranges visible to every lane
@@ -595,31 +674,31 @@ __device__ __forceinline__ void expand_list(const GraphDev &G, const Store &S, c
         jj[u] = ok[u] ? (int64_t)tb[u] + (k - poff[i]) : 0;
         xx[u] = ok[u] ? S.value(cur.item[i]) : 0;
       }
-      relax_batch<KIND, U>(G, S, jj, tb, tn, xx, ok, ListPush{nxt, fcap, append, nn}, c);
+      relax_batch<KIND, U>(G, S, jj, tb, tn, xx, ok, P, c);
     }
   } else {
     constexpr int kGroups = kBlock / TPV;
     const int g = threadIdx.x / TPV, lane = threadIdx.x % TPV;
-    // take the entries (clear bits, load unknown type ranges) before any push
-    for (int32_t e = threadIdx.x; e < n; e += kBlock) {
-      const int32_t item = cur.item[e];
-      if (clear) atomicAnd(&S.bits[item >> 5], ~(1u << (item & 31)));
-      if (cur.cnt[e] < 0) {
-        const int32_t u = S.stop(item);
-        const int2 r = G.vt[u];
-        cur.beg[e] = r.x;
-        cur.cnt[e] = r.y;
+    // take the entries (defer, clear bits, load unknown type ranges) before
+    // any relaxation pushes
+    for (int32_t e0 = 0; e0 < n; e0 += kBlock) {
+      const int32_t e = e0 + (int32_t)threadIdx.x;
+      bool defer = false;
+      int32_t dval = INF, item = 0, beg = 0, cnt = 0;
+      if (e < n) {
+        item = cur.item[e];
+        if (!take(e, defer, dval)) cur.item[e] = -1;  // not expanded this round
+        beg = cur.beg[e];
+        cnt = cur.cnt[e];
       }
+      P(defer, item, beg, cnt, dval);
     }
     __syncthreads();
     for (int32_t base = 0; base < n; base += kGroups) {
       const int32_t i = base + g;
-      if (i < n) {
-        const int32_t item = cur.item[i];
-        const int32_t x = S.value(item);
+      if (i < n && cur.item[i] >= 0) {
+        const int32_t x = S.value(cur.item[i]);
         const int32_t b = cur.beg[i], cn = cur.cnt[i], e = b + cn;
-        if (lane == 0) c.act++;
-        const ListPush P{nxt, fcap, append, nn};
         for (int32_t j = b + lane; j < e; j += TPV) relax<KIND>(G, S, j, b, cn, x, P, c);
       }
     }
@@ -636,9 +715,9 @@ struct QState {
 // (topology mode); every other bit is clear.  Returns false if the store
 // overflowed.
 template <int TPV, int KIND, int U, class Store>
-__device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, int32_t n_items,
+__device__ bool run_rounds(const RunArgs &a, const GraphG &G, const Store &S, int32_t n_items,
                            const FList &list0, const FList &list1, int32_t *poff, bool topo,
-                           int32_t max_rounds, Shared &sh, QState &qs, Ctr &c) {
+                           int32_t max_rounds, int32_t x0, Shared &sh, QState &qs, Ctr &c) {
   const int tid = threadIdx.x;
   const int32_t nwords = (n_items + 31) >> 5;
   const int32_t chunk_words = a.fcap >> 5;  // a sweep stages at most fcap items at a time
@@ -647,7 +726,10 @@ __device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, 
   bool sweep = topo;
   int32_t rounds = 0;
   int32_t scan_call = 0;
-  if (tid < 3) sh.nn[tid] = 0;
+  if (tid < 3) {
+    sh.nn[tid] = 0;
+    sh.nmin[tid] = tid == 2 ? x0 : INF;  // "pushed before round 0": the first item
+  }
   __syncthreads();
   for (;;) {
     if (rounds >= max_rounds) {
@@ -657,9 +739,17 @@ __device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, 
     int32_t *nn = &sh.nn[rounds % 3];
     // nn[(rounds + 1) % 3] was last read at the end of round rounds - 2, before
     // the barrier that ended round rounds - 1: safe to reset for the next round
-    if (tid == 0) sh.nn[(rounds + 1) % 3] = 0;
+    if (tid == 0) {
+      sh.nn[(rounds + 1) % 3] = 0;
+      sh.nmin[(rounds + 1) % 3] = INF;
+    }
+    // this round expands the items below the smallest arrival pushed for it
+    // plus the window (that item itself always qualifies)
+    const int32_t base = sh.nmin[(rounds + 2) % 3];
+    const int32_t thr = (a.window <= 0 || base >= INF - a.window) ? INF : base + a.window;
+    const ListPush P{nxt, a.fcap, !topo, nn, &sh.nmin[rounds % 3]};
     if (!sweep) {
-      expand_list<TPV, KIND, U>(G, S, cur, nf, true, nxt, a.fcap, !topo, nn, sh, poff, scan_call, c);
+      expand_list<TPV, KIND, U>(G, S, cur, nf, true, thr, P, sh, poff, scan_call, c);
     } else {
       ++qs.sweeps;
       for (int32_t w0 = 0; w0 < nwords; w0 += chunk_words) {
@@ -682,7 +772,7 @@ __device__ bool run_rounds(const RunArgs &a, const GraphDev &G, const Store &S, 
         }
         __syncthreads();
         const int32_t cnt = sh.cnt;
-        if (cnt) expand_list<TPV, KIND, U>(G, S, cur, cnt, false, nxt, a.fcap, !topo, nn, sh, poff, scan_call, c);
+        if (cnt) expand_list<TPV, KIND, U>(G, S, cur, cnt, false, thr, P, sh, poff, scan_call, c);
         __syncthreads();
       }
     }
@@ -762,17 +852,17 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
     }
     const uint64_t t_start = wall_clock64();
     const QueryDev Q = batch ? a.queries[q] : a.single;
-    const GraphDev G = a.graphs[batch ? Q.graph : 0];
+    const GraphG G = graph_g(a.graphs[batch ? Q.graph : 0]);
     const int32_t V = G.n_vertices;
-    int32_t *arr = Q.arr;
-    const int32_t max_rounds = a.max_rounds > 0 ? a.max_rounds : V + 2;
+    gp<int32_t> arr = (gp<int32_t>)Q.arr;
+    const int32_t max_rounds = a.max_rounds > 0 ? a.max_rounds : (a.window > 0 ? 8 * V + 64 : V + 2);
     QState qs;
     Ctr c;
 
     // ---- Initialize (Algorithm 2): the slab gets infinity everywhere.  The
     // stores drain while the on-chip relaxation runs.
     if ((reinterpret_cast<uintptr_t>(arr) & 15u) == 0) {
-      int4 *a4 = reinterpret_cast<int4 *>(arr);
+      gp<int4> a4 = (gp<int4>)arr;
       const int32_t n4 = V >> 2;
       const int4 inf4 = make_int4(INF, INF, INF, INF);
       for (int32_t i = tid; i < n4; i += kBlock) a4[i] = inf4;
@@ -812,7 +902,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
         l0.cnt[0] = -1;
       }
       __syncthreads();
-      if (run_rounds<TPV, KIND, U>(a, G, T, H, l0, l1, poff, topo, max_rounds, sh, qs, c)) {
+      if (run_rounds<TPV, KIND, U>(a, G, T, H, l0, l1, poff, topo, max_rounds, Q.ts, sh, qs, c)) {
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the infinity fill has landed
         __syncthreads();
         for (int32_t p = tid; p < H; p += kBlock) {
@@ -847,7 +937,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       }
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
-      run_rounds<TPV, KIND, U>(a, G, S, V, l0, l1, poff, topo, max_rounds, sh, qs, c);
+      run_rounds<TPV, KIND, U>(a, G, S, V, l0, l1, poff, topo, max_rounds, Q.ts, sh, qs, c);
       // reached stops
       int32_t mine = 0;
       for (int32_t i = tid; i < V; i += kBlock) mine += ld_arr(arr + i) != INF;
@@ -902,7 +992,7 @@ __global__ void k_next_departure(const GraphDev *gd, const int32_t *ids, const i
                                  int32_t *out, int32_t n) {
   const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const GraphDev G = *gd;
+  const GraphG G = graph_g(*gd);
   const int32_t j = ids[i], x = xs[i];
   if (j < 0 || (int64_t)j >= G.n_types || x < 0) {
     out[i] = -1;
@@ -921,8 +1011,9 @@ __global__ void k_next_departure(const GraphDev *gd, const int32_t *ids, const i
 // One thread per connection type: writes the type's n_clusters grid entries
 // from its compact headers, from the last cluster down, carrying the first
 // departure of the clusters after the current one.
-__global__ void k_build_grid(GraphDev G) {
-  int4 *grid = const_cast<int4 *>(G.grid);
+__global__ void k_build_grid(GraphDev Gd) {
+  const GraphG G = graph_g(Gd);
+  gp<int4> grid = (gp<int4>)const_cast<int4 *>(Gd.grid);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < G.n_types; j += stride) {
     const int4 r = G.ty[2 * j], r2 = G.ty[2 * j + 1];

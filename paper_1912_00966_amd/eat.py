@@ -86,7 +86,8 @@ class RunOptions(ctypes.Structure):
     _fields_ = [("threads_per_vertex", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("max_rounds", ctypes.c_int32), ("frontier_cap", ctypes.c_int32),
                 ("table_cap", ctypes.c_int32), ("types_per_lane", ctypes.c_int32),
-                ("headers", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("headers", ctypes.c_int32), ("time_window", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class QueryStats(ctypes.Structure):

@@ -212,6 +212,27 @@ def test_modes_stores_and_overflows_are_exact(mode, fcap, table):
         assert spills == 0
 
 
+@pytest.mark.parametrize("window", [-1, 1, 60, 600, 7200])
+@pytest.mark.parametrize("tpv", [0, 16])
+def test_time_windows_are_exact(window, tpv):
+    """Rounds that expand only the stops below the smallest pushed arrival plus a
+    window (deferring the rest) reach the same fixpoint; -1 = every listed stop
+    every round."""
+    tt, q = _workload("city-1k")
+    exp = _expected("city-1k")
+    g = _graph("city-1k", "hybrid")
+    _say(f"time window {window} tpv={tpv}")
+    for i, (s, ts) in enumerate(zip(q.s, q.ts)):
+        got, st = _query(g, s, ts, time_window=window, threads_per_vertex=tpv)
+        assert st["status"] == 0
+        assert np.array_equal(got, exp[i]), (i, s, ts)
+    # with overflowing lists (sweeps) and the topology schedule as well
+    for opts in ({"frontier_cap": 32}, {"mode": eat.EAT_MODE_TOPOLOGY}, {"table_cap": -1}):
+        for i in (0, 5, 11):
+            got, _ = _query(g, int(q.s[i]), int(q.ts[i]), time_window=window, threads_per_vertex=tpv, **opts)
+            assert np.array_equal(got, exp[i]), (i, opts)
+
+
 def test_certificate_holds_for_gpu_answers():
     tt, q = _workload("city-1k")
     g = _graph("city-1k", "hybrid")
