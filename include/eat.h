@@ -155,19 +155,21 @@ eat_status eat_graph_build(const int32_t *u, const int32_t *v, const int32_t *t,
  * opt (nullable) only header_grid is used.
  *
  * Header grid (hybrid layout, device side).  Besides the compact headers, the
- * device holds one 16-byte entry per (type, cluster) -- empty clusters
+ * device holds one 32-byte entry per (type, cluster) -- empty clusters
  * included -- so that the entry a lookup needs has an address computable from
  * the type index, the cluster index k = x / width and the tail stop's type
  * range, without reading the type record first.  The entries of stop u (types
  * b .. b+n-1) form one block ordered by cluster, then type:
- *   grid[b * n_clusters + k * n + (j - b)] = {t0, c, next, m}
- * where {t0, c} is the cluster's header (same encoding as hdr below), next is
- * the type's first departure in a later cluster (EAT_INF if none) and m a
- * multiplier that replaces the division by the progression step.  An empty
- * cluster holds {next, (1 << 16) | 1, next, 0}: a one-term progression
+ *   grid[b * n_clusters + k * n + (j - b)] = {t0, c, next, m}, {d2, d3, d4, d5}
+ * where {t0, c} is the cluster's header (same encoding as hdr below) and next
+ * the type's first departure in a later cluster (EAT_INF if none).  For a
+ * progression, m is a multiplier that replaces the division by its step; for
+ * a sorted array, m is its length and d2..d5 its departures 2..5 (EAT_INF past
+ * the length), so arrays of up to 5 departures need no further read.  An
+ * empty cluster holds {next, (1 << 16) | 1, next, 0}: a one-term progression
  * at the next departure, which is the answer of Section II-D for any x inside
  * that cluster.  Lanes that expand the types of one stop at one cluster read
- * consecutive entries.  Costs 16 * n_types * n_clusters bytes of HBM; built
+ * consecutive entries.  Costs 32 * n_types * n_clusters bytes of HBM; built
  * only when n_types * n_clusters < 2^31. */
 eat_status eat_graph_upload(const eat_layout *layout, const eat_build_options *opt, eat_graph **out);
 void eat_graph_free(eat_graph *g); /* NULL-safe; waits for the device */
@@ -189,15 +191,18 @@ typedef enum {
 } eat_headers;
 
 typedef struct {
-  int32_t threads_per_vertex; /* lanes sharing one active stop's types: 1,2,4,..,64; 0 = auto */
+  int32_t threads_per_vertex; /* lanes sharing one active stop's types (virtual warps,
+                                 Section IV-B): 1,2,4,..,64; 0 = wave claims (below) */
   int32_t mode;               /* eat_mode */
   int32_t max_rounds;         /* round limit per query; 0 = n_vertices + 2 without a time
                                  window, 8 * n_vertices + 64 with one */
   int32_t frontier_cap;       /* frontier list entries kept on chip; 0 = auto */
   int32_t table_cap;          /* on-chip arrival-table slots (power of two); 0 = auto,
                                  -1 = keep arrivals in the result slab (HBM) only */
-  int32_t types_per_lane;     /* load-balanced expansion: connection types each lane
-                                 keeps in flight, 1..3; 0 = 1 */
+  int32_t types_per_lane;     /* wave claims: each wave takes 4 * types_per_lane listed
+                                 stops at a time and spreads their connection types over its
+                                 64 lanes, types_per_lane types per lane in flight; 1..3,
+                                 0 = 1 */
   int32_t headers;            /* eat_headers: which form of the hybrid headers to read */
   int32_t time_window;        /* frontier rounds expand only the listed stops whose arrival
                                  is below (smallest arrival pushed for the round) + this

@@ -186,7 +186,7 @@ GraphBytes graph_bytes(const eat_layout &L, bool with_grid) {
   b.pool = align_up(std::max<size_t>(L.pool.size(), 1) * 4);
   b.side = with_grid ? align_up(T * 16) : 0;
   b.tail = with_grid ? align_up(T * 4) : 0;
-  b.grid = with_grid ? align_up(T * (size_t)L.n_clusters * 16) : 0;
+  b.grid = with_grid ? align_up(T * (size_t)L.n_clusters * 32) : 0;
   b.desc = align_up(sizeof(GraphDev));
   b.stats = align_up(sizeof(eat_query_stats)) + align_up(4);
   b.total = b.vt + b.ty + b.hdr + b.pool + b.side + b.tail + b.grid + b.desc + b.stats;
@@ -354,9 +354,9 @@ extern "C" eat_status eat_graph_info(const eat_graph *g, eat_graph_info_t *out) 
 namespace eat {
 
 // LDS bytes: two frontier lists of (item, type begin, type count) and the
-// prefix sums of the load-balanced expansion (fcap entries each), plus the
-// arrival table or the stop bitmap.
-static size_t lists_lds(int fcap) { return (size_t)fcap * 28; }
+// expand list of (item, type begin, type count, arrival), fcap entries each,
+// plus the arrival table or the stop bitmap.
+static size_t lists_lds(int fcap) { return (size_t)fcap * 40; }
 static size_t table_lds(int H, int fcap) { return (size_t)H * 8 + (size_t)(H / 32) * 4 + lists_lds(fcap); }
 
 eat_status exec_kind(const eat_graph *const *g, int32_t n, int headers, int *kind) {
@@ -405,7 +405,7 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   pl->window = o.time_window == 0 ? 7200 : (o.time_window < 0 ? 0 : o.time_window);
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;
-  int fcap = o.frontier_cap ? o.frontier_cap : 1024;
+  int fcap = o.frontier_cap ? o.frontier_cap : 512;
   fcap = (fcap + 31) / 32 * 32;
   DeviceLimits lim;
   eat_status s = device_limits(device, &lim);

@@ -19,11 +19,10 @@ struct GraphDev {
   const int2 *hdr;         // [K + 1] hybrid (one padding entry)
   const int32_t *pool;     // departures
   // Hybrid header grid (nullptr when not built): side[T] per type
-  // {v, lam, first type of v, type count of v}; grid[T * n_clusters] entries
-  // {t0, c, next, m} of every (type, cluster), stop-blocked and cluster-major
-  // (the layout is spelled out at eat_graph_upload in eat.h; m is the
-  // division multiplier of the progression step, see k_build_grid); tail[T]
-  // the tail stop of each type (diagnostics only).
+  // {v, lam, first type of v, type count of v}; grid[2 * T * n_clusters]:
+  // two int4 per (type, cluster), {t0, c, next, m} {d2, d3, d4, d5},
+  // stop-blocked and cluster-major (spelled out at eat_graph_upload in eat.h);
+  // tail[T] the tail stop of each type (diagnostics only).
   const int4 *side;
   const int4 *grid;
   const int32_t *tail;

@@ -42,6 +42,7 @@ namespace eat {
 namespace {
 
 constexpr int32_t INF = EAT_INF;
+constexpr int kClaim = 4;  // frontier entries a wave claims at a time
 
 // Pointers into device (global) memory.  The graph descriptor and the query
 // records hold plain pointers; the kernels read through these so that every
@@ -152,7 +153,7 @@ struct Look {
   bool has_next;  // another non-empty cluster follows cluster idx
   int2 h, hn;     // header idx and idx + 1 (hybrid)
   int32_t gidx;   // grid entry index (grid)
-  int4 e;         // grid entry {t0, c, next, m}
+  int4 e, e2;     // grid entry {t0, c, next, m} {d2, d3, d4, d5}
   int4 c0, c1;    // first chunks of an array cluster (hybrid) or departures 0..7 (flat)
   int4 c2, c3;    // departures 8..15 (flat)
 };
@@ -205,7 +206,10 @@ __device__ __forceinline__ void look_fetch_headers(const GraphG &G, const int4 r
     L.h = G.hdr[L.idx];
     L.hn = G.hdr[L.idx + 1];
   } else if constexpr (KIND == kKindGrid) {
-    if (L.mode != 0) L.e = G.grid[L.gidx];
+    if (L.mode != 0) {
+      L.e = G.grid[2 * (int64_t)L.gidx];
+      L.e2 = G.grid[2 * (int64_t)L.gidx + 1];
+    }
   } else {
     if (L.mode != 0 && r.w <= 16) {
       gp<const int4> p4 = (gp<const int4>)(G.pool + r.z);
@@ -228,7 +232,8 @@ __device__ __forceinline__ void look_fetch_chunks(const GraphG &G, int32_t x, Lo
       c.pool += 8;
     }
   } else if constexpr (KIND == kKindGrid) {
-    if (L.mode == 2 && L.e.y < 0 && x > L.e.x) {
+    // arrays of more than 5 departures, x past the fifth: the departures
+    if (L.mode == 2 && L.e.y < 0 && L.e.w > 5 && x > L.e2.w) {
       gp<const int4> p4 = (gp<const int4>)(G.pool + (~L.e.y));
       L.c0 = p4[0];
       L.c1 = p4[1];
@@ -287,8 +292,12 @@ __device__ __forceinline__ int32_t look_finish(const GraphG &G, const int4 r, in
       const uint32_t r = (uint32_t)(x - e.x - 1);
       const int32_t i = (int32_t)(e.w ? __umulhi(r, (uint32_t)e.w) : r) + 1;
       if (i < n) return e.x + i * d;
-    } else {
-      const int32_t t = array_next(G, ~e.y, x, L, c);
+    } else {  // sorted array: departures 2..5 in the entry (infinity past n),
+              // e.w = n; the rest in the pool
+      const int4 d = L.e2;
+      // (padding is infinity: "none in this cluster", not a departure)
+      int32_t t = x <= d.x ? d.x : x <= d.y ? d.y : x <= d.z ? d.z : x <= d.w ? d.w : INF;
+      if (t == INF && e.w > 5) t = array_next(G, ~e.y, x, L, c);
       if (t != INF) return t;
     }
     return e.z;  // first departure of a later cluster
@@ -356,18 +365,32 @@ struct FList {
   int32_t *cnt;
 };
 
+// The stops a round expands, with their arrival times (wave-claim expansion).
+struct XList {
+  int32_t *item;
+  int32_t *beg;
+  int32_t *cnt;
+  int32_t *x;
+};
+
 // Push: wave64 ballot, one LDS atomic per wave, lane offsets by masked
 // population count.
 __device__ __forceinline__ void push(bool want, int32_t item, int32_t beg, int32_t cnt, int32_t val,
                                      const FList &nxt, int32_t fcap, bool append, int32_t *nn,
                                      int32_t *nmin) {
-  if (want) atomicMin(nmin, val);  // smallest arrival pushed for the next round
   const uint64_t m = __ballot(want);
   if (m == 0) return;
   const int lane = __lane_id();
   const int leader = __ffsll((unsigned long long)m) - 1;
+  // smallest arrival pushed by the wave (lane reads, not shuffles: only the
+  // pushing lanes are sure to be active)
+  int32_t mv = INF;
+  for (uint64_t mm = m; mm; mm &= mm - 1ull) mv = min(mv, __builtin_amdgcn_readlane(val, __ffsll((unsigned long long)mm) - 1));
   int32_t base = 0;
-  if (lane == leader) base = atomicAdd(nn, (int32_t)__popcll(m));
+  if (lane == leader) {
+    atomicMin(nmin, mv);  // smallest arrival pushed for the next round
+    base = atomicAdd(nn, (int32_t)__popcll(m));
+  }
   base = __shfl(base, leader);
   if (want && append) {
     const int32_t slot = base + (int32_t)__popcll(m & ((1ull << lane) - 1ull));
@@ -409,8 +432,11 @@ struct SlabStore {
   uint32_t *bits;
   __device__ __forceinline__ int32_t stop(int32_t item) const { return item; }
   __device__ __forceinline__ int32_t value(int32_t item) const { return ld_arr(arr + item); }
-  __device__ __forceinline__ int32_t find(int32_t v) const { return ld_arr(arr + v); }
-  __device__ __forceinline__ int32_t slot(int32_t v) const { return v; }
+  __device__ __forceinline__ int32_t find(int32_t v, int32_t &pos) const {
+    pos = v;
+    return ld_arr(arr + v);
+  }
+  __device__ __forceinline__ int32_t slot(int32_t v, int32_t) const { return v; }
   __device__ __forceinline__ int32_t lower(int32_t item, int32_t cand) const { return min_arr(arr + item, cand); }
 };
 
@@ -418,8 +444,7 @@ struct SlabStore {
 // touched; item = table slot.  The result slab only receives the final values.
 constexpr int32_t EMPTY = -1;
 struct TableStore {
-  int32_t *keys;   // stop id or EMPTY
-  int32_t *vals;   // arrival time (INF until lowered)
+  int2 *kv;        // {stop id or EMPTY, arrival time (INF until lowered)}
   uint32_t *bits;
   int32_t *count;  // slots in use
   int32_t *over;   // set when the table is too full to take another stop
@@ -427,28 +452,39 @@ struct TableStore {
   int32_t shift;
   int32_t limit;
   __device__ __forceinline__ uint32_t home(int32_t v) const { return ((uint32_t)v * 2654435761u) >> shift; }
-  __device__ __forceinline__ int32_t stop(int32_t item) const { return lds_ld(keys + item); }
-  __device__ __forceinline__ int32_t value(int32_t item) const { return lds_ld(vals + item); }
-  // arrival of v, INF when v is not in the table (yet)
-  __device__ __forceinline__ int32_t find(int32_t v) const {
+  __device__ __forceinline__ int32_t stop(int32_t item) const { return lds_ld(&kv[item].x); }
+  __device__ __forceinline__ int32_t value(int32_t item) const { return lds_ld(&kv[item].y); }
+  // both halves of slot p in one 8-byte read
+  __device__ __forceinline__ int2 entry(uint32_t p) const {
+    const unsigned long long e =
+        __hip_atomic_load(reinterpret_cast<unsigned long long *>(kv + p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return make_int2((int32_t)(uint32_t)e, (int32_t)(uint32_t)(e >> 32));
+  }
+  // arrival of v, INF when v is not in the table (yet); pos = v's slot, or the
+  // empty slot where it would go (entries are never removed, so a later
+  // insertion of v lands at pos or after it)
+  __device__ __forceinline__ int32_t find(int32_t v, int32_t &pos) const {
     uint32_t p = home(v);
     for (uint32_t n = 0; n <= mask; ++n) {
-      const int32_t k = lds_ld(keys + p);
-      if (k == v) return lds_ld(vals + p);
-      if (k == EMPTY) return INF;
+      const int2 e = entry(p);
+      pos = (int32_t)p;
+      if (e.x == v) return e.y;
+      if (e.x == EMPTY) return INF;
       p = (p + 1u) & mask;
     }
+    pos = -1;
     return INF;
   }
-  // slot of v, inserting it; -1 (and *over = 1) when the table is full
-  __device__ __forceinline__ int32_t slot(int32_t v) const {
-    uint32_t p = home(v);
+  // slot of v, inserting it, probing from the position find() gave; -1 (and
+  // *over = 1) when the table is full
+  __device__ __forceinline__ int32_t slot(int32_t v, int32_t hint) const {
+    uint32_t p = hint >= 0 ? (uint32_t)hint : home(v);
     for (uint32_t n = 0; n <= mask; ++n) {
-      const int32_t k = lds_ld(keys + p);
+      const int32_t k = lds_ld(&kv[p].x);
       if (k == v) return (int32_t)p;
       if (k == EMPTY) {
         if (lds_ld(count) >= limit) break;
-        const int32_t old = atomicCAS(keys + p, EMPTY, v);
+        const int32_t old = atomicCAS(&kv[p].x, EMPTY, v);
         if (old == EMPTY) {
           atomicAdd(count, 1);
           return (int32_t)p;
@@ -460,7 +496,7 @@ struct TableStore {
     __hip_atomic_store(over, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     return -1;
   }
-  __device__ __forceinline__ int32_t lower(int32_t item, int32_t cand) const { return atomicMin(vals + item, cand); }
+  __device__ __forceinline__ int32_t lower(int32_t item, int32_t cand) const { return atomicMin(&kv[item].y, cand); }
 };
 
 // After a successful atomic minimum on item: set the item's bit; the lane that
@@ -504,11 +540,12 @@ __device__ __forceinline__ void relax_batch(const GraphG &G, const Store &S, con
       look_fetch_headers<KIND>(G, r[u], L[u]);
     }
   }
-  int32_t av[U];
+  int32_t av[U], pos[U];
   bool live[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    av[u] = ok[u] ? S.find(r[u].x) : INF;
+    pos[u] = -1;
+    av[u] = ok[u] ? S.find(r[u].x, pos[u]) : INF;
     // any departure leaves at t_c >= x, so it arrives at >= x + lam: skip the
     // type when that cannot beat arr[v] (early termination, Section III-D)
     live[u] = ok[u] && x[u] < av[u] - r[u].y && L[u].mode != 0;
@@ -530,7 +567,7 @@ __device__ __forceinline__ void relax_batch(const GraphG &G, const Store &S, con
       if (tc != INF) {
         const int32_t cand = tc + r[u].y;
         if (cand < av[u]) {
-          const int32_t it = S.slot(r[u].x);
+          const int32_t it = S.slot(r[u].x, pos[u]);
           if (it >= 0) {
             const int32_t old = S.lower(it, cand);
             if (cand < old) {
@@ -563,35 +600,11 @@ struct Shared {
   int32_t q, cnt, count, over, reached;
   int32_t nn[3];                // pushes of round r go to nn[r % 3]
   int32_t nmin[3];              // smallest arrival pushed in round r: nmin[r % 3]
-  int32_t wsum[2][kBlock / 64]; // wave totals of the prefix sum, alternating per call
+  int32_t cur[3];               // wave-claim cursor of round r: cur[r % 3]
+  int32_t xn[3];                // stops expanded in round r: xn[r % 3]
+  int32_t cnt2, xn2;            // the same two for a sweep chunk
   unsigned long long acc[5];
 };
-
-// Exclusive prefix sum of v over the work-group; *total receives the sum.
-// Every thread must call it (one barrier).  The wave totals alternate between
-// two buffers, so consecutive calls need no barrier between them.
-__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, Shared &sh, int32_t call, int32_t *total) {
-  constexpr int kWaves = kBlock / 64;
-  const int lane = __lane_id(), w = threadIdx.x >> 6;
-  int32_t *ws = sh.wsum[call & 1];
-  int32_t s = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int32_t o = __shfl_up(s, d);
-    if (lane >= d) s += o;
-  }
-  if (lane == 63) ws[w] = s;
-  __syncthreads();
-  int32_t base = 0, tot = 0;
-#pragma unroll
-  for (int k = 0; k < kWaves; ++k) {
-    const int32_t t = ws[k];
-    base += k < w ? t : 0;
-    tot += t;
-  }
-  *total = tot;
-  return base + s - v;
-}
 
 // Expand the entries of list[0..n) whose arrival is below thr; the others
 // are deferred: they go to the next list unexpanded, with their bit still set
@@ -599,16 +612,15 @@ __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, Shared &sh, i
 // An expanded entry's bit is cleared (with `clear`; a sweep has claimed them
 // already) before its arrival time is read, so an improvement that lands
 // later pushes it again.
-// TPV == 0: load-balanced -- the connection types of all expanded stops form
-//   one index space (prefix sum of their type counts) and lane k relaxes
-//   types k, k + kBlock, ..., U at a time; a lane finds its stop by bisection
-//   of the prefix sums.
+// TPV == 0: wave claims -- each wave takes 4 * U entries at a time from a
+//   shared cursor and spreads their connection types over its lanes, U types
+//   per lane in flight (a load-balanced expansion without a block-wide scan).
 // TPV > 0: virtual warps (Section IV-B) -- groups of TPV lanes, one stop per
 //   group, lane i of a group takes the stop's types i, i + TPV, ...
 template <int TPV, int KIND, int U, class Store>
 __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, const FList &cur, int32_t n,
                                             bool clear, int32_t thr, const ListPush &P, Shared &sh,
-                                            int32_t *poff, int32_t &scan_call, Ctr &c) {
+                                            const XList &X, int32_t *xn, int32_t *cursor, Ctr &c) {
   // Takes entry e (e < n): true if it is expanded this round; a deferred
   // entry is pushed to the next list (by the caller's wave-wide push).
   auto take = [&](int32_t e, bool &defer, int32_t &dval) -> bool {
@@ -632,49 +644,84 @@ __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, con
     return true;
   };
   if constexpr (TPV == 0) {
-    int32_t carry = 0;
+    // Take pass: every thread takes list entries (no relaxation runs, so the
+    // arrival times are stable): deferred ones go to the next list, the
+    // others to X, with their arrival, bits cleared.
+    const int lane = __lane_id();
     for (int32_t e0 = 0; e0 < n; e0 += kBlock) {
       const int32_t e = e0 + (int32_t)threadIdx.x;
-      int32_t d = 0;
-      bool defer = false;
+      bool defer = false, go = false;
       int32_t dval = INF, item = 0, beg = 0, cnt = 0;
       if (e < n) {
         item = cur.item[e];
-        if (take(e, defer, dval)) d = cur.cnt[e];
+        go = take(e, defer, dval);
         beg = cur.beg[e];
         cnt = cur.cnt[e];
       }
       P(defer, item, beg, cnt, dval);
-      int32_t tot;
-      const int32_t off = block_exclusive_scan(d, sh, scan_call++, &tot);
-      if (e < n) {
-        poff[e] = carry + off;
-        if (d == 0) cur.cnt[e] = 0;  // deferred: no types this round
-      }
-      carry += tot;
-    }
-    __syncthreads();  // offsets and type ranges visible to every lane
-    const int32_t total = carry;
-    for (int32_t k0 = threadIdx.x; k0 < total; k0 += kBlock * U) {
-      int64_t jj[U];
-      int32_t tb[U], tn[U], xx[U];
-      bool ok[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int32_t k = k0 + u * kBlock;
-        ok[u] = k < total;
-        int32_t lo = 0, hi = ok[u] ? n : 0;  // first entry whose offset exceeds k
-        while (lo < hi) {
-          const int32_t mid = (lo + hi) >> 1;
-          if (poff[mid] <= k) lo = mid + 1; else hi = mid;
+      const uint64_t m = __ballot(go);
+      if (m) {
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        int32_t xb = 0;
+        if (lane == leader) xb = atomicAdd(xn, (int32_t)__popcll(m));
+        xb = __shfl(xb, leader);
+        if (go) {
+          const int32_t slot = xb + (int32_t)__popcll(m & ((1ull << lane) - 1ull));
+          X.item[slot] = item;
+          X.beg[slot] = beg;
+          X.cnt[slot] = cnt;
+          X.x[slot] = dval;
         }
-        const int32_t i = ok[u] ? lo - 1 : 0;
-        tb[u] = ok[u] ? cur.beg[i] : 0;
-        tn[u] = ok[u] ? cur.cnt[i] : 0;
-        jj[u] = ok[u] ? (int64_t)tb[u] + (k - poff[i]) : 0;
-        xx[u] = ok[u] ? S.value(cur.item[i]) : 0;
       }
-      relax_batch<KIND, U>(G, S, jj, tb, tn, xx, ok, P, c);
+    }
+    __syncthreads();  // X complete
+    const int32_t nx = *xn;
+    // Wave claims: each wave takes kClaim * U entries of X at a time from a
+    // shared cursor and spreads their connection types over its 64 lanes (a
+    // prefix sum of their counts in registers), U types per lane in flight,
+    // until X is used up.  No block-wide scan and no barrier inside.
+    constexpr int kC = kClaim * U;
+    for (;;) {
+      int32_t base = 0;
+      if (lane == 0) base = atomicAdd(cursor, kC);
+      base = __shfl(base, 0);
+      if (base >= nx) break;
+      int32_t beg = 0, cnt = 0, x = 0;
+      const int32_t e = base + lane;
+      if (lane < kC && e < nx) {
+        beg = X.beg[e];
+        cnt = X.cnt[e];
+        x = X.x[e];
+      }
+      int32_t eo[kC];  // entry offsets in the claim's type space
+      int32_t total = 0, off = 0;
+#pragma unroll
+      for (int i = 0; i < kC; ++i) {
+        eo[i] = total;
+        if (lane == i) off = total;
+        total += __shfl(cnt, i);
+      }
+      // wave-uniform trip count: the shuffles below read lanes 0 .. kC-1,
+      // which must be active (a shuffle from an inactive lane returns 0)
+      for (int32_t k0 = 0; k0 < total; k0 += 64 * U) {
+        int64_t jj[U];
+        int32_t tb[U], tn[U], xx[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int32_t k = k0 + lane + 64 * u;
+          ok[u] = k < total;
+          int32_t i = 0;  // last entry whose offset is <= k
+#pragma unroll
+          for (int t = 1; t < kC; ++t) i += (eo[t] <= k) ? 1 : 0;
+          const int32_t bi = __shfl(beg, i), oi = __shfl(off, i), xi = __shfl(x, i), ni = __shfl(cnt, i);
+          tb[u] = ok[u] ? bi : 0;
+          tn[u] = ok[u] ? ni : 0;
+          jj[u] = ok[u] ? (int64_t)bi + (k - oi) : 0;
+          xx[u] = ok[u] ? xi : 0;
+        }
+        relax_batch<KIND, U>(G, S, jj, tb, tn, xx, ok, P, c);
+      }
     }
   } else {
     constexpr int kGroups = kBlock / TPV;
@@ -715,8 +762,8 @@ struct QState {
 // (topology mode); every other bit is clear.  Returns false if the store
 // overflowed.
 template <int TPV, int KIND, int U, class Store>
-__device__ bool run_rounds(const RunArgs &a, const GraphG &G, const Store &S, int32_t n_items,
-                           const FList &list0, const FList &list1, int32_t *poff, bool topo,
+__device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, const Store &S, int32_t n_items,
+                           const FList &list0, const FList &list1, const XList &X, bool topo,
                            int32_t max_rounds, int32_t x0, Shared &sh, QState &qs, Ctr &c) {
   const int tid = threadIdx.x;
   const int32_t nwords = (n_items + 31) >> 5;
@@ -725,9 +772,10 @@ __device__ bool run_rounds(const RunArgs &a, const GraphG &G, const Store &S, in
   int32_t nf = topo ? 0 : 1;
   bool sweep = topo;
   int32_t rounds = 0;
-  int32_t scan_call = 0;
   if (tid < 3) {
     sh.nn[tid] = 0;
+    sh.cur[tid] = 0;
+    sh.xn[tid] = 0;
     sh.nmin[tid] = tid == 2 ? x0 : INF;  // "pushed before round 0": the first item
   }
   __syncthreads();
@@ -742,6 +790,8 @@ __device__ bool run_rounds(const RunArgs &a, const GraphG &G, const Store &S, in
     if (tid == 0) {
       sh.nn[(rounds + 1) % 3] = 0;
       sh.nmin[(rounds + 1) % 3] = INF;
+      sh.cur[(rounds + 1) % 3] = 0;
+      sh.xn[(rounds + 1) % 3] = 0;
     }
     // this round expands the items below the smallest arrival pushed for it
     // plus the window (that item itself always qualifies)
@@ -749,11 +799,15 @@ __device__ bool run_rounds(const RunArgs &a, const GraphG &G, const Store &S, in
     const int32_t thr = (a.window <= 0 || base >= INF - a.window) ? INF : base + a.window;
     const ListPush P{nxt, a.fcap, !topo, nn, &sh.nmin[rounds % 3]};
     if (!sweep) {
-      expand_list<TPV, KIND, U>(G, S, cur, nf, true, thr, P, sh, poff, scan_call, c);
+      expand_list<TPV, KIND, U>(G, S, cur, nf, true, thr, P, sh, X, &sh.xn[rounds % 3], &sh.cur[rounds % 3], c);
     } else {
       ++qs.sweeps;
       for (int32_t w0 = 0; w0 < nwords; w0 += chunk_words) {
-        if (tid == 0) sh.cnt = 0;
+        if (tid == 0) {
+          sh.cnt = 0;
+          sh.cnt2 = 0;
+          sh.xn2 = 0;
+        }
         __syncthreads();
         const int32_t w1 = min(w0 + chunk_words, nwords);
         for (int32_t w = w0 + tid; w < w1; w += kBlock) {
@@ -772,7 +826,7 @@ __device__ bool run_rounds(const RunArgs &a, const GraphG &G, const Store &S, in
         }
         __syncthreads();
         const int32_t cnt = sh.cnt;
-        if (cnt) expand_list<TPV, KIND, U>(G, S, cur, cnt, false, thr, P, sh, poff, scan_call, c);
+        if (cnt) expand_list<TPV, KIND, U>(G, S, cur, cnt, false, thr, P, sh, X, &sh.xn2, &sh.cnt2, c);
         __syncthreads();
       }
     }
@@ -874,12 +928,11 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
     bool done = false;
     if (a.table_cap > 0) {
       // ---- arrivals in the on-chip table ----------------------------------------
-      // LDS: keys[H] vals[H] bits[H/32] | two lists (item, beg, cnt) x F | offsets[F]
+      // LDS: {key, arrival}[H] bits[H/32] | two lists (item, beg, cnt) x F | X x F
       const int32_t H = a.table_cap;
       TableStore T;
-      T.keys = reinterpret_cast<int32_t *>(lds);
-      T.vals = T.keys + H;
-      T.bits = reinterpret_cast<uint32_t *>(T.vals + H);
+      T.kv = reinterpret_cast<int2 *>(lds);
+      T.bits = reinterpret_cast<uint32_t *>(T.kv + H);
       T.count = &sh.count;
       T.over = &sh.over;
       T.mask = (uint32_t)H - 1u;
@@ -887,27 +940,26 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       T.limit = H - H / 4;
       int32_t *l = reinterpret_cast<int32_t *>(T.bits + (H >> 5));
       const FList l0{l, l + F, l + 2 * F}, l1{l + 3 * F, l + 4 * F, l + 5 * F};
-      int32_t *poff = l + 6 * F;
+      const XList X{l + 6 * F, l + 7 * F, l + 8 * F, l + 9 * F};
       for (int32_t i = tid; i < H; i += kBlock) {
-        T.keys[i] = EMPTY;
-        T.vals[i] = INF;
+        T.kv[i] = make_int2(EMPTY, INF);
       }
       for (int32_t i = tid; i < (H >> 5); i += kBlock) T.bits[i] = 0u;
       __syncthreads();
       if (tid == 0) {
-        const int32_t p = T.slot(Q.s);  // empty table: always succeeds
-        T.vals[p] = Q.ts;
+        const int32_t p = T.slot(Q.s, -1);  // empty table: always succeeds
+        T.kv[p].y = Q.ts;
         T.bits[p >> 5] = 1u << (p & 31);
         l0.item[0] = p;
         l0.cnt[0] = -1;
       }
       __syncthreads();
-      if (run_rounds<TPV, KIND, U>(a, G, T, H, l0, l1, poff, topo, max_rounds, Q.ts, sh, qs, c)) {
+      if (run_rounds<TPV, KIND, U>(a, G, T, H, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c)) {
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the infinity fill has landed
         __syncthreads();
         for (int32_t p = tid; p < H; p += kBlock) {
-          const int32_t k = T.keys[p];
-          if (k != EMPTY) arr[k] = T.vals[p];
+          const int2 e = T.kv[p];
+          if (e.x != EMPTY) arr[e.x] = e.y;
         }
         if (tid == 0) sh.reached = sh.count;
         done = true;
@@ -915,7 +967,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
     }
     if (!done) {
       // ---- arrivals in the result slab (no table, or the table overflowed) ----------
-      // LDS: bits[ceil(V/32)] | two lists | offsets.  An overflowed table attempt
+      // LDS: bits[ceil(V/32)] | two lists | X.  An overflowed table attempt
       // never wrote the slab: it still holds infinity.
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
@@ -925,7 +977,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       const int32_t VW = (V + 31) >> 5;
       int32_t *l = reinterpret_cast<int32_t *>(lds + VW);
       const FList l0{l, l + F, l + 2 * F}, l1{l + 3 * F, l + 4 * F, l + 5 * F};
-      int32_t *poff = l + 6 * F;
+      const XList X{l + 6 * F, l + 7 * F, l + 8 * F, l + 9 * F};
       for (int32_t i = tid; i < VW; i += kBlock) S.bits[i] = 0u;
       if (tid == 0) sh.over = 0;
       __syncthreads();
@@ -937,7 +989,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       }
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
-      run_rounds<TPV, KIND, U>(a, G, S, V, l0, l1, poff, topo, max_rounds, Q.ts, sh, qs, c);
+      run_rounds<TPV, KIND, U>(a, G, S, V, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c);
       // reached stops
       int32_t mine = 0;
       for (int32_t i = tid; i < V; i += kBlock) mine += ld_arr(arr + i) != INF;
@@ -1024,25 +1076,37 @@ __global__ void k_build_grid(GraphDev Gd) {
     int32_t next = INF;
     for (int32_t k = G.n_clusters - 1; k >= 0; --k) {
       int4 e;
+      int4 e2 = make_int4(INF, INF, INF, INF);
       if ((m >> k) & 1ull) {
         const int2 h = G.hdr[idx--];
-        // progression step d >= 2: m = ceil(2^32 / d) <= 2^31; d = 1 (or no
-        // step: arrays, single terms): 0
-        const uint32_t d = h.y >= 0 ? (uint32_t)(h.y & 0xffff) : 0u;
-        const uint32_t mul = d >= 2 ? (uint32_t)((((uint64_t)1 << 32) + d - 1) / d) : 0u;
-        e = make_int4(h.x, h.y, next, (int32_t)mul);
+        if (h.y >= 0) {
+          // progression step d >= 2: m = ceil(2^32 / d) <= 2^31; d = 1 (or a
+          // single term): 0
+          const uint32_t d = (uint32_t)(h.y & 0xffff);
+          const uint32_t mul = d >= 2 ? (uint32_t)((((uint64_t)1 << 32) + d - 1) / d) : 0u;
+          e = make_int4(h.x, h.y, next, (int32_t)mul);
+        } else {
+          // sorted array pool[off] = n, pool[off + 1 ..] = departures: the
+          // entry keeps n and departures 2..5
+          const int32_t off = ~h.y, n = G.pool[off];
+          e = make_int4(h.x, h.y, next, n);
+          e2 = make_int4(n > 1 ? G.pool[off + 2] : INF, n > 2 ? G.pool[off + 3] : INF,
+                         n > 3 ? G.pool[off + 4] : INF, n > 4 ? G.pool[off + 5] : INF);
+        }
         next = h.x;
       } else {
         e = make_int4(next, (1 << 16) | 1, next, 0);
       }
-      grid[base + (int64_t)k * rng.y] = e;
+      const int64_t at = base + (int64_t)k * rng.y;
+      grid[2 * at] = e;
+      grid[2 * at + 1] = e2;
     }
   }
 }
 
 using RelaxFn = void (*)(RunArgs);
 
-// TPV = 0: load-balanced expansion with ub connection types in flight per lane
+// TPV = 0: wave-claim expansion with ub connection types in flight per lane
 // (1..3); TPV > 0: virtual warps of TPV lanes.
 template <int KIND>
 RelaxFn relax_fn(int tpv, int ub) {
