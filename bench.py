@@ -58,6 +58,9 @@ MODES = {"auto": 0, "topology": 2}  # eat_mode values
 # query (few queries per CU); a batch that fills the chip for its whole launch
 # only loses L2 locality to it.  Measured on MI355X.
 DEFAULT_STREAMS = {"city-1k": 4, "city-50k": 4, "region-500k": 2, "mixed": 1}
+# Threads per query: 512 puts two queries on a CU (more queries in flight),
+# 1024 finishes one long query sooner (region-500k's batch is one such query).
+DEFAULT_THREADS = {"city-1k": 1024, "city-50k": 512, "region-500k": 1024, "mixed": 512}
 HEADERS = {"auto": 0, "grid": 1, "compact": 2}  # eat_headers values
 
 
@@ -103,6 +106,9 @@ def main():
                     help="streams the timed steps alternate between (each with its own prepared "
                          "batch), so one launch's tail overlaps the next launch; 0 = per workload "
                          "(%s)" % ", ".join(f"{k} {v}" for k, v in DEFAULT_STREAMS.items()))
+    ap.add_argument("--threads", type=int, default=0, choices=(0, 512, 1024),
+                    help="threads per query (work-group size); 0 = per workload (%s)"
+                         % ", ".join(f"{k} {v}" for k, v in DEFAULT_THREADS.items()))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-query comparison")
     ap.add_argument("--no-verify", action="store_true")
@@ -244,7 +250,8 @@ def main():
     achieved = bytes_per_launch / (kernel_ms / 1e3) / 1e9
     traffic = None
     if (args.workload == "city-50k" and args.layout == "hybrid" and args.table == 0 and args.mode == "auto"
-            and args.headers == "auto" and args.window == 0 and args.tpv == 0 and args.types_per_lane == 0):
+            and args.headers == "auto" and args.window == 0 and args.tpv == 0 and args.types_per_lane == 0
+            and args.threads == 0):
         traffic = profiled_traffic(os.path.join(ROOT, "profiles", "k_relax_city-50k.md"),
                                    os.path.join(ROOT, "paper_1912_00966_amd", "csrc", "kernels.hip"))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -297,6 +304,7 @@ def main():
                    "connections": tt.n_conn, "queries_per_step": Q, "layout": args.layout,
                    "headers": ("grid" if grid else "compact") if args.layout == "hybrid" else None,
                    "mode": args.mode, "time_window": args.window, "streams": S,
+                   "threads_per_query": opts["threads_per_query"],
                    "graphs": 1, "digest": tt.digest()},
         "bit_exact": bit_exact,
         "one_stream": one_stream,
@@ -310,9 +318,12 @@ def main():
 
 
 def _opts(args):
+    threads = args.threads or DEFAULT_THREADS.get(args.workload, 1024)
+    if args.tpv:
+        threads = 1024  # virtual warps run in 1024-thread work-groups
     return {"threads_per_vertex": args.tpv, "types_per_lane": args.types_per_lane,
             "time_window": args.window, "table_cap": args.table, "mode": MODES[args.mode],
-            "headers": HEADERS[args.headers]}
+            "headers": HEADERS[args.headers], "threads_per_query": threads}
 
 
 def run_mixed(args, log):
@@ -404,7 +415,7 @@ def run_mixed(args, log):
         "config": {"workload": f"mixed batch ({args.reading} reading)",
                    "graphs": [t.n_vertices for t in tts], "queries_per_step": Q,
                    "connections": int(sum(t.n_conn for t in tts)), "time_window": args.window,
-                   "streams": S},
+                   "streams": S, "threads_per_query": _opts(args)["threads_per_query"]},
         "bit_exact": exact if not args.no_verify else None, "checked_vs_scan": checked,
         "certified": certified, "plain": plain,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -64,7 +64,7 @@ using eat::make_plan;
 struct eat_batch {
   int device = 0;
   int32_t n_q = 0;
-  int tpv = 0, ub = 1, kind = 0, grid = 0;
+  int tpv = 0, ub = 1, kind = 0, block = 1024, grid = 0;
   size_t lds = 0;
   RunArgs args{};
   void *d_buf = nullptr;
@@ -402,10 +402,16 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
     return set_err(EAT_ERR_INVALID_ARGUMENT, "unknown header form");
   pl->headers = o.headers;
   if (o.time_window < -1) return set_err(EAT_ERR_INVALID_ARGUMENT, "time_window must be >= -1");
+  if (o.threads_per_query != 0 && o.threads_per_query != kBlock && o.threads_per_query != kBlockSmall)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query must be 0, 512 or 1024");
+  pl->block = o.threads_per_query ? o.threads_per_query : kBlock;
+  if (pl->block == kBlockSmall && o.threads_per_vertex != 0)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query 512 needs threads_per_vertex 0");
   pl->window = o.time_window == 0 ? 7200 : (o.time_window < 0 ? 0 : o.time_window);
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;
-  int fcap = o.frontier_cap ? o.frontier_cap : 512;
+  const bool small = o.threads_per_query == kBlockSmall;
+  int fcap = o.frontier_cap ? o.frontier_cap : (small ? 256 : 512);
   fcap = (fcap + 31) / 32 * 32;
   DeviceLimits lim;
   eat_status s = device_limits(device, &lim);
@@ -422,7 +428,9 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   fcap = std::min(fcap, items);
   const size_t slab_lds = (size_t)pl->bm_words * 4 + lists_lds(fcap);
   auto need = [&](int h) { return std::max(table_lds(h, fcap), slab_lds); };
-  while (table_auto && H >= 64 && need(H) > lim.lds) H >>= 1;
+  // two 512-thread work-groups share a CU: each gets half its LDS
+  const size_t budget = small ? lim.lds / 2 - 512 : lim.lds;
+  while (table_auto && H >= 64 && need(H) > budget) H >>= 1;
   if (H < 64) H = 0;
   if (H && need(H) > lim.lds) return set_err(EAT_ERR_UNSUPPORTED, "table_cap too large for the device's LDS");
   pl->table_cap = H;
@@ -498,14 +506,14 @@ extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32
   if (!stats) {
     a.stats = nullptr;
     a.n_failed = nullptr;
-    hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, kind, 1, pl.lds, hs);
+    hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, kind, pl.block, 1, pl.lds, hs);
     if (e != hipSuccess) return hip_err(e, "relaxation launch");
     return EAT_OK;
   }
   std::lock_guard<std::mutex> lk(gm->mu);
   a.stats = gm->d_stats;
   a.n_failed = nullptr;
-  hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, kind, 1, pl.lds, hs);
+  hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, kind, pl.block, 1, pl.lds, hs);
   if (e != hipSuccess) return hip_err(e, "relaxation launch");
   HIP_TRY(hipMemcpyAsync(stats, gm->d_stats, sizeof(eat_query_stats), hipMemcpyDeviceToHost, hs));
   HIP_TRY(hipStreamSynchronize(hs));
@@ -567,6 +575,7 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   b->tpv = pl.tpv;
   b->ub = pl.ub;
   b->kind = kind;
+  b->block = pl.block;
   b->lds = pl.lds;
   const size_t b_g = align_up((size_t)n_graphs * sizeof(GraphDev));
   const size_t b_q = align_up(std::max<size_t>((size_t)n_q, 1) * sizeof(QueryDev));
@@ -596,7 +605,7 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
     delete b;
     return hip_err(e, "batch upload");
   }
-  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, pl.ub, kind, pl.lds));
+  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, pl.ub, kind, pl.block, pl.lds));
   b->grid = std::max(1, std::min<int>(n_q, lim.cus * per_cu));
   RunArgs &a = b->args;
   a.graphs = d_g;
@@ -616,7 +625,7 @@ extern "C" eat_status eat_batch_run(eat_batch *b, void *stream) {
   if (!b) return set_err(EAT_ERR_INVALID_ARGUMENT, "batch is NULL");
   if (b->n_q == 0) return EAT_OK;
   hipStream_t hs = static_cast<hipStream_t>(stream);
-  hipError_t e = eat::launch_relax(b->args, b->tpv, b->ub, b->kind, b->grid, b->lds, hs);
+  hipError_t e = eat::launch_relax(b->args, b->tpv, b->ub, b->kind, b->block, b->grid, b->lds, hs);
   if (e != hipSuccess) return hip_err(e, "relaxation launch");
   HIP_TRY(hipEventRecord(b->done, hs));
   b->ran = true;

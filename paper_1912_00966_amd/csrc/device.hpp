@@ -80,12 +80,13 @@ struct RunArgs {
   int64_t ns_per_tick;       // device wall clock period in ns (x 1024)
 };
 
-constexpr int kBlock = 1024;
+constexpr int kBlock = 1024;      // threads per query (work-group), default
+constexpr int kBlockSmall = 512;  // the alternative: two queries per CU
 constexpr int kMaxBuckets = 32;
 constexpr int kCounterWords = 4 + kMaxBuckets;
 
 // Host-side launchers (kernels.hip).
-hipError_t launch_relax(const RunArgs &a, int tpv, int ub, int kind, int grid, size_t lds_bytes,
+hipError_t launch_relax(const RunArgs &a, int tpv, int ub, int kind, int block, int grid, size_t lds_bytes,
                         hipStream_t stream);
 hipError_t launch_zero(int32_t *p, int n, hipStream_t stream);
 hipError_t launch_next_departure(const GraphDev *g_dev, int kind, const int32_t *type_ids,
@@ -93,6 +94,6 @@ hipError_t launch_next_departure(const GraphDev *g_dev, int kind, const int32_t 
 // Fills g.grid from the compact headers (g as on the host: device pointers).
 hipError_t launch_build_grid(const GraphDev &g, hipStream_t stream);
 // Work-groups of the relaxation kernel that fit on one CU with lds_bytes of LDS.
-int relax_blocks_per_cu(int tpv, int ub, int kind, size_t lds_bytes);
+int relax_blocks_per_cu(int tpv, int ub, int kind, int block, size_t lds_bytes);
 
 }  // namespace eat

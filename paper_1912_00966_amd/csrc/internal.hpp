@@ -57,6 +57,7 @@ struct Plan {
   int table_bits = 0;
   int headers = EAT_HEADERS_AUTO;
   int window = 0;  // seconds, 0 = none
+  int block = 1024; // threads per query
   int64_t ns_per_tick = 0;
   size_t lds = 0;
 };

@@ -617,7 +617,7 @@ struct Shared {
 //   per lane in flight (a load-balanced expansion without a block-wide scan).
 // TPV > 0: virtual warps (Section IV-B) -- groups of TPV lanes, one stop per
 //   group, lane i of a group takes the stop's types i, i + TPV, ...
-template <int TPV, int KIND, int U, class Store>
+template <int TPV, int KIND, int U, int B, class Store>
 __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, const FList &cur, int32_t n,
                                             bool clear, int32_t thr, const ListPush &P, Shared &sh,
                                             const XList &X, int32_t *xn, int32_t *cursor, Ctr &c) {
@@ -648,7 +648,7 @@ __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, con
     // arrival times are stable): deferred ones go to the next list, the
     // others to X, with their arrival, bits cleared.
     const int lane = __lane_id();
-    for (int32_t e0 = 0; e0 < n; e0 += kBlock) {
+    for (int32_t e0 = 0; e0 < n; e0 += B) {
       const int32_t e = e0 + (int32_t)threadIdx.x;
       bool defer = false, go = false;
       int32_t dval = INF, item = 0, beg = 0, cnt = 0;
@@ -724,11 +724,11 @@ __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, con
       }
     }
   } else {
-    constexpr int kGroups = kBlock / TPV;
+    constexpr int kGroups = B / TPV;
     const int g = threadIdx.x / TPV, lane = threadIdx.x % TPV;
     // take the entries (defer, clear bits, load unknown type ranges) before
     // any relaxation pushes
-    for (int32_t e0 = 0; e0 < n; e0 += kBlock) {
+    for (int32_t e0 = 0; e0 < n; e0 += B) {
       const int32_t e = e0 + (int32_t)threadIdx.x;
       bool defer = false;
       int32_t dval = INF, item = 0, beg = 0, cnt = 0;
@@ -761,7 +761,7 @@ struct QState {
 // is list0 entry 0 with its bit set (frontier mode), or only its bit is set
 // (topology mode); every other bit is clear.  Returns false if the store
 // overflowed.
-template <int TPV, int KIND, int U, class Store>
+template <int TPV, int KIND, int U, int B, class Store>
 __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, const Store &S, int32_t n_items,
                            const FList &list0, const FList &list1, const XList &X, bool topo,
                            int32_t max_rounds, int32_t x0, Shared &sh, QState &qs, Ctr &c) {
@@ -799,7 +799,7 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
     const int32_t thr = (a.window <= 0 || base >= INF - a.window) ? INF : base + a.window;
     const ListPush P{nxt, a.fcap, !topo, nn, &sh.nmin[rounds % 3]};
     if (!sweep) {
-      expand_list<TPV, KIND, U>(G, S, cur, nf, true, thr, P, sh, X, &sh.xn[rounds % 3], &sh.cur[rounds % 3], c);
+      expand_list<TPV, KIND, U, B>(G, S, cur, nf, true, thr, P, sh, X, &sh.xn[rounds % 3], &sh.cur[rounds % 3], c);
     } else {
       ++qs.sweeps;
       for (int32_t w0 = 0; w0 < nwords; w0 += chunk_words) {
@@ -810,7 +810,7 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
         }
         __syncthreads();
         const int32_t w1 = min(w0 + chunk_words, nwords);
-        for (int32_t w = w0 + tid; w < w1; w += kBlock) {
+        for (int32_t w = w0 + tid; w < w1; w += B) {
           uint32_t bits = S.bits[w];
           if (bits) {
             bits = atomicExch(&S.bits[w], 0u);  // claim: these items are expanded now
@@ -826,7 +826,7 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
         }
         __syncthreads();
         const int32_t cnt = sh.cnt;
-        if (cnt) expand_list<TPV, KIND, U>(G, S, cur, cnt, false, thr, P, sh, X, &sh.xn2, &sh.cnt2, c);
+        if (cnt) expand_list<TPV, KIND, U, B>(G, S, cur, cnt, false, thr, P, sh, X, &sh.xn2, &sh.cnt2, c);
         __syncthreads();
       }
     }
@@ -850,8 +850,8 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
   return true;
 }
 
-template <int TPV, int KIND, int U>
-__global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
+template <int TPV, int KIND, int U, int B>
+__global__ __launch_bounds__(B) void k_relax(RunArgs a) {
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ Shared sh;
 
@@ -919,10 +919,10 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       gp<int4> a4 = (gp<int4>)arr;
       const int32_t n4 = V >> 2;
       const int4 inf4 = make_int4(INF, INF, INF, INF);
-      for (int32_t i = tid; i < n4; i += kBlock) a4[i] = inf4;
-      for (int32_t i = (n4 << 2) + tid; i < V; i += kBlock) arr[i] = INF;
+      for (int32_t i = tid; i < n4; i += B) a4[i] = inf4;
+      for (int32_t i = (n4 << 2) + tid; i < V; i += B) arr[i] = INF;
     } else {
-      for (int32_t i = tid; i < V; i += kBlock) arr[i] = INF;
+      for (int32_t i = tid; i < V; i += B) arr[i] = INF;
     }
 
     bool done = false;
@@ -941,10 +941,10 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       int32_t *l = reinterpret_cast<int32_t *>(T.bits + (H >> 5));
       const FList l0{l, l + F, l + 2 * F}, l1{l + 3 * F, l + 4 * F, l + 5 * F};
       const XList X{l + 6 * F, l + 7 * F, l + 8 * F, l + 9 * F};
-      for (int32_t i = tid; i < H; i += kBlock) {
+      for (int32_t i = tid; i < H; i += B) {
         T.kv[i] = make_int2(EMPTY, INF);
       }
-      for (int32_t i = tid; i < (H >> 5); i += kBlock) T.bits[i] = 0u;
+      for (int32_t i = tid; i < (H >> 5); i += B) T.bits[i] = 0u;
       __syncthreads();
       if (tid == 0) {
         const int32_t p = T.slot(Q.s, -1);  // empty table: always succeeds
@@ -954,10 +954,10 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
         l0.cnt[0] = -1;
       }
       __syncthreads();
-      if (run_rounds<TPV, KIND, U>(a, G, T, H, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c)) {
+      if (run_rounds<TPV, KIND, U, B>(a, G, T, H, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c)) {
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the infinity fill has landed
         __syncthreads();
-        for (int32_t p = tid; p < H; p += kBlock) {
+        for (int32_t p = tid; p < H; p += B) {
           const int2 e = T.kv[p];
           if (e.x != EMPTY) arr[e.x] = e.y;
         }
@@ -978,7 +978,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       int32_t *l = reinterpret_cast<int32_t *>(lds + VW);
       const FList l0{l, l + F, l + 2 * F}, l1{l + 3 * F, l + 4 * F, l + 5 * F};
       const XList X{l + 6 * F, l + 7 * F, l + 8 * F, l + 9 * F};
-      for (int32_t i = tid; i < VW; i += kBlock) S.bits[i] = 0u;
+      for (int32_t i = tid; i < VW; i += B) S.bits[i] = 0u;
       if (tid == 0) sh.over = 0;
       __syncthreads();
       if (tid == 0) {
@@ -989,10 +989,10 @@ __global__ __launch_bounds__(kBlock) void k_relax(RunArgs a) {
       }
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
-      run_rounds<TPV, KIND, U>(a, G, S, V, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c);
+      run_rounds<TPV, KIND, U, B>(a, G, S, V, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c);
       // reached stops
       int32_t mine = 0;
-      for (int32_t i = tid; i < V; i += kBlock) mine += ld_arr(arr + i) != INF;
+      for (int32_t i = tid; i < V; i += B) mine += ld_arr(arr + i) != INF;
       if (mine) atomicAdd(&sh.reached, mine);
     }
 
@@ -1109,25 +1109,31 @@ using RelaxFn = void (*)(RunArgs);
 // TPV = 0: wave-claim expansion with ub connection types in flight per lane
 // (1..3); TPV > 0: virtual warps of TPV lanes.
 template <int KIND>
-RelaxFn relax_fn(int tpv, int ub) {
+RelaxFn relax_fn(int tpv, int ub, int block) {
+  if (block == kBlockSmall) {  // wave claims only
+    if (tpv != 0) return nullptr;
+    return ub == 1 ? k_relax<0, KIND, 1, kBlockSmall>
+                   : ub == 3 ? k_relax<0, KIND, 3, kBlockSmall> : k_relax<0, KIND, 2, kBlockSmall>;
+  }
+  if (block != kBlock) return nullptr;
   switch (tpv) {
-    case 0: return ub == 1 ? k_relax<0, KIND, 1> : ub == 3 ? k_relax<0, KIND, 3> : k_relax<0, KIND, 2>;
-    case 1: return k_relax<1, KIND, 1>;
-    case 2: return k_relax<2, KIND, 1>;
-    case 4: return k_relax<4, KIND, 1>;
-    case 8: return k_relax<8, KIND, 1>;
-    case 16: return k_relax<16, KIND, 1>;
-    case 32: return k_relax<32, KIND, 1>;
-    case 64: return k_relax<64, KIND, 1>;
+    case 0: return ub == 1 ? k_relax<0, KIND, 1, kBlock> : ub == 3 ? k_relax<0, KIND, 3, kBlock> : k_relax<0, KIND, 2, kBlock>;
+    case 1: return k_relax<1, KIND, 1, kBlock>;
+    case 2: return k_relax<2, KIND, 1, kBlock>;
+    case 4: return k_relax<4, KIND, 1, kBlock>;
+    case 8: return k_relax<8, KIND, 1, kBlock>;
+    case 16: return k_relax<16, KIND, 1, kBlock>;
+    case 32: return k_relax<32, KIND, 1, kBlock>;
+    case 64: return k_relax<64, KIND, 1, kBlock>;
     default: return nullptr;
   }
 }
 
-RelaxFn pick(int tpv, int ub, int kind) {
+RelaxFn pick(int tpv, int ub, int kind, int block) {
   switch (kind) {
-    case kKindCompact: return relax_fn<kKindCompact>(tpv, ub);
-    case kKindFlat: return relax_fn<kKindFlat>(tpv, ub);
-    case kKindGrid: return relax_fn<kKindGrid>(tpv, ub);
+    case kKindCompact: return relax_fn<kKindCompact>(tpv, ub, block);
+    case kKindFlat: return relax_fn<kKindFlat>(tpv, ub, block);
+    case kKindGrid: return relax_fn<kKindGrid>(tpv, ub, block);
     default: return nullptr;
   }
 }
@@ -1148,22 +1154,22 @@ hipError_t allow_lds(RelaxFn f, size_t bytes) {
 
 }  // namespace
 
-hipError_t launch_relax(const RunArgs &a, int tpv, int ub, int kind, int grid, size_t lds_bytes,
+hipError_t launch_relax(const RunArgs &a, int tpv, int ub, int kind, int block, int grid, size_t lds_bytes,
                         hipStream_t stream) {
-  RelaxFn f = pick(tpv, ub, kind);
+  RelaxFn f = pick(tpv, ub, kind, block);
   if (!f) return hipErrorInvalidValue;
   hipError_t e = allow_lds(f, lds_bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(f, dim3(grid), dim3(kBlock), lds_bytes, stream, a);
+  hipLaunchKernelGGL(f, dim3(grid), dim3(block), lds_bytes, stream, a);
   return hipGetLastError();
 }
 
-int relax_blocks_per_cu(int tpv, int ub, int kind, size_t lds_bytes) {
-  RelaxFn f = pick(tpv, ub, kind);
+int relax_blocks_per_cu(int tpv, int ub, int kind, int block, size_t lds_bytes) {
+  RelaxFn f = pick(tpv, ub, kind, block);
   if (!f) return 0;
   if (allow_lds(f, lds_bytes) != hipSuccess) return 0;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(f), kBlock,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(f), block,
                                                    lds_bytes) != hipSuccess)
     return 0;
   return nb;

@@ -190,7 +190,7 @@ extern "C" eat_status eat_session_create(const eat_graph *const *graphs, int32_t
   S->plan = pl;
   S->kind = kind;
   S->max_step = max_step;
-  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, pl.ub, kind, pl.lds));
+  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, pl.ub, kind, pl.block, pl.lds));
   S->grid_cap = lim.cus * per_cu;
   S->n_buckets = std::min(lim.xccs, eat::kMaxBuckets);
   S->pool_words = pool_bytes / 4 / kSlotAlignWords * kSlotAlignWords;
@@ -312,7 +312,7 @@ extern "C" eat_status eat_session_step(eat_session *S, int32_t *n_launched) {
   a.stats = b.d_stats;
   a.n_failed = b.d_ctr + 1;
   const int grid = std::max(1, std::min(n, S->grid_cap));
-  hipError_t e = eat::launch_relax(a, S->plan.tpv, S->plan.ub, S->kind, grid, S->plan.lds, b.stream);
+  hipError_t e = eat::launch_relax(a, S->plan.tpv, S->plan.ub, S->kind, S->plan.block, grid, S->plan.lds, b.stream);
   if (e != hipSuccess) return hip_err(e, "relaxation launch");
   HIP_TRY(hipMemcpyAsync(b.h_stats, b.d_stats, sizeof(eat_query_stats) * (size_t)n, hipMemcpyDeviceToHost,
                          b.stream));

@@ -87,7 +87,7 @@ class RunOptions(ctypes.Structure):
                 ("max_rounds", ctypes.c_int32), ("frontier_cap", ctypes.c_int32),
                 ("table_cap", ctypes.c_int32), ("types_per_lane", ctypes.c_int32),
                 ("headers", ctypes.c_int32), ("time_window", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("threads_per_query", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
 
 
 class QueryStats(ctypes.Structure):
