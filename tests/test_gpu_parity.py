@@ -439,3 +439,29 @@ def test_autotuner_picks_an_exact_configuration(tmp_path):
     assert best2 == best  # served from the cache
     got, _ = _query(g, int(q.s[3]), int(q.ts[3]), **best)
     assert np.array_equal(got, _expected("city-1k")[3])
+    # timed over two streams, with 512-thread queries among the candidates
+    cands2 = [{"threads_per_query": 512}, {"threads_per_query": 1024}]
+    best3, results3 = autotune.tune([g], np.zeros(len(q), np.int32), q.s, q.ts, reps=2,
+                                    cache_path=None, cands=cands2, streams=2)
+    assert best3 in cands2 and len(results3) == 2
+
+
+def test_concurrent_batches_on_several_streams():
+    """Prepared batches of the same graph run concurrently on four streams (the
+    way bench.py overlaps steps); every stream's slabs stay exact."""
+    tt, q = _workload("city-50k")
+    g = _graph("city-50k", "hybrid")
+    exp = _expected("city-50k")
+    V, Q = tt.n_vertices, len(q)
+    slabs = [torch.full((Q, V), -7, dtype=torch.int32, device="cuda") for _ in range(4)]
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(3)]
+    batches = [eat.Batch([g], np.zeros(Q, np.int32), q.s, q.ts, [sl[i] for i in range(Q)],
+                         options={"threads_per_query": 512 if k % 2 else 1024}) for k, sl in enumerate(slabs)]
+    _say("concurrent batches on 4 streams")
+    for i in range(12):
+        batches[i % 4].run(streams[i % 4])
+    torch.cuda.synchronize()
+    for b, sl in zip(batches, slabs):
+        assert b.wait(stats=True) is not None
+        assert np.array_equal(sl.cpu().numpy(), exp)
+        b.free()
