@@ -603,6 +603,7 @@ struct Shared {
   int32_t cur[3];               // wave-claim cursor of round r: cur[r % 3]
   int32_t xn[3];                // stops expanded in round r: xn[r % 3]
   int32_t cnt2, xn2;            // the same two for a sweep chunk
+  int32_t wcur, resume;         // sweep: next word to claim, first word of the next chunk
   unsigned long long acc[5];
 };
 
@@ -767,7 +768,6 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
                            int32_t max_rounds, int32_t x0, Shared &sh, QState &qs, Ctr &c) {
   const int tid = threadIdx.x;
   const int32_t nwords = (n_items + 31) >> 5;
-  const int32_t chunk_words = a.fcap >> 5;  // a sweep stages at most fcap items at a time
   FList cur = list0, nxt = list1;
   int32_t nf = topo ? 0 : 1;
   bool sweep = topo;
@@ -802,30 +802,52 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
       expand_list<TPV, KIND, U, B>(G, S, cur, nf, true, thr, P, sh, X, &sh.xn[rounds % 3], &sh.cur[rounds % 3], c);
     } else {
       ++qs.sweeps;
-      for (int32_t w0 = 0; w0 < nwords; w0 += chunk_words) {
+      // Chunks of up to fcap items: threads claim words from a shared cursor
+      // and stage a word's items only if all of them fit (bits are stable:
+      // no relaxation runs while staging); the next chunk resumes at the
+      // first word that did not fit.
+      if (tid == 0) sh.wcur = 0;
+      for (;;) {
         if (tid == 0) {
           sh.cnt = 0;
           sh.cnt2 = 0;
           sh.xn2 = 0;
+          sh.resume = nwords;
         }
         __syncthreads();
-        const int32_t w1 = min(w0 + chunk_words, nwords);
-        for (int32_t w = w0 + tid; w < w1; w += B) {
+        if (sh.wcur >= nwords) break;  // uniform: read after the barrier
+        for (;;) {
+          const int32_t w = atomicAdd(&sh.wcur, 1);
+          if (w >= nwords) break;
           uint32_t bits = S.bits[w];
-          if (bits) {
-            bits = atomicExch(&S.bits[w], 0u);  // claim: these items are expanded now
-            int32_t pos = atomicAdd(&sh.cnt, (int32_t)__popc(bits));
-            while (bits) {
-              const int b = __ffs(bits) - 1;
-              bits &= bits - 1u;
-              cur.item[pos] = (w << 5) + b;
-              cur.cnt[pos] = -1;
-              ++pos;
+          if (!bits) continue;
+          const int32_t pc = (int32_t)__popc(bits);
+          int32_t pos = lds_ld(&sh.cnt);
+          bool fits = false;
+          while (pos + pc <= a.fcap) {
+            const int32_t seen = atomicCAS(&sh.cnt, pos, pos + pc);
+            if (seen == pos) {
+              fits = true;
+              break;
             }
+            pos = seen;
+          }
+          if (!fits) {  // the chunk is full: this word starts the next one
+            atomicMin(&sh.resume, w);
+            break;
+          }
+          S.bits[w] = 0u;  // claimed: these items are expanded now
+          while (bits) {
+            const int b = __ffs(bits) - 1;
+            bits &= bits - 1u;
+            cur.item[pos] = (w << 5) + b;
+            cur.cnt[pos] = -1;
+            ++pos;
           }
         }
         __syncthreads();
         const int32_t cnt = sh.cnt;
+        if (tid == 0) sh.wcur = min(sh.wcur, sh.resume);  // read by all after the next barrier
         if (cnt) expand_list<TPV, KIND, U, B>(G, S, cur, cnt, false, thr, P, sh, X, &sh.xn2, &sh.cnt2, c);
         __syncthreads();
       }
