@@ -411,7 +411,9 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;
   const bool small = o.threads_per_query == kBlockSmall;
-  int fcap = o.frontier_cap ? o.frontier_cap : (small ? 256 : 512);
+  // default list capacity: the largest that still leaves room for a
+  // 16,384-slot table (1024 threads) or an 8,192-slot one (512 threads)
+  int fcap = o.frontier_cap ? o.frontier_cap : (small ? 256 : 704);
   fcap = (fcap + 31) / 32 * 32;
   DeviceLimits lim;
   eat_status s = device_limits(device, &lim);
