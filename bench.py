@@ -57,7 +57,7 @@ MODES = {"auto": 0, "topology": 2}  # eat_mode values
 # Overlapping consecutive batches pays when a batch is shorter than its slowest
 # query (few queries per CU); a batch that fills the chip for its whole launch
 # only loses L2 locality to it.  Measured on MI355X.
-DEFAULT_STREAMS = {"city-1k": 4, "city-50k": 4, "region-500k": 2, "mixed": 1}
+DEFAULT_STREAMS = {"city-1k": 4, "city-50k": 4, "region-500k": 2, "mixed": 2}
 # Threads per query: 512 puts two queries on a CU (more queries in flight),
 # 1024 finishes one long query sooner (region-500k's batch is one such query).
 DEFAULT_THREADS = {"city-1k": 1024, "city-50k": 512, "region-500k": 1024, "mixed": 512}
