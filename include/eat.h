@@ -196,7 +196,8 @@ typedef struct {
   int32_t mode;               /* eat_mode */
   int32_t max_rounds;         /* round limit per query; 0 = n_vertices + 2 without a time
                                  window, 8 * n_vertices + 64 with one */
-  int32_t frontier_cap;       /* frontier list entries kept on chip; 0 = auto */
+  int32_t frontier_cap;       /* frontier list entries kept on chip, rounded up to a
+                                 multiple of 64; 0 = auto */
   int32_t table_cap;          /* on-chip arrival-table slots (power of two); 0 = auto,
                                  -1 = keep arrivals in the result slab (HBM) only */
   int32_t types_per_lane;     /* wave claims: each wave takes 4 * types_per_lane listed

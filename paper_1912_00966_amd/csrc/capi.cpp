@@ -357,7 +357,7 @@ namespace eat {
 // expand list of (item, type begin, type count, arrival), fcap entries each,
 // plus the arrival table or the stop bitmap.
 static size_t lists_lds(int fcap) { return (size_t)fcap * 40; }
-static size_t table_lds(int H, int fcap) { return (size_t)H * 8 + (size_t)(H / 32) * 4 + lists_lds(fcap); }
+static size_t table_lds(int H, int fcap) { return (size_t)H * 8 + lists_lds(fcap); }
 
 eat_status exec_kind(const eat_graph *const *g, int32_t n, int headers, int *kind) {
   if (headers < EAT_HEADERS_AUTO || headers > EAT_HEADERS_COMPACT)
@@ -414,7 +414,9 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   // default list capacity: the largest that still leaves room for a
   // 16,384-slot table (1024 threads) or an 8,192-slot one (512 threads)
   int fcap = o.frontier_cap ? o.frontier_cap : (small ? 256 : 704);
-  fcap = (fcap + 31) / 32 * 32;
+  // a multiple of 64, at least 64: a sweep stages the active items of 64
+  // consecutive items at once, which must fit an empty list
+  fcap = (fcap + 63) / 64 * 64;
   DeviceLimits lim;
   eat_status s = device_limits(device, &lim);
   if (s != EAT_OK) return s;
@@ -426,7 +428,7 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
     H = o.table_cap;
   }
   // a frontier never holds more items than there are stops (or table slots)
-  const int items = std::max(32, (std::max(max_v, H) + 31) / 32 * 32);
+  const int items = std::max(64, (std::max(max_v, H) + 63) / 64 * 64);
   fcap = std::min(fcap, items);
   const size_t slab_lds = (size_t)pl->bm_words * 4 + lists_lds(fcap);
   auto need = [&](int h) { return std::max(table_lds(h, fcap), slab_lds); };

@@ -365,147 +365,199 @@ struct FList {
   int32_t *cnt;
 };
 
-// The stops a round expands, with their arrival times (wave-claim expansion).
-struct XList {
-  int32_t *item;
-  int32_t *beg;
-  int32_t *cnt;
-  int32_t *x;
-};
+// The stops a round expands (wave-claim expansion): {first type, type count,
+// arrival time, item} per entry, read by a claiming wave in one 16-byte load.
+using XList = int4 *;
 
-// Push: wave64 ballot, one LDS atomic per wave, lane offsets by masked
-// population count.
-__device__ __forceinline__ void push(bool want, int32_t item, int32_t beg, int32_t cnt, int32_t val,
-                                     const FList &nxt, int32_t fcap, bool append, int32_t *nn,
-                                     int32_t *nmin) {
-  const uint64_t m = __ballot(want);
-  if (m == 0) return;
-  const int lane = __lane_id();
-  const int leader = __ffsll((unsigned long long)m) - 1;
-  // smallest arrival pushed by the wave (lane reads, not shuffles: only the
-  // pushing lanes are sure to be active)
-  int32_t mv = INF;
-  for (uint64_t mm = m; mm; mm &= mm - 1ull) mv = min(mv, __builtin_amdgcn_readlane(val, __ffsll((unsigned long long)mm) - 1));
-  int32_t base = 0;
-  if (lane == leader) {
-    atomicMin(nmin, mv);  // smallest arrival pushed for the next round
-    base = atomicAdd(nn, (int32_t)__popcll(m));
-  }
-  base = __shfl(base, leader);
-  if (want && append) {
-    const int32_t slot = base + (int32_t)__popcll(m & ((1ull << lane) - 1ull));
-    if (slot < fcap) {
-      nxt.item[slot] = item;
-      nxt.beg[slot] = beg;
-      nxt.cnt[slot] = cnt;
-    }
-  }
-}
-
-// Pushes into the next round's list (bulk-synchronous rounds).
+// Pushes into the next round's list.  The list's entry count is the low half
+// of a 64-bit LDS word whose high half counts the round's X entries, so the
+// take pass books both with one atomic.  The smallest arrival a lane pushes is
+// kept in a register and reduced once per round (wave_min).
 struct ListPush {
   FList nxt;
   int32_t fcap;
   bool append;
-  int32_t *nn;
-  int32_t *nmin;
-  __device__ __forceinline__ void operator()(bool want, int32_t item, int32_t beg, int32_t cnt,
-                                             int32_t val) const {
-    push(want, item, beg, cnt, val, nxt, fcap, append, nn, nmin);
+  unsigned long long *cx;
+  int32_t lmin;
+  // wave64 ballot, one LDS atomic per wave, lane offsets by masked population count
+  __device__ __forceinline__ void operator()(bool want, int32_t item, int32_t beg, int32_t cnt, int32_t val) {
+    const uint64_t m = __ballot(want);
+    if (m == 0) return;
+    if (want) lmin = min(lmin, val);
+    const int lane = __lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = (uint32_t)atomicAdd(cx, (unsigned long long)__popcll(m));
+    base = (uint32_t)__builtin_amdgcn_readlane((int32_t)base, leader);
+    if (want && append) {
+      const int32_t slot = (int32_t)base + (int32_t)__popcll(m & ((1ull << lane) - 1ull));
+      if (slot < fcap) {
+        nxt.item[slot] = item;
+        nxt.beg[slot] = beg;
+        nxt.cnt[slot] = cnt;
+      }
+    }
   }
 };
+
+// Minimum over the 64 lanes of a wave, every lane active: DPP steps inside
+// rows of 16 lanes, then row broadcasts; lane 63 ends with the minimum.
+__device__ __forceinline__ int32_t wave_min(int32_t v) {
+  v = min(v, __builtin_amdgcn_update_dpp(INF, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = min(v, __builtin_amdgcn_update_dpp(INF, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = min(v, __builtin_amdgcn_update_dpp(INF, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = min(v, __builtin_amdgcn_update_dpp(INF, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = min(v, __builtin_amdgcn_update_dpp(INF, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = min(v, __builtin_amdgcn_update_dpp(INF, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
+}
 
 __device__ __forceinline__ int32_t lds_ld(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // ---------------------------------------------------------------------------
-// Where a query keeps its arrival times.  An "item" names one stop's entry;
-// `bits` holds one activity bit per item: set when the item's arrival
-// improves (and it is pushed), cleared when the item is taken for expansion
-// (the active / nextactive flags of Section III-B).
+// Where a query keeps its arrival times.  An "item" names one stop's entry.
+// Each item carries an activity flag: set when the item's arrival improves
+// (and it is pushed), cleared when the item is taken for expansion (the active
+// / nextactive flags of Section III-B).  Both stores offer:
+//   find(v, pos)              arrival of stop v (INF if none yet), pos = where
+//   improve(v, pos, av, cand, item, c)
+//                             lower v's arrival to cand < av (av, pos from
+//                             find); true if the item was not active, i.e.
+//                             the caller pushes it; item = v's item
+//   value / stop / active / deactivate / reactivate   per item
+//   claim_group(g, lane, act) a sweep stages every active item of items
+//                             [64 g, 64 g + 64): clear their flags
+//   full()                    the store overflowed (checked between rounds)
 // ---------------------------------------------------------------------------
 
-// In the caller's result slab (HBM); item = stop id.
+__device__ __forceinline__ bool mark_improved(uint32_t *bits, int32_t it) {
+  const uint32_t bit = 1u << (it & 31);
+  return !(atomicOr(&bits[it >> 5], bit) & bit);
+}
+
+// In the caller's result slab (HBM), item = stop id; one activity bit per
+// stop in LDS.
 struct SlabStore {
   gp<int32_t> arr;
   uint32_t *bits;
+  int32_t n;
   __device__ __forceinline__ int32_t stop(int32_t item) const { return item; }
   __device__ __forceinline__ int32_t value(int32_t item) const { return ld_arr(arr + item); }
   __device__ __forceinline__ int32_t find(int32_t v, int32_t &pos) const {
     pos = v;
     return ld_arr(arr + v);
   }
-  __device__ __forceinline__ int32_t slot(int32_t v, int32_t) const { return v; }
-  __device__ __forceinline__ int32_t lower(int32_t item, int32_t cand) const { return min_arr(arr + item, cand); }
+  __device__ __forceinline__ bool improve(int32_t v, int32_t, int32_t, int32_t cand, int32_t &item, Ctr &c) const {
+    item = v;
+    if (cand < min_arr(arr + v, cand)) {
+      c.imp++;
+      return mark_improved(bits, v);
+    }
+    return false;
+  }
+  __device__ __forceinline__ bool active(int32_t item) const {
+    return (lds_ld(reinterpret_cast<int32_t *>(bits) + (item >> 5)) >> (item & 31)) & 1;
+  }
+  __device__ __forceinline__ void deactivate(int32_t item) const { atomicAnd(&bits[item >> 5], ~(1u << (item & 31))); }
+  __device__ __forceinline__ bool reactivate(int32_t item) const { return mark_improved(bits, item); }
+  __device__ __forceinline__ void claim_group(int32_t g, int lane, bool) const {
+    // items 64 g .. 64 g + 63 are words 2 g and 2 g + 1; no relaxation runs
+    const int32_t first = (g << 6) + lane;
+    if ((lane & 31) == 0 && first < n) bits[first >> 5] = 0u;
+  }
+  __device__ __forceinline__ bool full() const { return false; }
 };
 
 // In an on-chip open-addressing hash table (LDS) of the stops the query has
-// touched; item = table slot.  The result slab only receives the final values.
-constexpr int32_t EMPTY = -1;
+// touched, item = table slot; the result slab only receives the final values.
+// A slot is one 64-bit word: arrival time in the high half, the idle flag
+// (set = not active) and the stop id in the low half.  One 64-bit atomic
+// minimum with {candidate, stop, flag clear} then lowers the arrival, makes the
+// item active and tells whether it was idle.  An equal candidate never reaches
+// an idle slot: within a relaxation phase flags only go from idle to active and
+// arrivals only drop, and a candidate is tried only below the arrival find()
+// read, so an arrival equal to it was set during the phase, flag clear.
+constexpr uint32_t IDLE = 0x80000000u;
+constexpr uint32_t NO_KEY = 0xffffffffu;  // low half of an empty slot (idle, no stop)
+constexpr unsigned long long EMPTY_SLOT = ((unsigned long long)(uint32_t)INF << 32) | NO_KEY;
 struct TableStore {
-  int2 *kv;        // {stop id or EMPTY, arrival time (INF until lowered)}
-  uint32_t *bits;
+  unsigned long long *kv;
   int32_t *count;  // slots in use
-  int32_t *over;   // set when the table is too full to take another stop
+  int32_t *over;   // set when a stop found no slot
   uint32_t mask;
   int32_t shift;
-  int32_t limit;
+  int32_t limit;   // more slots in use than this (checked between rounds): overflow
   __device__ __forceinline__ uint32_t home(int32_t v) const { return ((uint32_t)v * 2654435761u) >> shift; }
-  __device__ __forceinline__ int32_t stop(int32_t item) const { return lds_ld(&kv[item].x); }
-  __device__ __forceinline__ int32_t value(int32_t item) const { return lds_ld(&kv[item].y); }
-  // both halves of slot p in one 8-byte read
-  __device__ __forceinline__ int2 entry(uint32_t p) const {
-    const unsigned long long e =
-        __hip_atomic_load(reinterpret_cast<unsigned long long *>(kv + p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    return make_int2((int32_t)(uint32_t)e, (int32_t)(uint32_t)(e >> 32));
+  __device__ __forceinline__ int32_t *lo(int32_t p) const { return reinterpret_cast<int32_t *>(kv + p); }
+  __device__ __forceinline__ int32_t *hi(int32_t p) const { return reinterpret_cast<int32_t *>(kv + p) + 1; }
+  __device__ __forceinline__ unsigned long long entry(uint32_t p) const {
+    return __hip_atomic_load(kv + p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
-  // arrival of v, INF when v is not in the table (yet); pos = v's slot, or the
-  // empty slot where it would go (entries are never removed, so a later
-  // insertion of v lands at pos or after it)
+  __device__ __forceinline__ int32_t stop(int32_t item) const { return (int32_t)((uint32_t)lds_ld(lo(item)) & ~IDLE); }
+  __device__ __forceinline__ int32_t value(int32_t item) const { return lds_ld(hi(item)); }
+  // pos = v's slot, or the empty slot where it would go (slots are never
+  // freed, so a later insertion of v lands at pos or after it); -1 if full
   __device__ __forceinline__ int32_t find(int32_t v, int32_t &pos) const {
     uint32_t p = home(v);
     for (uint32_t n = 0; n <= mask; ++n) {
-      const int2 e = entry(p);
+      const unsigned long long e = entry(p);
       pos = (int32_t)p;
-      if (e.x == v) return e.y;
-      if (e.x == EMPTY) return INF;
+      const uint32_t key = (uint32_t)e;
+      if ((key & ~IDLE) == (uint32_t)v) return (int32_t)(e >> 32);
+      if (key == NO_KEY) return INF;
       p = (p + 1u) & mask;
     }
     pos = -1;
     return INF;
   }
-  // slot of v, inserting it, probing from the position find() gave; -1 (and
-  // *over = 1) when the table is full
-  __device__ __forceinline__ int32_t slot(int32_t v, int32_t hint) const {
-    uint32_t p = hint >= 0 ? (uint32_t)hint : home(v);
-    for (uint32_t n = 0; n <= mask; ++n) {
-      const int32_t k = lds_ld(&kv[p].x);
-      if (k == v) return (int32_t)p;
-      if (k == EMPTY) {
-        if (lds_ld(count) >= limit) break;
-        const int32_t old = atomicCAS(&kv[p].x, EMPTY, v);
-        if (old == EMPTY) {
-          atomicAdd(count, 1);
-          return (int32_t)p;
+  __device__ __forceinline__ bool improve(int32_t v, int32_t pos, int32_t av, int32_t cand, int32_t &item,
+                                          Ctr &c) const {
+    const unsigned long long want = ((unsigned long long)(uint32_t)cand << 32) | (uint32_t)v;
+    if (pos >= 0) {
+      uint32_t p = (uint32_t)pos;
+      // what find() saw at pos: v (every stored arrival is finite) or no stop
+      uint32_t key = av != INF ? (uint32_t)v : NO_KEY;
+      for (uint32_t n = 0; n <= mask; ++n) {
+        if (key == NO_KEY) {
+          const unsigned long long old = atomicCAS(kv + p, EMPTY_SLOT, want);
+          if (old == EMPTY_SLOT) {
+            atomicAdd(count, 1);
+            item = (int32_t)p;
+            c.imp++;
+            return true;
+          }
+          key = (uint32_t)old;
         }
-        if (old == v) return (int32_t)p;
+        if ((key & ~IDLE) == (uint32_t)v) {
+          const unsigned long long old = atomicMin(kv + p, want);
+          item = (int32_t)p;
+          if (cand < (int32_t)(old >> 32)) {
+            c.imp++;
+            return ((uint32_t)old & IDLE) != 0u;
+          }
+          return false;
+        }
+        p = (p + 1u) & mask;
+        key = (uint32_t)lds_ld(lo((int32_t)p));
       }
-      p = (p + 1u) & mask;
     }
     __hip_atomic_store(over, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    return -1;
+    return false;
   }
-  __device__ __forceinline__ int32_t lower(int32_t item, int32_t cand) const { return atomicMin(&kv[item].y, cand); }
+  __device__ __forceinline__ bool active(int32_t item) const { return !((uint32_t)lds_ld(lo(item)) & IDLE); }
+  __device__ __forceinline__ void deactivate(int32_t item) const {
+    atomicOr(reinterpret_cast<uint32_t *>(lo(item)), IDLE);
+  }
+  __device__ __forceinline__ bool reactivate(int32_t item) const {
+    return (atomicAnd(reinterpret_cast<uint32_t *>(lo(item)), ~IDLE) & IDLE) != 0u;
+  }
+  __device__ __forceinline__ void claim_group(int32_t g, int lane, bool act) const {
+    if (act) deactivate((g << 6) + lane);
+  }
+  __device__ __forceinline__ bool full() const { return lds_ld(count) > limit; }
 };
-
-// After a successful atomic minimum on item: set the item's bit; the lane that
-// sets it pushes the item (the caller holds the stop's type range).
-template <class Store>
-__device__ __forceinline__ bool mark_improved(const Store &S, int32_t it) {
-  const uint32_t bit = 1u << (it & 31);
-  return !(atomicOr(&S.bits[it >> 5], bit) & bit);
-}
 
 // Relax (Algorithm 3) U connection types per lane, with their memory reads
 // overlapped: all type records (and, for the grid, the grid entries, whose
@@ -516,7 +568,7 @@ __device__ __forceinline__ bool mark_improved(const Store &S, int32_t it) {
 template <int KIND, int U, class Store, class Push>
 __device__ __forceinline__ void relax_batch(const GraphG &G, const Store &S, const int64_t *j,
                                             const int32_t *tb, const int32_t *tn, const int32_t *x,
-                                            const bool *ok, const Push &P, Ctr &c) {
+                                            const bool *ok, Push &P, Ctr &c) {
   int4 r[U], r2[U];
   Look L[U];
 #pragma unroll
@@ -567,16 +619,8 @@ __device__ __forceinline__ void relax_batch(const GraphG &G, const Store &S, con
       if (tc != INF) {
         const int32_t cand = tc + r[u].y;
         if (cand < av[u]) {
-          const int32_t it = S.slot(r[u].x, pos[u]);
-          if (it >= 0) {
-            const int32_t old = S.lower(it, cand);
-            if (cand < old) {
-              c.imp++;
-              want[u] = mark_improved(S, it);
-              item[u] = it;
-              val[u] = cand;
-            }
-          }
+          want[u] = S.improve(r[u].x, pos[u], av[u], cand, item[u], c);
+          val[u] = cand;
         }
       }
     }
@@ -591,119 +635,121 @@ __device__ __forceinline__ void relax_batch(const GraphG &G, const Store &S, con
 // One connection type per lane.
 template <int KIND, class Store, class Push>
 __device__ __forceinline__ void relax(const GraphG &G, const Store &S, int64_t j, int32_t b, int32_t n, int32_t x,
-                                      const Push &P, Ctr &c) {
+                                      Push &P, Ctr &c) {
   const bool ok = true;
   relax_batch<KIND, 1>(G, S, &j, &b, &n, &x, &ok, P, c);
 }
 
 struct Shared {
   int32_t q, cnt, count, over, reached;
-  int32_t nn[3];                // pushes of round r go to nn[r % 3]
   int32_t nmin[3];              // smallest arrival pushed in round r: nmin[r % 3]
   int32_t cur[3];               // wave-claim cursor of round r: cur[r % 3]
-  int32_t xn[3];                // stops expanded in round r: xn[r % 3]
-  int32_t cnt2, xn2;            // the same two for a sweep chunk
-  int32_t wcur, resume;         // sweep: next word to claim, first word of the next chunk
+  int32_t wcur, resume;         // sweep: next group to claim, first group of the next chunk
+  unsigned long long cx[3];     // round r: low half entries pushed, high half X entries (per sweep chunk)
   unsigned long long acc[5];
 };
 
+__device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
+
 // Expand the entries of list[0..n) whose arrival is below thr; the others
-// are deferred: they go to the next list unexpanded, with their bit still set
-// (re-set after a sweep, which claimed it), so a later round expands them.
-// An expanded entry's bit is cleared (with `clear`; a sweep has claimed them
-// already) before its arrival time is read, so an improvement that lands
-// later pushes it again.
-// TPV == 0: wave claims -- each wave takes 4 * U entries at a time from a
-//   shared cursor and spreads their connection types over its lanes, U types
-//   per lane in flight (a load-balanced expansion without a block-wide scan).
+// are deferred: they go to the next list unexpanded, still active (made
+// active again after a sweep, which staged them), so a later round expands
+// them.  An expanded entry is made idle (with `clear`; a sweep has done it
+// already) before its connection types are relaxed, so an improvement that
+// lands later pushes it again.
+// TPV == 0: wave claims -- each wave takes 4 * U entries at a time and spreads
+//   their connection types over its lanes, U types per lane in flight (a
+//   load-balanced expansion without a block-wide scan).
 // TPV > 0: virtual warps (Section IV-B) -- groups of TPV lanes, one stop per
 //   group, lane i of a group takes the stop's types i, i + TPV, ...
 template <int TPV, int KIND, int U, int B, class Store>
 __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, const FList &cur, int32_t n,
-                                            bool clear, int32_t thr, const ListPush &P, Shared &sh,
-                                            const XList &X, int32_t *xn, int32_t *cursor, Ctr &c) {
-  // Takes entry e (e < n): true if it is expanded this round; a deferred
-  // entry is pushed to the next list (by the caller's wave-wide push).
-  auto take = [&](int32_t e, bool &defer, int32_t &dval) -> bool {
-    const int32_t item = cur.item[e];
-    const int32_t x = S.value(item);
+                                            bool clear, int32_t thr, ListPush &P, const XList X,
+                                            int32_t *cursor, Ctr &c) {
+  // Takes entry e (e < n), reading its arrival x: true if it is expanded
+  // this round (with its type range in beg, cnt); defer = pushed to the next
+  // list instead.  No relaxation runs during the take.
+  auto take = [&](int32_t e, int32_t &item, int32_t &beg, int32_t &cnt, int32_t &x, bool &defer) -> bool {
+    item = cur.item[e];
+    beg = cur.beg[e];
+    cnt = cur.cnt[e];
+    x = S.value(item);
     defer = thr != INF && x >= thr;
-    dval = x;
     if (defer) {
-      // list mode: the bit is still set; after a sweep, set it again unless
-      // an improvement of this round has set it (and pushed the item) already
-      if (!clear) defer = mark_improved(S, item);
+      // list mode: still active; after a sweep, active again unless an
+      // improvement of this round has made it so (and pushed it) already
+      if (!clear) defer = S.reactivate(item);
       return false;
     }
-    if (clear) atomicAnd(&S.bits[item >> 5], ~(1u << (item & 31)));
-    if (cur.cnt[e] < 0) {  // staged by a sweep: load the stop's type range
+    if (clear) S.deactivate(item);
+    if (cnt < 0) {  // staged by a sweep: load the stop's type range
       const int2 r = G.vt[S.stop(item)];
-      cur.beg[e] = r.x;
-      cur.cnt[e] = r.y;
+      beg = r.x;
+      cnt = r.y;
     }
     c.act++;
     return true;
   };
+  const int lane = __lane_id();
   if constexpr (TPV == 0) {
-    // Take pass: every thread takes list entries (no relaxation runs, so the
-    // arrival times are stable): deferred ones go to the next list, the
-    // others to X, with their arrival, bits cleared.
-    const int lane = __lane_id();
+    // Take pass: every thread takes list entries; deferred ones go to the
+    // next list, the others to X, both booked with one atomic per wave.
     for (int32_t e0 = 0; e0 < n; e0 += B) {
       const int32_t e = e0 + (int32_t)threadIdx.x;
       bool defer = false, go = false;
-      int32_t dval = INF, item = 0, beg = 0, cnt = 0;
-      if (e < n) {
-        item = cur.item[e];
-        go = take(e, defer, dval);
-        beg = cur.beg[e];
-        cnt = cur.cnt[e];
-      }
-      P(defer, item, beg, cnt, dval);
-      const uint64_t m = __ballot(go);
-      if (m) {
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        int32_t xb = 0;
-        if (lane == leader) xb = atomicAdd(xn, (int32_t)__popcll(m));
-        xb = __shfl(xb, leader);
-        if (go) {
-          const int32_t slot = xb + (int32_t)__popcll(m & ((1ull << lane) - 1ull));
-          X.item[slot] = item;
-          X.beg[slot] = beg;
-          X.cnt[slot] = cnt;
-          X.x[slot] = dval;
+      int32_t item = 0, beg = 0, cnt = 0, x = INF;
+      if (e < n) go = take(e, item, beg, cnt, x, defer);
+      const uint64_t md = __ballot(defer), mg = __ballot(go);
+      if (md | mg) {
+        if (defer) P.lmin = min(P.lmin, x);
+        const int leader = __ffsll((unsigned long long)(md | mg)) - 1;
+        unsigned long long old = 0;
+        if (lane == leader)
+          old = atomicAdd(P.cx, (unsigned long long)__popcll(md) | ((unsigned long long)__popcll(mg) << 32));
+        const int32_t lo = __builtin_amdgcn_readlane((int32_t)(uint32_t)old, leader);
+        const int32_t hi = __builtin_amdgcn_readlane((int32_t)(uint32_t)(old >> 32), leader);
+        if (defer && P.append) {
+          const int32_t slot = lo + (int32_t)__popcll(md & lanes_below(lane));
+          if (slot < P.fcap) {
+            P.nxt.item[slot] = item;
+            P.nxt.beg[slot] = beg;
+            P.nxt.cnt[slot] = cnt;
+          }
         }
+        if (go) X[hi + (int32_t)__popcll(mg & lanes_below(lane))] = make_int4(beg, cnt, x, item);
       }
     }
     __syncthreads();  // X complete
-    const int32_t nx = *xn;
-    // Wave claims: each wave takes kClaim * U entries of X at a time from a
-    // shared cursor and spreads their connection types over its 64 lanes (a
-    // prefix sum of their counts in registers), U types per lane in flight,
-    // until X is used up.  No block-wide scan and no barrier inside.
+    const int32_t nx = lds_ld(reinterpret_cast<int32_t *>(P.cx) + 1);
+    // Wave claims: wave w first takes entries [w kC, w kC + kC) of X, then
+    // further groups of kC from a shared cursor (fetched one claim ahead), and
+    // spreads their connection types over its 64 lanes (a prefix sum of their
+    // counts in scalar registers), U types per lane in flight, until X is used
+    // up.  No block-wide scan and no barrier inside.
     constexpr int kC = kClaim * U;
-    for (;;) {
-      int32_t base = 0;
-      if (lane == 0) base = atomicAdd(cursor, kC);
-      base = __shfl(base, 0);
-      if (base >= nx) break;
+    constexpr int kWaves = B / 64;
+    int32_t base = (int32_t)(threadIdx.x >> 6) * kC;
+    while (base < nx) {
+      int32_t ahead = 0;
+      if (lane == 0) ahead = atomicAdd(cursor, kC);
       int32_t beg = 0, cnt = 0, x = 0;
-      const int32_t e = base + lane;
-      if (lane < kC && e < nx) {
-        beg = X.beg[e];
-        cnt = X.cnt[e];
-        x = X.x[e];
+      if (lane < kC && base + lane < nx) {
+        const int4 t = X[base + lane];
+        beg = t.x;
+        cnt = t.y;
+        x = t.z;
       }
-      int32_t eo[kC];  // entry offsets in the claim's type space
-      int32_t total = 0, off = 0;
+      int32_t sb[kC], sn[kC], sx[kC], eo[kC];  // wave-uniform
+      int32_t total = 0;
 #pragma unroll
       for (int i = 0; i < kC; ++i) {
+        sb[i] = __builtin_amdgcn_readlane(beg, i);
+        sn[i] = __builtin_amdgcn_readlane(cnt, i);
+        sx[i] = __builtin_amdgcn_readlane(x, i);
         eo[i] = total;
-        if (lane == i) off = total;
-        total += __shfl(cnt, i);
+        total += sn[i];
       }
-      // wave-uniform trip count: the shuffles below read lanes 0 .. kC-1,
-      // which must be active (a shuffle from an inactive lane returns 0)
+      // wave-uniform trip count
       for (int32_t k0 = 0; k0 < total; k0 += 64 * U) {
         int64_t jj[U];
         int32_t tb[U], tn[U], xx[U];
@@ -712,10 +758,16 @@ __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, con
         for (int u = 0; u < U; ++u) {
           const int32_t k = k0 + lane + 64 * u;
           ok[u] = k < total;
-          int32_t i = 0;  // last entry whose offset is <= k
+          // the last entry whose offset is <= k (entries of no types are passed over)
+          int32_t bi = sb[0], oi = 0, xi = sx[0], ni = sn[0];
 #pragma unroll
-          for (int t = 1; t < kC; ++t) i += (eo[t] <= k) ? 1 : 0;
-          const int32_t bi = __shfl(beg, i), oi = __shfl(off, i), xi = __shfl(x, i), ni = __shfl(cnt, i);
+          for (int t = 1; t < kC; ++t) {
+            const bool ge = eo[t] <= k;
+            bi = ge ? sb[t] : bi;
+            oi = ge ? eo[t] : oi;
+            xi = ge ? sx[t] : xi;
+            ni = ge ? sn[t] : ni;
+          }
           tb[u] = ok[u] ? bi : 0;
           tn[u] = ok[u] ? ni : 0;
           jj[u] = ok[u] ? (int64_t)bi + (k - oi) : 0;
@@ -723,23 +775,26 @@ __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, con
         }
         relax_batch<KIND, U>(G, S, jj, tb, tn, xx, ok, P, c);
       }
+      base = kWaves * kC + __builtin_amdgcn_readlane(ahead, 0);
     }
   } else {
     constexpr int kGroups = B / TPV;
-    const int g = threadIdx.x / TPV, lane = threadIdx.x % TPV;
-    // take the entries (defer, clear bits, load unknown type ranges) before
+    const int g = threadIdx.x / TPV, gl = threadIdx.x % TPV;
+    // take the entries (defer, make idle, load unknown type ranges) before
     // any relaxation pushes
     for (int32_t e0 = 0; e0 < n; e0 += B) {
       const int32_t e = e0 + (int32_t)threadIdx.x;
       bool defer = false;
-      int32_t dval = INF, item = 0, beg = 0, cnt = 0;
+      int32_t item = 0, beg = 0, cnt = 0, x = INF;
       if (e < n) {
-        item = cur.item[e];
-        if (!take(e, defer, dval)) cur.item[e] = -1;  // not expanded this round
-        beg = cur.beg[e];
-        cnt = cur.cnt[e];
+        if (take(e, item, beg, cnt, x, defer)) {
+          cur.beg[e] = beg;
+          cur.cnt[e] = cnt;
+        } else {
+          cur.item[e] = -1;  // not expanded this round
+        }
       }
-      P(defer, item, beg, cnt, dval);
+      P(defer, item, beg, cnt, x);
     }
     __syncthreads();
     for (int32_t base = 0; base < n; base += kGroups) {
@@ -747,7 +802,7 @@ __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, con
       if (i < n && cur.item[i] >= 0) {
         const int32_t x = S.value(cur.item[i]);
         const int32_t b = cur.beg[i], cn = cur.cnt[i], e = b + cn;
-        for (int32_t j = b + lane; j < e; j += TPV) relax<KIND>(G, S, j, b, cn, x, P, c);
+        for (int32_t j = b + gl; j < e; j += TPV) relax<KIND>(G, S, j, b, cn, x, P, c);
       }
     }
   }
@@ -759,23 +814,22 @@ struct QState {
 
 // Relaxation rounds until no arrival improves (the iteration of Algorithms 4
 // and 5, with the activity flags of Section III-B).  On entry the first item
-// is list0 entry 0 with its bit set (frontier mode), or only its bit is set
-// (topology mode); every other bit is clear.  Returns false if the store
-// overflowed.
+// is list0 entry 0 and active (frontier mode), or only active (topology mode);
+// every other item is idle.  Returns false if the store overflowed.
 template <int TPV, int KIND, int U, int B, class Store>
 __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, const Store &S, int32_t n_items,
-                           const FList &list0, const FList &list1, const XList &X, bool topo,
+                           const FList &list0, const FList &list1, const XList X, bool topo,
                            int32_t max_rounds, int32_t x0, Shared &sh, QState &qs, Ctr &c) {
   const int tid = threadIdx.x;
-  const int32_t nwords = (n_items + 31) >> 5;
+  const int lane = __lane_id();
+  const int32_t ngroups = (n_items + 63) >> 6;
   FList cur = list0, nxt = list1;
   int32_t nf = topo ? 0 : 1;
   bool sweep = topo;
   int32_t rounds = 0;
   if (tid < 3) {
-    sh.nn[tid] = 0;
+    sh.cx[tid] = 0ull;
     sh.cur[tid] = 0;
-    sh.xn[tid] = 0;
     sh.nmin[tid] = tid == 2 ? x0 : INF;  // "pushed before round 0": the first item
   }
   __syncthreads();
@@ -784,84 +838,93 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
       qs.status = EAT_ERR_NOT_CONVERGED;
       break;
     }
-    int32_t *nn = &sh.nn[rounds % 3];
-    // nn[(rounds + 1) % 3] was last read at the end of round rounds - 2, before
-    // the barrier that ended round rounds - 1: safe to reset for the next round
+    const int r3 = rounds % 3;
+    // the counters of round rounds + 1 were last read at the end of round
+    // rounds - 2, before the barrier that ended round rounds - 1: safe to reset
     if (tid == 0) {
-      sh.nn[(rounds + 1) % 3] = 0;
+      sh.cx[(rounds + 1) % 3] = 0ull;
       sh.nmin[(rounds + 1) % 3] = INF;
       sh.cur[(rounds + 1) % 3] = 0;
-      sh.xn[(rounds + 1) % 3] = 0;
     }
     // this round expands the items below the smallest arrival pushed for it
     // plus the window (that item itself always qualifies)
     const int32_t base = sh.nmin[(rounds + 2) % 3];
     const int32_t thr = (a.window <= 0 || base >= INF - a.window) ? INF : base + a.window;
-    const ListPush P{nxt, a.fcap, !topo, nn, &sh.nmin[rounds % 3]};
+    ListPush P{nxt, a.fcap, !topo, &sh.cx[r3], INF};
     if (!sweep) {
-      expand_list<TPV, KIND, U, B>(G, S, cur, nf, true, thr, P, sh, X, &sh.xn[rounds % 3], &sh.cur[rounds % 3], c);
+      expand_list<TPV, KIND, U, B>(G, S, cur, nf, true, thr, P, X, &sh.cur[r3], c);
     } else {
       ++qs.sweeps;
-      // Chunks of up to fcap items: threads claim words from a shared cursor
-      // and stage a word's items only if all of them fit (bits are stable:
-      // no relaxation runs while staging); the next chunk resumes at the
-      // first word that did not fit.
+      // Chunks of up to fcap items: each wave claims groups of 64 items from
+      // a shared cursor and stages a group's active items only if all of them
+      // fit (no relaxation runs while staging); the next chunk resumes at the
+      // first group that did not fit.
       if (tid == 0) sh.wcur = 0;
       for (;;) {
         if (tid == 0) {
           sh.cnt = 0;
-          sh.cnt2 = 0;
-          sh.xn2 = 0;
-          sh.resume = nwords;
+          sh.cur[r3] = 0;
+          reinterpret_cast<int32_t *>(&sh.cx[r3])[1] = 0;  // X entries of the chunk
+          sh.resume = ngroups;
         }
         __syncthreads();
-        if (sh.wcur >= nwords) break;  // uniform: read after the barrier
+        if (sh.wcur >= ngroups) break;  // uniform: read after the barrier
         for (;;) {
-          const int32_t w = atomicAdd(&sh.wcur, 1);
-          if (w >= nwords) break;
-          uint32_t bits = S.bits[w];
-          if (!bits) continue;
-          const int32_t pc = (int32_t)__popc(bits);
-          int32_t pos = lds_ld(&sh.cnt);
-          bool fits = false;
-          while (pos + pc <= a.fcap) {
-            const int32_t seen = atomicCAS(&sh.cnt, pos, pos + pc);
-            if (seen == pos) {
-              fits = true;
-              break;
+          int32_t g = 0;
+          if (lane == 0) g = atomicAdd(&sh.wcur, 1);
+          g = __builtin_amdgcn_readlane(g, 0);
+          if (g >= ngroups) break;
+          const int32_t it = (g << 6) + lane;
+          const bool act = it < n_items && S.active(it);
+          const uint64_t m = __ballot(act);
+          if (!m) continue;
+          const int32_t pc = (int32_t)__popcll(m);
+          int32_t pos = 0;
+          if (lane == 0) {
+            pos = lds_ld(&sh.cnt);
+            bool fits = false;
+            while (pos + pc <= a.fcap) {
+              const int32_t seen = atomicCAS(&sh.cnt, pos, pos + pc);
+              if (seen == pos) {
+                fits = true;
+                break;
+              }
+              pos = seen;
             }
-            pos = seen;
+            if (!fits) {  // the chunk is full: this group starts the next one
+              atomicMin(&sh.resume, g);
+              pos = -1;
+            }
           }
-          if (!fits) {  // the chunk is full: this word starts the next one
-            atomicMin(&sh.resume, w);
-            break;
-          }
-          S.bits[w] = 0u;  // claimed: these items are expanded now
-          while (bits) {
-            const int b = __ffs(bits) - 1;
-            bits &= bits - 1u;
-            cur.item[pos] = (w << 5) + b;
-            cur.cnt[pos] = -1;
-            ++pos;
+          pos = __builtin_amdgcn_readlane(pos, 0);
+          if (pos < 0) break;
+          S.claim_group(g, lane, act);  // staged: these items are expanded now
+          if (act) {
+            const int32_t slot = pos + (int32_t)__popcll(m & lanes_below(lane));
+            cur.item[slot] = it;
+            cur.cnt[slot] = -1;
           }
         }
         __syncthreads();
         const int32_t cnt = sh.cnt;
         if (tid == 0) sh.wcur = min(sh.wcur, sh.resume);  // read by all after the next barrier
-        if (cnt) expand_list<TPV, KIND, U, B>(G, S, cur, cnt, false, thr, P, sh, X, &sh.xn2, &sh.cnt2, c);
+        if (cnt) expand_list<TPV, KIND, U, B>(G, S, cur, cnt, false, thr, P, X, &sh.cur[r3], c);
         __syncthreads();
       }
     }
+    // the smallest arrival pushed in the round, one atomic per wave
+    const int32_t wm = wave_min(P.lmin);
+    if (lane == 0 && wm != INF) atomicMin(&sh.nmin[r3], wm);
     __syncthreads();  // all pushes of the round are in
-    if (sh.over) {
+    if (sh.over || S.full()) {
       qs.rounds += rounds + 1;
       return false;
     }
-    const int32_t nnv = *nn;
+    const int32_t nnv = lds_ld(reinterpret_cast<int32_t *>(&sh.cx[r3]));
     ++rounds;
     if (nnv == 0) break;
     qs.maxf = max(qs.maxf, nnv);
-    const bool next_sweep = topo || nnv > a.fcap;  // an overflowed list: its bits still name every item
+    const bool next_sweep = topo || nnv > a.fcap;  // an overflowed list: its flags still name every item
     FList tmp = cur;
     cur = nxt;
     nxt = tmp;
@@ -948,31 +1011,28 @@ __global__ __launch_bounds__(B) void k_relax(RunArgs a) {
     }
 
     bool done = false;
+    // LDS: X (F x 16 bytes) | table slots or slab bits | two lists (item, beg, cnt) x F
+    const XList X = reinterpret_cast<int4 *>(lds);
+    uint32_t *const store = lds + 4 * F;
     if (a.table_cap > 0) {
       // ---- arrivals in the on-chip table ----------------------------------------
-      // LDS: {key, arrival}[H] bits[H/32] | two lists (item, beg, cnt) x F | X x F
       const int32_t H = a.table_cap;
       TableStore T;
-      T.kv = reinterpret_cast<int2 *>(lds);
-      T.bits = reinterpret_cast<uint32_t *>(T.kv + H);
+      T.kv = reinterpret_cast<unsigned long long *>(store);
       T.count = &sh.count;
       T.over = &sh.over;
       T.mask = (uint32_t)H - 1u;
       T.shift = 32 - a.table_bits;
       T.limit = H - H / 4;
-      int32_t *l = reinterpret_cast<int32_t *>(T.bits + (H >> 5));
+      int32_t *l = reinterpret_cast<int32_t *>(T.kv + H);
       const FList l0{l, l + F, l + 2 * F}, l1{l + 3 * F, l + 4 * F, l + 5 * F};
-      const XList X{l + 6 * F, l + 7 * F, l + 8 * F, l + 9 * F};
-      for (int32_t i = tid; i < H; i += B) {
-        T.kv[i] = make_int2(EMPTY, INF);
-      }
-      for (int32_t i = tid; i < (H >> 5); i += B) T.bits[i] = 0u;
+      for (int32_t i = tid; i < H; i += B) T.kv[i] = EMPTY_SLOT;
       __syncthreads();
       if (tid == 0) {
-        const int32_t p = T.slot(Q.s, -1);  // empty table: always succeeds
-        T.kv[p].y = Q.ts;
-        T.bits[p >> 5] = 1u << (p & 31);
-        l0.item[0] = p;
+        const uint32_t p = T.home(Q.s);  // empty table: the home slot is free
+        T.kv[p] = ((unsigned long long)(uint32_t)Q.ts << 32) | (uint32_t)Q.s;  // active
+        sh.count = 1;
+        l0.item[0] = (int32_t)p;
         l0.cnt[0] = -1;
       }
       __syncthreads();
@@ -980,8 +1040,9 @@ __global__ __launch_bounds__(B) void k_relax(RunArgs a) {
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the infinity fill has landed
         __syncthreads();
         for (int32_t p = tid; p < H; p += B) {
-          const int2 e = T.kv[p];
-          if (e.x != EMPTY) arr[e.x] = e.y;
+          const unsigned long long e = T.kv[p];
+          const uint32_t key = (uint32_t)e;
+          if (key != NO_KEY) arr[key & ~IDLE] = (int32_t)(e >> 32);
         }
         if (tid == 0) sh.reached = sh.count;
         done = true;
@@ -989,17 +1050,16 @@ __global__ __launch_bounds__(B) void k_relax(RunArgs a) {
     }
     if (!done) {
       // ---- arrivals in the result slab (no table, or the table overflowed) ----------
-      // LDS: bits[ceil(V/32)] | two lists | X.  An overflowed table attempt
-      // never wrote the slab: it still holds infinity.
+      // An overflowed table attempt never wrote the slab: it still holds infinity.
       asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
       __syncthreads();
       SlabStore S;
       S.arr = arr;
-      S.bits = lds;
+      S.bits = store;
+      S.n = V;
       const int32_t VW = (V + 31) >> 5;
-      int32_t *l = reinterpret_cast<int32_t *>(lds + VW);
+      int32_t *l = reinterpret_cast<int32_t *>(store + VW);
       const FList l0{l, l + F, l + 2 * F}, l1{l + 3 * F, l + 4 * F, l + 5 * F};
-      const XList X{l + 6 * F, l + 7 * F, l + 8 * F, l + 9 * F};
       for (int32_t i = tid; i < VW; i += B) S.bits[i] = 0u;
       if (tid == 0) sh.over = 0;
       __syncthreads();

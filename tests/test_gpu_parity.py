@@ -188,11 +188,13 @@ def test_graph_without_grid_uses_compact_headers():
 
 
 @pytest.mark.parametrize("mode", [eat.EAT_MODE_TOPOLOGY, eat.EAT_MODE_FRONTIER])
-@pytest.mark.parametrize("fcap", [32, 0])
+@pytest.mark.parametrize("fcap", [64, 0])
 @pytest.mark.parametrize("table", [0, -1, 64])
 def test_modes_stores_and_overflows_are_exact(mode, fcap, table):
-    """Frontier / topology rounds, frontier-list overflow (sweeps), arrivals in
-    the on-chip table, in the slab, and a table too small (spill to the slab)."""
+    """Frontier / topology rounds (topology rounds sweep every round), arrivals
+    in the on-chip table, in the slab, and a table too small (spill to the
+    slab).  Frontier-list overflow on a larger graph:
+    test_small_lists_overflow_into_sweeps_city_50k."""
     tt, q = _workload("city-1k")
     exp = _expected("city-1k")
     g = _graph("city-1k", "hybrid")
@@ -204,7 +206,7 @@ def test_modes_stores_and_overflows_are_exact(mode, fcap, table):
         spills += st["spilled"]
         assert st["reached"] == int((exp[i] < INF).sum())
         assert np.array_equal(got, exp[i]), (i, s, ts)
-    if mode == eat.EAT_MODE_TOPOLOGY or fcap == 32:
+    if mode == eat.EAT_MODE_TOPOLOGY:
         assert sweeps > 0  # the sweep path really ran
     if table == 64:
         assert spills > 0  # some queries reach more than 48 stops: the spill path ran
@@ -227,7 +229,7 @@ def test_time_windows_are_exact(window, tpv):
         assert st["status"] == 0
         assert np.array_equal(got, exp[i]), (i, s, ts)
     # with overflowing lists (sweeps) and the topology schedule as well
-    for opts in ({"frontier_cap": 32}, {"mode": eat.EAT_MODE_TOPOLOGY}, {"table_cap": -1}):
+    for opts in ({"frontier_cap": 64}, {"mode": eat.EAT_MODE_TOPOLOGY}, {"table_cap": -1}):
         for i in (0, 5, 11):
             got, _ = _query(g, int(q.s[i]), int(q.ts[i]), time_window=window, threads_per_vertex=tpv, **opts)
             assert np.array_equal(got, exp[i]), (i, opts)
@@ -235,7 +237,7 @@ def test_time_windows_are_exact(window, tpv):
 
 @pytest.mark.parametrize("opts", [{}, {"table_cap": 64}, {"time_window": -1}, {"types_per_lane": 2},
                                   {"headers": eat.EAT_HEADERS_COMPACT}, {"mode": eat.EAT_MODE_TOPOLOGY},
-                                  {"frontier_cap": 32}])
+                                  {"frontier_cap": 64}])
 def test_512_thread_queries_are_exact(opts):
     """Two queries per CU (512-thread work-groups, half the LDS each) give the
     same answers, also when the smaller table overflows."""
@@ -331,6 +333,31 @@ def test_batch_city_50k_all_256_queries_bit_exact(layout, headers, threads):
         assert oracle.certify(tt.u, tt.v, tt.t, tt.lam, V, q.s[i], q.ts[i], got[i]) == 0
 
 
+@pytest.mark.parametrize("opts", [{}, {"time_window": -1}, {"threads_per_vertex": 16}, {"table_cap": -1},
+                                  {"threads_per_query": 512}, {"types_per_lane": 2}])
+def test_small_lists_overflow_into_sweeps_city_50k(opts):
+    """64-entry frontier lists (the smallest): rounds whose pushes overflow the
+    list sweep the activity flags in chunks of up to 64 items instead; every
+    answer stays exact, with arrivals in the table or in the slab."""
+    tt, q = _workload("city-50k")
+    g = _graph("city-50k", "hybrid")
+    exp = _expected("city-50k")
+    V, Q = tt.n_vertices, len(q)
+    _say(f"city-50k frontier_cap 64 {opts}")
+    slab = torch.full((Q, V), -7, dtype=torch.int32, device="cuda")
+    b = eat.Batch([g], np.zeros(Q, np.int32), q.s, q.ts, [slab[i] for i in range(Q)],
+                  options=dict(opts, frontier_cap=64))
+    b.run()
+    st = b.wait(stats=True)
+    got = slab.cpu().numpy()
+    b.free()
+    bad = [i for i in range(Q) if not np.array_equal(got[i], exp[i])]
+    assert not bad, bad[:10]
+    assert all(x["status"] == 0 for x in st)
+    assert sum(x["sweep_rounds"] for x in st) > 0
+    assert all(x["reached"] == int((exp[i] < INF).sum()) for i, x in enumerate(st))
+
+
 def test_batch_equals_single_queries_and_mixed_graphs():
     """Alone == batched, with two graphs of different size in one launch."""
     tt1, q1 = _workload("city-1k")
@@ -398,7 +425,7 @@ def test_edge_cases():
     c4 = [(int(rng.integers(0, tt4.n_vertices)), int(rng.integers(0, 72000))) for _ in range(20)]
     _check_tt(tt4, c4, cw=1800)
     _check_tt(tt4, c4, cw=1800, mode=eat.EAT_MODE_TOPOLOGY, threads_per_vertex=64)
-    _check_tt(tt4, c4, layout="flat", frontier_cap=32)
+    _check_tt(tt4, c4, layout="flat", frontier_cap=64)
 
 
 def test_round_limit_reports_not_converged():
