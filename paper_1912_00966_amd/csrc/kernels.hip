@@ -827,6 +827,7 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
   int32_t nf = topo ? 0 : 1;
   bool sweep = topo;
   int32_t rounds = 0;
+  int32_t base = x0;  // smallest arrival pushed for the round ("before round 0": the first item)
   if (tid < 3) {
     sh.cx[tid] = 0ull;
     sh.cur[tid] = 0;
@@ -848,7 +849,6 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
     }
     // this round expands the items below the smallest arrival pushed for it
     // plus the window (that item itself always qualifies)
-    const int32_t base = sh.nmin[(rounds + 2) % 3];
     const int32_t thr = (a.window <= 0 || base >= INF - a.window) ? INF : base + a.window;
     ListPush P{nxt, a.fcap, !topo, &sh.cx[r3], INF};
     if (!sweep) {
@@ -916,11 +916,15 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
     const int32_t wm = wave_min(P.lmin);
     if (lane == 0 && wm != INF) atomicMin(&sh.nmin[r3], wm);
     __syncthreads();  // all pushes of the round are in
-    if (sh.over || S.full()) {
+    // independent reads, one LDS round trip
+    const int32_t over = lds_ld(&sh.over);
+    const bool full = S.full();
+    const int32_t nnv = lds_ld(reinterpret_cast<int32_t *>(&sh.cx[r3]));
+    base = lds_ld(&sh.nmin[r3]);
+    if (over != 0 || full) {
       qs.rounds += rounds + 1;
       return false;
     }
-    const int32_t nnv = lds_ld(reinterpret_cast<int32_t *>(&sh.cx[r3]));
     ++rounds;
     if (nnv == 0) break;
     qs.maxf = max(qs.maxf, nnv);
