@@ -109,6 +109,7 @@ def main():
     ap.add_argument("--threads", type=int, default=0, choices=(0, 512, 1024),
                     help="threads per query (work-group size); 0 = per workload (%s)"
                          % ", ".join(f"{k} {v}" for k, v in DEFAULT_THREADS.items()))
+    ap.add_argument("--fcap", type=int, default=0, help="frontier list entries (0 = default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-query comparison")
     ap.add_argument("--no-verify", action="store_true")
@@ -251,7 +252,7 @@ def main():
     traffic = None
     if (args.workload == "city-50k" and args.layout == "hybrid" and args.table == 0 and args.mode == "auto"
             and args.headers == "auto" and args.window == 0 and args.tpv == 0 and args.types_per_lane == 0
-            and args.threads == 0):
+            and args.threads == 0 and args.fcap == 0):
         traffic = profiled_traffic(os.path.join(ROOT, "profiles", "k_relax_city-50k.md"),
                                    os.path.join(ROOT, "paper_1912_00966_amd", "csrc", "kernels.hip"))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -323,7 +324,7 @@ def _opts(args):
         threads = 1024  # virtual warps run in 1024-thread work-groups
     return {"threads_per_vertex": args.tpv, "types_per_lane": args.types_per_lane,
             "time_window": args.window, "table_cap": args.table, "mode": MODES[args.mode],
-            "headers": HEADERS[args.headers], "threads_per_query": threads}
+            "headers": HEADERS[args.headers], "threads_per_query": threads, "frontier_cap": args.fcap}
 
 
 def run_mixed(args, log):
