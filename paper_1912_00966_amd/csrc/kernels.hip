@@ -498,50 +498,79 @@ struct TableStore {
   __device__ __forceinline__ int32_t stop(int32_t item) const { return (int32_t)((uint32_t)lds_ld(lo(item)) & ~IDLE); }
   __device__ __forceinline__ int32_t value(int32_t item) const { return lds_ld(hi(item)); }
   // pos = v's slot, or the empty slot where it would go (slots are never
-  // freed, so a later insertion of v lands at pos or after it); -1 if full
+  // freed, so a later insertion of v lands at pos or after it); -1 if full.
+  // The home slot is read on its own: most lookups end there.
   __device__ __forceinline__ int32_t find(int32_t v, int32_t &pos) const {
     uint32_t p = home(v);
-    for (uint32_t n = 0; n <= mask; ++n) {
-      const unsigned long long e = entry(p);
-      pos = (int32_t)p;
-      const uint32_t key = (uint32_t)e;
-      if ((key & ~IDLE) == (uint32_t)v) return (int32_t)(e >> 32);
-      if (key == NO_KEY) return INF;
+    unsigned long long e = entry(p);
+    pos = (int32_t)p;
+    uint32_t key = (uint32_t)e;
+    for (uint32_t n = 1; (key & ~IDLE) != (uint32_t)v && key != NO_KEY; ++n) {
+      if (n > mask) {
+        pos = -1;
+        return INF;
+      }
       p = (p + 1u) & mask;
+      e = entry(p);
+      pos = (int32_t)p;
+      key = (uint32_t)e;
     }
-    pos = -1;
-    return INF;
+    return key == NO_KEY ? INF : (int32_t)(e >> 32);
   }
+  // The common case is straight-line: a new stop takes the empty slot find()
+  // returned with a compare-and-swap, a known one is lowered with an atomic
+  // minimum; a wave issues both kinds together and waits once.  Only a lane
+  // whose swap lost a race for its slot goes on probing (improve_probe).
   __device__ __forceinline__ bool improve(int32_t v, int32_t pos, int32_t av, int32_t cand, int32_t &item,
                                           Ctr &c) const {
+    if (pos < 0) {
+      __hip_atomic_store(over, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return false;
+    }
     const unsigned long long want = ((unsigned long long)(uint32_t)cand << 32) | (uint32_t)v;
-    if (pos >= 0) {
-      uint32_t p = (uint32_t)pos;
-      // what find() saw at pos: v (every stored arrival is finite) or no stop
-      uint32_t key = av != INF ? (uint32_t)v : NO_KEY;
-      for (uint32_t n = 0; n <= mask; ++n) {
-        if (key == NO_KEY) {
-          const unsigned long long old = atomicCAS(kv + p, EMPTY_SLOT, want);
-          if (old == EMPTY_SLOT) {
-            atomicAdd(count, 1);
-            item = (int32_t)p;
-            c.imp++;
-            return true;
-          }
-          key = (uint32_t)old;
-        }
-        if ((key & ~IDLE) == (uint32_t)v) {
-          const unsigned long long old = atomicMin(kv + p, want);
-          item = (int32_t)p;
-          if (cand < (int32_t)(old >> 32)) {
-            c.imp++;
-            return ((uint32_t)old & IDLE) != 0u;
-          }
-          return false;
-        }
-        p = (p + 1u) & mask;
-        key = (uint32_t)lds_ld(lo((int32_t)p));
+    const bool fresh = av == INF;  // pos is an empty slot (every stored arrival is finite)
+    const unsigned long long old = fresh ? atomicCAS(kv + pos, EMPTY_SLOT, want) : atomicMin(kv + pos, want);
+    item = pos;
+    if (fresh) {
+      if (old == EMPTY_SLOT) {
+        atomicAdd(count, 1);
+        c.imp++;
+        return true;
       }
+      return improve_probe(v, (uint32_t)pos, (uint32_t)old, want, cand, item, c);
+    }
+    if (cand < (int32_t)(old >> 32)) {
+      c.imp++;
+      return ((uint32_t)old & IDLE) != 0u;
+    }
+    return false;
+  }
+  // After a lost swap at slot p (key = the stop now there): lower v's slot if
+  // that is v, else probe on to v's slot or the next empty one.
+  __device__ __forceinline__ bool improve_probe(int32_t v, uint32_t p, uint32_t key, unsigned long long want,
+                                             int32_t cand, int32_t &item, Ctr &c) const {
+    for (uint32_t n = 0; n <= mask; ++n) {
+      if (key == NO_KEY) {
+        const unsigned long long old = atomicCAS(kv + p, EMPTY_SLOT, want);
+        if (old == EMPTY_SLOT) {
+          atomicAdd(count, 1);
+          item = (int32_t)p;
+          c.imp++;
+          return true;
+        }
+        key = (uint32_t)old;
+      }
+      if ((key & ~IDLE) == (uint32_t)v) {
+        const unsigned long long old = atomicMin(kv + p, want);
+        item = (int32_t)p;
+        if (cand < (int32_t)(old >> 32)) {
+          c.imp++;
+          return ((uint32_t)old & IDLE) != 0u;
+        }
+        return false;
+      }
+      p = (p + 1u) & mask;
+      key = (uint32_t)lds_ld(lo((int32_t)p));
     }
     __hip_atomic_store(over, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     return false;
