@@ -181,7 +181,7 @@ eat_status eat_graph_info(const eat_graph *g, eat_graph_info_t *out);
 typedef enum {
   EAT_MODE_AUTO = 0,     /* frontier-driven; topology sweep when a frontier overflows */
   EAT_MODE_FRONTIER = 1, /* same as AUTO */
-  EAT_MODE_TOPOLOGY = 2  /* every round sweeps the activity bitmap of all stops */
+  EAT_MODE_TOPOLOGY = 2  /* every round sweeps the activity flags of all touched stops */
 } eat_mode;
 
 typedef enum {

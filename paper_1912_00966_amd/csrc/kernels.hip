@@ -12,17 +12,22 @@
 //   work-group, pulled from a shared counter by a persistent grid.
 //
 // Per query:
-//   arr[]      the caller's result slab in HBM (Algorithm 2 fills it with
-//              infinity, arr[s] = ts); updated with atomic minimum (Algorithm
-//              3, Section III-C).
-//   bitmap     one bit per stop in LDS: "improved since it was last expanded"
-//              (the active/nextactive flags of Section III-B).  Setting the bit
-//              also de-duplicates pushes.
+//   arrivals   an open-addressing hash table in LDS of the stops the query has
+//              touched: one 64-bit word per slot {arrival, idle flag, stop}.
+//              The caller's result slab in HBM (Algorithm 2 fills it with
+//              infinity, arr[s] = ts) receives the final values; if the table
+//              overflows, the query runs again with its arrivals in the slab,
+//              updated with global atomic minimum (Algorithm 3, Section III-C).
+//   activity   the slot's flag (one LDS bit per stop in slab mode): "improved
+//              since it was last expanded" (the active/nextactive flags of
+//              Section III-B).  Setting it also de-duplicates pushes.
 //   lists      two frontier lists in LDS (current / next round).  When the next
-//              frontier does not fit, the next round sweeps the bitmap instead
-//              (the topology-driven scan of the paper, at bit granularity).
-//   Each active stop u is expanded by a group of TPV lanes (the virtual warps
-//   of Section IV-B): lane i takes u's connection types i, i+TPV, ...  A type
+//              frontier does not fit, the next round sweeps the flags instead
+//              (the topology-driven scan of the paper, 64 items at a time).
+//   Each round takes the listed stops (those past the round's arrival window
+//   wait for a later round), then the waves claim them a few at a time and
+//   spread their connection types over their 64 lanes (or, with TPV > 0, a
+//   group of TPV lanes per stop: the virtual warps of Section IV-B).  A type
 //   (u, v, lam) gives the earliest departure t_c >= arr[u] (Section II-B) via
 //   the cluster lookup of Section II-D and the progression closed form of
 //   Algorithm 6; arr[v] drops to t_c + lam if that is earlier.
