@@ -358,6 +358,43 @@ def test_small_lists_overflow_into_sweeps_city_50k(opts):
     assert all(x["reached"] == int((exp[i] < INF).sum()) for i, x in enumerate(st))
 
 
+def test_batch_run_replays_from_a_captured_hip_graph():
+    """A prepared batch's run is one persistent kernel launch on the caller's
+    stream, with no memset or copy (its counters re-arm on the device), so it
+    can be captured into a HIP graph and replayed.  Every replay -- with eager
+    work and synchronisations between the replays -- gives the oracle's
+    answers, and the batch still runs eagerly afterwards."""
+    tt, q = _workload("city-50k")
+    g = _graph("city-50k", "hybrid")
+    exp = _expected("city-50k")
+    V, Q = tt.n_vertices, len(q)
+    _say("city-50k batch in a captured HIP graph")
+    slab = torch.full((Q, V), -7, dtype=torch.int32, device="cuda")
+    b = eat.Batch([g], np.zeros(Q, np.int32), q.s, q.ts, [slab[i] for i in range(Q)],
+                  options={"threads_per_query": 512})
+    b.run()
+    b.wait()  # an eager run first
+    assert np.array_equal(slab.cpu().numpy(), exp)
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.graph(graph, stream=cap):
+        b.run()  # on the capturing stream
+    torch.cuda.synchronize()
+    for rep in range(4):
+        slab.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(slab.cpu().numpy(), exp), rep
+    del graph
+    slab.fill_(-7)
+    b.run()
+    b.wait()
+    assert np.array_equal(slab.cpu().numpy(), exp)
+    b.free()
+
+
 def test_batch_equals_single_queries_and_mixed_graphs():
     """Alone == batched, with two graphs of different size in one launch."""
     tt1, q1 = _workload("city-1k")
