@@ -110,6 +110,8 @@ def main():
                     help="threads per query (work-group size); 0 = per workload (%s)"
                          % ", ".join(f"{k} {v}" for k, v in DEFAULT_THREADS.items()))
     ap.add_argument("--fcap", type=int, default=0, help="frontier list entries (0 = default)")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture each stream's batch run into a HIP graph and replay it in the timed steps")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-query comparison")
     ap.add_argument("--no-verify", action="store_true")
@@ -180,7 +182,9 @@ def main():
     slabs = [torch.empty((Q, V), dtype=torch.int32, device=dev) for _ in range(S)]
     batches = [eat.Batch([g], np.zeros(Q, np.int32), q.s, q.ts, [sl[i] for i in range(Q)], options=opts)
                for sl in slabs]
-    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(S - 1)]
+    # (a HIP graph is captured on a stream of its own, not the default one)
+    streams = ([torch.cuda.Stream() for _ in range(S)] if args.graph else
+               [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(S - 1)])
     slab, batch, stream = slabs[0], batches[0], streams[0]
 
     for w in range(max(args.warmup, 1)):
@@ -193,6 +197,19 @@ def main():
         with open(args.dump_stats, "w") as f:
             json.dump([dict(st, s=int(q.s[i]), ts=int(q.ts[i])) for i, st in enumerate(stats)], f)
 
+    # With --graph each stream's batch run is captured once into a HIP graph
+    # and the timed steps replay the graphs (same kernel, no per-step launch
+    # call through the library).
+    graphs = None
+    if args.graph:
+        graphs = []
+        for k in range(S):
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr, stream=streams[k]):
+                batches[k].run(streams[k])
+            graphs.append(gr)
+        torch.cuda.synchronize()
+
     # ---- timed region: K batched steps ------------------------------------------------
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -201,7 +218,11 @@ def main():
     for i in range(args.steps):
         st_ = streams[i % S]
         starts[i].record(st_)
-        batches[i % S].run(st_)
+        if graphs is not None:
+            with torch.cuda.stream(st_):
+                graphs[i % S].replay()
+        else:
+            batches[i % S].run(st_)
         ends[i].record(st_)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -305,7 +326,7 @@ def main():
                    "connections": tt.n_conn, "queries_per_step": Q, "layout": args.layout,
                    "headers": ("grid" if grid else "compact") if args.layout == "hybrid" else None,
                    "mode": args.mode, "time_window": args.window, "streams": S,
-                   "threads_per_query": opts["threads_per_query"],
+                   "threads_per_query": opts["threads_per_query"], "hip_graph": bool(args.graph),
                    "graphs": 1, "digest": tt.digest()},
         "bit_exact": bit_exact,
         "one_stream": one_stream,

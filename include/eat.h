@@ -255,7 +255,11 @@ eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n_graphs,
                             const int32_t *q_graph, const int32_t *q_src,
                             const int32_t *q_ts, int32_t n_q, int32_t *const *arr,
                             const eat_run_options *ro, eat_batch **out);
-/* Enqueues the whole batch on stream (asynchronous; repeatable). */
+/* Enqueues the whole batch on stream (asynchronous; repeatable): one
+ * persistent kernel launch and an event record, no allocation, memset or
+ * copy -- the launch re-arms its own device counters -- so a run can be
+ * captured into a HIP graph (stream capture) and replayed.  Runs of one batch
+ * must not overlap (they share its counters and slabs). */
 eat_status eat_batch_run(eat_batch *b, void *stream);
 /* Waits for the last run and copies per-query stats (host array of n_q,
  * nullable); returns EAT_ERR_NOT_CONVERGED if any query hit its limit. */
