@@ -64,6 +64,19 @@ DEFAULT_THREADS = {"city-1k": 1024, "city-50k": 512, "region-500k": 1024, "mixed
 HEADERS = {"auto": 0, "grid": 1, "compact": 2}  # eat_headers values
 
 
+def profile_traffic_for(args):
+    """HBM bytes per launch from the committed rocprofv3 summary of this
+    workload (profiles/k_relax_<workload>[-topology].md), for the default
+    launch options only, and only while the kernel source is the profiled one."""
+    defaults = (args.layout == "hybrid" and args.table == 0 and args.headers == "auto" and args.window == 0
+                and args.tpv == 0 and args.types_per_lane == 0 and args.threads == 0 and args.fcap == 0)
+    if not defaults:
+        return None
+    name = f"k_relax_{args.workload}" + ("-topology" if args.mode == "topology" else "") + ".md"
+    return profiled_traffic(os.path.join(ROOT, "profiles", name),
+                            os.path.join(ROOT, "paper_1912_00966_amd", "csrc", "kernels.hip"))
+
+
 def profiled_traffic(path, kernel_source):
     """Bytes per launch measured by the rocprofv3 counter runs recorded in
     `path`, or None when the kernel source changed since they were taken."""
@@ -146,6 +159,14 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log = lambda m: print(m, file=sys.stderr, flush=True)
+    if args.calibrate_copy:
+        n = args.calibrate_copy * 2**20 // 4
+        src = torch.ones(n, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written")
+        del src, dst
     if args.serve:
         return run_serving(args, log)
     if args.workload == "mixed":
@@ -162,15 +183,6 @@ def main():
     info = g.info
     log(f"[bench] preprocess+upload {prep_s:.2f}s: T={info.n_types} K={info.n_headers} "
         f"ap={info.n_ap_clusters} array={info.n_array_clusters} device={info.device_bytes / 2**20:.1f} MiB")
-
-    if args.calibrate_copy:
-        n = args.calibrate_copy * 2**20 // 4
-        src = torch.ones(n, dtype=torch.int32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written")
-        del src, dst
 
     V, Q = tt.n_vertices, len(q)
     opts = _opts(args)
@@ -270,12 +282,7 @@ def main():
     # ---- roofline of the relaxation kernel ---------------------------------------------
     bytes_per_launch = algorithmic_bytes(stats, V, slab_only=args.table == -1, grid=grid)
     achieved = bytes_per_launch / (kernel_ms / 1e3) / 1e9
-    traffic = None
-    if (args.workload == "city-50k" and args.layout == "hybrid" and args.table == 0 and args.mode == "auto"
-            and args.headers == "auto" and args.window == 0 and args.tpv == 0 and args.types_per_lane == 0
-            and args.threads == 0 and args.fcap == 0):
-        traffic = profiled_traffic(os.path.join(ROOT, "profiles", "k_relax_city-50k.md"),
-                                   os.path.join(ROOT, "paper_1912_00966_amd", "csrc", "kernels.hip"))
+    traffic = profile_traffic_for(args)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "k_relax", "kernel_ms": round(kernel_ms, 4),
@@ -389,7 +396,21 @@ def run_mixed(args, log):
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms_per_step = wall * 1e3 / args.steps
-    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(starts, ends)]))
+    launch_ms = [a.elapsed_time(b) for a, b in zip(starts, ends)]
+    # the same steps on one stream: each launch alone gives the kernel's own
+    # duration (what the roofline divides by, and what a profiler reports)
+    one_stream = None
+    if S > 1:
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for i in range(args.steps):
+            starts[i].record(stream)
+            batch.run(stream)
+            ends[i].record(stream)
+        torch.cuda.synchronize()
+        one_stream = round(Q / ((time.perf_counter() - w0) / args.steps), 1)
+        launch_ms = [a.elapsed_time(b) for a, b in zip(starts, ends)]
+    kernel_ms = float(np.mean(launch_ms))
     # the same queries, one launch each
     plain = None
     if not args.no_plain:
@@ -438,10 +459,11 @@ def run_mixed(args, log):
                    "graphs": [t.n_vertices for t in tts], "queries_per_step": Q,
                    "connections": int(sum(t.n_conn for t in tts)), "time_window": args.window,
                    "streams": S, "threads_per_query": _opts(args)["threads_per_query"]},
-        "bit_exact": exact if not args.no_verify else None, "checked_vs_scan": checked,
+        "bit_exact": exact if not args.no_verify else None, "one_stream": one_stream, "checked_vs_scan": checked,
         "certified": certified, "plain": plain,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_relax",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profile_traffic_for(args),
+                     "kernel": "k_relax",
                      "kernel_ms": round(kernel_ms, 4), "algorithmic_bytes_per_launch": int(total),
                      "sustained_gbs": round(total / (ms_per_step / 1e3) / 1e9, 1)},
         "per_query_mean": {k: float(np.mean([st[k] for st in stats]))
