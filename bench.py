@@ -58,9 +58,10 @@ MODES = {"auto": 0, "topology": 2}  # eat_mode values
 # query (few queries per CU); a batch that fills the chip for its whole launch
 # only loses L2 locality to it.  Measured on MI355X.
 DEFAULT_STREAMS = {"city-1k": 4, "city-50k": 4, "region-500k": 2, "mixed": 2}
-# Threads per query: 512 puts two queries on a CU (more queries in flight),
-# 1024 finishes one long query sooner (region-500k's batch is one such query).
-DEFAULT_THREADS = {"city-1k": 1024, "city-50k": 512, "region-500k": 1024, "mixed": 512}
+# Threads per query: 768 puts two queries of 12 waves on a CU (more queries in
+# flight, the heavy ones still with many waves), 1024 finishes one long query
+# sooner and keeps the whole LDS for its table (region-500k).
+DEFAULT_THREADS = {"city-1k": 1024, "city-50k": 768, "region-500k": 1024, "mixed": 768}
 HEADERS = {"auto": 0, "grid": 1, "compact": 2}  # eat_headers values
 
 
@@ -119,7 +120,7 @@ def main():
                     help="streams the timed steps alternate between (each with its own prepared "
                          "batch), so one launch's tail overlaps the next launch; 0 = per workload "
                          "(%s)" % ", ".join(f"{k} {v}" for k, v in DEFAULT_STREAMS.items()))
-    ap.add_argument("--threads", type=int, default=0, choices=(0, 512, 1024),
+    ap.add_argument("--threads", type=int, default=0, choices=(0, 512, 768, 1024),
                     help="threads per query (work-group size); 0 = per workload (%s)"
                          % ", ".join(f"{k} {v}" for k, v in DEFAULT_THREADS.items()))
     ap.add_argument("--fcap", type=int, default=0, help="frontier list entries (0 = default)")

@@ -212,11 +212,11 @@ typedef struct {
                                  round, the schedule of Section III-B).  The answer is the
                                  same either way; the window trades a few more rounds for
                                  fewer re-expansions of stops whose arrival improves */
-  int32_t threads_per_query;  /* work-group size of one query: 1024 (default), or 512 --
-                                 two queries share a CU, each with half of its LDS for the
-                                 arrival table (wave claims only: threads_per_vertex = 0).
-                                 512 raises throughput when many queries are in flight; 1024
-                                 finishes a single long query sooner.  0 = 1024 */
+  int32_t threads_per_query;  /* work-group size of one query: 1024 (default), 768 or 512
+                                 -- two queries share a CU, each with half of its LDS for
+                                 the arrival table (wave claims only: threads_per_vertex =
+                                 0).  Two per CU raise throughput when many queries are in
+                                 flight; 1024 finishes a single long query sooner.  0 = 1024 */
   int32_t reserved[1];        /* must be zero */
 } eat_run_options;
 

@@ -10,7 +10,7 @@ with the same key returns at once.
 Knobs (all exact; they change only speed):
   threads_per_vertex  0 = wave claims, or 16/32 lanes per active stop
                       (virtual warps)
-  threads_per_query   1024, or 512 (two queries per CU)
+  threads_per_query   1024, or 768 / 512 (two queries per CU)
   time_window         arrival window of a round (seconds; -1 = none)
   types_per_lane      load-balanced expansion: connection types each lane keeps
                       in flight
@@ -36,8 +36,8 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "eat_autotune.js
 def candidates():
     for tpv, window in itertools.product((0, 16, 32), (3600, 7200, -1)):
         yield {"threads_per_vertex": tpv, "time_window": window, "mode": eat.EAT_MODE_FRONTIER}
-    for window in (7200, 14400):
-        yield {"threads_per_query": 512, "time_window": window}
+    for threads, window in itertools.product((768, 512), (3600, 7200)):
+        yield {"threads_per_query": threads, "time_window": window}
     yield {"threads_per_vertex": 0, "types_per_lane": 2, "mode": eat.EAT_MODE_FRONTIER}
     yield {"table_cap": -1}
     yield {"headers": eat.EAT_HEADERS_COMPACT}

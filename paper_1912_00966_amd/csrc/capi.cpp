@@ -402,15 +402,16 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
     return set_err(EAT_ERR_INVALID_ARGUMENT, "unknown header form");
   pl->headers = o.headers;
   if (o.time_window < -1) return set_err(EAT_ERR_INVALID_ARGUMENT, "time_window must be >= -1");
-  if (o.threads_per_query != 0 && o.threads_per_query != kBlock && o.threads_per_query != kBlockSmall)
-    return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query must be 0, 512 or 1024");
+  if (o.threads_per_query != 0 && o.threads_per_query != kBlock && o.threads_per_query != kBlockSmall &&
+      o.threads_per_query != kBlockMid)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query must be 0, 512, 768 or 1024");
   pl->block = o.threads_per_query ? o.threads_per_query : kBlock;
-  if (pl->block == kBlockSmall && o.threads_per_vertex != 0)
-    return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query 512 needs threads_per_vertex 0");
+  if (pl->block != kBlock && o.threads_per_vertex != 0)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query 512 or 768 needs threads_per_vertex 0");
   pl->window = o.time_window == 0 ? 7200 : (o.time_window < 0 ? 0 : o.time_window);
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;
-  const bool small = o.threads_per_query == kBlockSmall;
+  const bool small = pl->block != kBlock;  // two work-groups per CU
   // default list capacity: the largest that still leaves room for a
   // 16,384-slot table (1024 threads) or an 8,192-slot one (512 threads)
   int fcap = o.frontier_cap ? o.frontier_cap : (small ? 256 : 704);
@@ -432,7 +433,7 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   fcap = std::min(fcap, items);
   const size_t slab_lds = (size_t)pl->bm_words * 4 + lists_lds(fcap);
   auto need = [&](int h) { return std::max(table_lds(h, fcap), slab_lds); };
-  // two 512-thread work-groups share a CU: each gets half its LDS
+  // two 512- or 768-thread work-groups share a CU: each gets half its LDS
   const size_t budget = small ? lim.lds / 2 - 512 : lim.lds;
   while (table_auto && H >= 64 && need(H) > budget) H >>= 1;
   if (H < 64) H = 0;

@@ -81,7 +81,8 @@ struct RunArgs {
 };
 
 constexpr int kBlock = 1024;      // threads per query (work-group), default
-constexpr int kBlockSmall = 512;  // the alternative: two queries per CU
+constexpr int kBlockSmall = 512;  // the alternatives: two queries per CU ...
+constexpr int kBlockMid = 768;    // ... with 8 or 12 waves each
 constexpr int kMaxBuckets = 32;
 constexpr int kCounterWords = 4 + kMaxBuckets;
 

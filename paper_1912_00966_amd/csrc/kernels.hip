@@ -973,8 +973,10 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
   return true;
 }
 
+// 768-thread work-groups share a CU two at a time (24 waves, 6 per SIMD),
+// which needs at most 80 VGPRs: asked of the compiler here.
 template <int TPV, int KIND, int U, int B>
-__global__ __launch_bounds__(B) void k_relax(RunArgs a) {
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(B == kBlockMid ? 6 : 1))) void k_relax(RunArgs a) {
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ Shared sh;
 
@@ -1234,6 +1236,11 @@ RelaxFn relax_fn(int tpv, int ub, int block) {
     if (tpv != 0) return nullptr;
     return ub == 1 ? k_relax<0, KIND, 1, kBlockSmall>
                    : ub == 3 ? k_relax<0, KIND, 3, kBlockSmall> : k_relax<0, KIND, 2, kBlockSmall>;
+  }
+  if (block == kBlockMid) {  // wave claims only
+    if (tpv != 0) return nullptr;
+    return ub == 1 ? k_relax<0, KIND, 1, kBlockMid>
+                   : ub == 3 ? k_relax<0, KIND, 3, kBlockMid> : k_relax<0, KIND, 2, kBlockMid>;
   }
   if (block != kBlock) return nullptr;
   switch (tpv) {

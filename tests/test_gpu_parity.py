@@ -235,18 +235,19 @@ def test_time_windows_are_exact(window, tpv):
             assert np.array_equal(got, exp[i]), (i, opts)
 
 
+@pytest.mark.parametrize("threads", [512, 768])
 @pytest.mark.parametrize("opts", [{}, {"table_cap": 64}, {"time_window": -1}, {"types_per_lane": 2},
                                   {"headers": eat.EAT_HEADERS_COMPACT}, {"mode": eat.EAT_MODE_TOPOLOGY},
                                   {"frontier_cap": 64}])
-def test_512_thread_queries_are_exact(opts):
-    """Two queries per CU (512-thread work-groups, half the LDS each) give the
-    same answers, also when the smaller table overflows."""
+def test_two_queries_per_cu_are_exact(threads, opts):
+    """Two queries per CU (512- or 768-thread work-groups, half the LDS each)
+    give the same answers, also when the smaller table overflows."""
     tt, q = _workload("city-1k")
     exp = _expected("city-1k")
     g = _graph("city-1k", "hybrid")
-    _say(f"512 threads {opts}")
+    _say(f"{threads} threads {opts}")
     for i, (s, ts) in enumerate(zip(q.s, q.ts)):
-        got, st = _query(g, s, ts, threads_per_query=512, **opts)
+        got, st = _query(g, s, ts, threads_per_query=threads, **opts)
         assert st["status"] == 0
         assert np.array_equal(got, exp[i]), (i, s, ts)
 
@@ -254,7 +255,8 @@ def test_512_thread_queries_are_exact(opts):
 def test_512_threads_need_wave_claims():
     g = _graph("city-1k", "hybrid")
     out = torch.empty(g.n_vertices, dtype=torch.int32, device="cuda")
-    for bad in ({"threads_per_query": 512, "threads_per_vertex": 16}, {"threads_per_query": 256}):
+    for bad in ({"threads_per_query": 512, "threads_per_vertex": 16}, {"threads_per_query": 768, "threads_per_vertex": 4},
+                {"threads_per_query": 256}):
         with pytest.raises(eat.EatError) as ei:
             eat.eat_query(g, 0, 0, out, options=bad)
         assert ei.value.status == eat.EAT_ERR_INVALID_ARGUMENT
@@ -305,6 +307,7 @@ def test_batch_city_1k_equals_oracle(layout):
 
 @pytest.mark.parametrize("layout,headers,threads", [("hybrid", eat.EAT_HEADERS_GRID, 1024),
                                                     ("hybrid", eat.EAT_HEADERS_GRID, 512),
+                                                    ("hybrid", eat.EAT_HEADERS_GRID, 768),
                                                     ("hybrid", eat.EAT_HEADERS_COMPACT, 1024),
                                                     ("flat", eat.EAT_HEADERS_AUTO, 512)])
 def test_batch_city_50k_all_256_queries_bit_exact(layout, headers, threads):
