@@ -337,7 +337,8 @@ def test_batch_city_50k_all_256_queries_bit_exact(layout, headers, threads):
 
 
 @pytest.mark.parametrize("opts", [{}, {"time_window": -1}, {"threads_per_vertex": 16}, {"table_cap": -1},
-                                  {"threads_per_query": 512}, {"types_per_lane": 2}])
+                                  {"threads_per_query": 512}, {"threads_per_query": 768},
+                                  {"threads_per_query": 768, "table_cap": -1}, {"types_per_lane": 2}])
 def test_small_lists_overflow_into_sweeps_city_50k(opts):
     """64-entry frontier lists (the smallest): rounds whose pushes overflow the
     list sweep the activity flags in chunks of up to 64 items instead; every
@@ -523,7 +524,7 @@ def test_concurrent_batches_on_several_streams():
     slabs = [torch.full((Q, V), -7, dtype=torch.int32, device="cuda") for _ in range(4)]
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(3)]
     batches = [eat.Batch([g], np.zeros(Q, np.int32), q.s, q.ts, [sl[i] for i in range(Q)],
-                         options={"threads_per_query": 512 if k % 2 else 1024}) for k, sl in enumerate(slabs)]
+                         options={"threads_per_query": (1024, 768, 512)[k % 3]}) for k, sl in enumerate(slabs)]
     _say("concurrent batches on 4 streams")
     for i in range(12):
         batches[i % 4].run(streams[i % 4])
