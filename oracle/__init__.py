@@ -26,7 +26,6 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
-_i64p = ctypes.POINTER(ctypes.c_int64)
 
 
 class OracleError(RuntimeError):
@@ -62,8 +61,6 @@ def _load():
     lib.oracle_certify.restype = ctypes.c_int
     lib.oracle_next_departure.argtypes = [ctypes.c_int64, _i32p, ctypes.c_int32]
     lib.oracle_next_departure.restype = ctypes.c_int32
-    lib.oracle_next_departure_table.argtypes = [ctypes.c_int64, _i64p, _i32p, ctypes.c_int32, _i32p, _i32p]
-    lib.oracle_next_departure_table.restype = None
     _lib = lib
     return lib
 
@@ -75,10 +72,6 @@ def _arr(a, dtype=np.int32):
 
 def _p32(a):
     return a.ctypes.data_as(_i32p)
-
-
-def _p64(a):
-    return a.ctypes.data_as(_i64p)
 
 
 def _conn(u, v, t, lam):
@@ -176,13 +169,3 @@ def certify(u, v, t, lam, nv, s, ts, arr):
 def next_departure(deps, x):
     d = _arr(deps)
     return int(_load().oracle_next_departure(len(d), _p32(d), int(x)))
-
-
-def next_departure_table(off, dep, xs):
-    off = _arr(off, np.int64)
-    dep = _arr(dep)
-    xs = _arr(xs)
-    nt = len(off) - 1
-    out = np.empty((nt, len(xs)), dtype=np.int32)
-    _load().oracle_next_departure_table(nt, _p64(off), _p32(dep), len(xs), _p32(xs), _p32(out))
-    return out

@@ -52,12 +52,3 @@ int32_t oracle_next_departure(int64_t n, const int32_t *d, int32_t x) {
     if (d[i] >= x && d[i] < best) best = d[i];
   return best;
 }
-
-void oracle_next_departure_table(int64_t ntypes, const int64_t *off,
-                                 const int32_t *dep, int32_t nx,
-                                 const int32_t *xs, int32_t *out) {
-  for (int64_t i = 0; i < ntypes; ++i)
-    for (int32_t j = 0; j < nx; ++j)
-      out[i * (int64_t)nx + j] =
-          oracle_next_departure(off[i + 1] - off[i], dep + off[i], xs[j]);
-}

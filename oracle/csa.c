@@ -36,10 +36,34 @@ int oracle_validate(int64_t n, const int32_t *u, const int32_t *v,
   return ORACLE_OK;
 }
 
-/* departure time in the high half, original index in the low half */
-static int cmp_u64(const void *a, const void *b) {
-  uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
-  return (x > y) - (x < y);
+/* Order of the scan: the indices 0..n-1 sorted by departure time, ties kept
+ * in input order (a stable least-significant-digit radix sort on the two
+ * 16-bit halves of t).  Any order by t gives the same answer (lam >= 1). */
+static int order_by_departure(int64_t n, const int32_t *t, uint32_t *out) {
+  uint32_t *tmp = (uint32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+  size_t *count = (size_t *)malloc(65537 * sizeof(size_t));
+  if (!tmp || !count) {
+    free(tmp);
+    free(count);
+    return ORACLE_ENOMEM;
+  }
+  for (int64_t i = 0; i < n; ++i) tmp[i] = (uint32_t)i;
+  uint32_t *src = tmp, *dst = out;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int shift = 16 * pass;
+    memset(count, 0, 65537 * sizeof(size_t));
+    for (int64_t i = 0; i < n; ++i) count[(((uint32_t)t[src[i]] >> shift) & 0xffffu) + 1]++;
+    for (int d = 0; d < 65536; ++d) count[d + 1] += count[d];
+    for (int64_t i = 0; i < n; ++i) dst[count[((uint32_t)t[src[i]] >> shift) & 0xffffu]++] = src[i];
+    uint32_t *sw = src;
+    src = dst;
+    dst = sw;
+  }
+  /* after two passes the sorted indices are back in tmp: copy them out */
+  memcpy(out, src, (size_t)n * sizeof(uint32_t));
+  free(tmp);
+  free(count);
+  return ORACLE_OK;
 }
 
 oracle_csa *oracle_csa_new(int64_t n, const int32_t *u, const int32_t *v,
@@ -55,22 +79,20 @@ oracle_csa *oracle_csa_new(int64_t n, const int32_t *u, const int32_t *v,
   h->v = (int32_t *)malloc(bytes);
   h->t = (int32_t *)malloc(bytes);
   h->lam = (int32_t *)malloc(bytes);
-  uint64_t *key = (uint64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint64_t));
-  if (!h->u || !h->v || !h->t || !h->lam || !key) {
-    free(key);
+  uint32_t *idx = (uint32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+  if (!h->u || !h->v || !h->t || !h->lam || !idx || order_by_departure(n, t, idx) != ORACLE_OK) {
+    free(idx);
     oracle_csa_free(h);
     return NULL;
   }
-  for (int64_t i = 0; i < n; ++i) key[i] = ((uint64_t)(uint32_t)t[i] << 32) | (uint64_t)i;
-  qsort(key, (size_t)n, sizeof(uint64_t), cmp_u64);
   for (int64_t k = 0; k < n; ++k) {
-    int64_t i = (int64_t)(key[k] & 0xffffffffu);
+    int64_t i = (int64_t)idx[k];
     h->u[k] = u[i];
     h->v[k] = v[i];
     h->t[k] = t[i];
     h->lam[k] = lam[i];
   }
-  free(key);
+  free(idx);
   return h;
 }
 

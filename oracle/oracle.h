@@ -100,11 +100,6 @@ int oracle_certify(int64_t n, const int32_t *u, const int32_t *v,
 /* ---- Next departure of one connection type (Section II-B) ------------------- */
 /* min { d[i] : d[i] >= x } over n departures in any order, or ORACLE_INF. */
 int32_t oracle_next_departure(int64_t n, const int32_t *d, int32_t x);
-/* For each type i of a type table (departures dep[off[i] .. off[i+1]) in any
- * order) and each probe x in xs: out[i * nx + j] = next departure >= xs[j]. */
-void oracle_next_departure_table(int64_t ntypes, const int64_t *off,
-                                 const int32_t *dep, int32_t nx,
-                                 const int32_t *xs, int32_t *out);
 
 #ifdef __cplusplus
 }

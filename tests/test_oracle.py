@@ -187,3 +187,42 @@ def test_next_departure_is_the_minimum_at_or_after_x():
     assert oracle.next_departure(d, 201) == 300
     assert oracle.next_departure(d, 301) == INF
     assert oracle.next_departure([], 0) == INF
+
+
+def test_next_departure_equals_a_sorted_search():
+    """min{t >= x} (Section II-B) equals numpy's left-sided search in the
+    sorted departures, on random departure sets in random order."""
+    rng = np.random.default_rng(21)
+    for _ in range(300):
+        n = int(rng.integers(0, 40))
+        d = rng.integers(0, 5000, size=n).astype(np.int32)
+        srt = np.sort(d)
+        for x in rng.integers(-5, 5100, size=25):
+            x = max(int(x), 0)
+            pos = int(np.searchsorted(srt, x, side="left"))
+            want = int(srt[pos]) if pos < n else INF
+            assert oracle.next_departure(d, x) == want, (d, x)
+
+
+def test_csa_scan_order_over_the_whole_time_range():
+    """Departure times spread over the full int32 range (both 16-bit digits of
+    the scan's ordering vary): the scan still equals the time-dependent
+    Dijkstra and the state closure."""
+    rng = np.random.default_rng(31)
+    for _ in range(200):
+        nv = int(rng.integers(2, 12))
+        n = int(rng.integers(1, 120))
+        u = rng.integers(0, nv, size=n).astype(np.int32)
+        v = rng.integers(0, nv, size=n).astype(np.int32)
+        # a few anchor times spread over [0, 2^31 - 2^20) plus small offsets:
+        # many equal high digits with different low digits, and the reverse
+        anchors = rng.integers(0, 2**31 - 2**20, size=4)
+        t = (anchors[rng.integers(0, 4, size=n)] + rng.integers(0, 3 * 65536, size=n)).astype(np.int32)
+        lam = rng.integers(1, 70000, size=n).astype(np.int32)
+        tt = synth.Timetable("wide", nv, u, v, t, lam, -1, -1, -1)
+        s = int(rng.integers(0, nv))
+        ts = int(rng.choice(t)) - int(rng.integers(0, 2))
+        ts = max(ts, 0)
+        csa, args = _run_all(tt, s, ts)
+        assert np.array_equal(csa, oracle.td_dijkstra(*args)), (s, ts)
+        assert np.array_equal(csa, oracle.brute_states(*args)), (s, ts)

@@ -21,7 +21,8 @@ MUTANTS = {
     "head and tail swapped": ("a < arr[h->v[i]]) arr[h->v[i]] = a;", "a < arr[h->u[i]]) arr[h->u[i]] = a;"),
     "scan starts after ts": ("if (h->t[mid] < ts)", "if (h->t[mid] <= ts)"),
     "source not initialised": ("arr[s] = ts;\n  /* first", "/* first"),
-    "reverse time order": ("return (x > y) - (x < y);", "return (x < y) - (x > y);"),
+    "reverse time order": ("int64_t i = (int64_t)idx[k];", "int64_t i = (int64_t)idx[n - 1 - k];"),
+    "high digit of the time not sorted": ("pass < 2; ++pass", "pass < 1; ++pass"),
     "boarding tests arrival of head": ("int32_t tu = arr[h->u[i]];", "int32_t tu = arr[h->v[i]];"),
 }
 
@@ -53,10 +54,17 @@ def test_planted_mistake_is_caught(tmp_path, name):
     lib = _build_mutant(tmp_path, name, old, new)
     p = ctypes.POINTER(ctypes.c_int32)
     rng = np.random.default_rng(2024)
-    for _ in range(3000):
+    for k in range(3000):
         tt = synth.random_tiny(rng)
         s = int(rng.integers(0, tt.n_vertices))
         ts = int(rng.integers(0, 32))
+        if k % 2:
+            # the same timetable stretched over a wide time range: departure
+            # times then differ in both 16-bit digits
+            scale = 40_000
+            tt = synth.Timetable("wide", tt.n_vertices, tt.u, tt.v, (tt.t * scale).astype(np.int32),
+                                 (tt.lam * scale).astype(np.int32), -1, -1, -1)
+            ts *= scale
         ref = oracle.brute_states(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices, s, ts)
         arrs = [np.ascontiguousarray(a, dtype=np.int32) for a in (tt.u, tt.v, tt.t, tt.lam)]
         h = lib.oracle_csa_new(len(tt.u), *(a.ctypes.data_as(p) for a in arrs), tt.n_vertices)
