@@ -1,17 +1,26 @@
-"""Benchmark: earliest-arrival-time queries per second on one MI355X.
+"""Benchmark: earliest-arrival-time (EAT) queries per second on one MI355X.
 
-A step answers one batch of queries (256 random (s, ts) pairs on the 50,000-stop
-synthetic city, about 12M connections) with one launch of the batched
-relaxation kernel; results land in device-resident int32 slabs.  The batch and
-the graph are prepared before the timed region (inputs resident in HBM).
+Default workload -- batched EAT over several graphs: 4,096 (s, ts) queries
+spread over eight synthetic cities of 2k, 5k, 10k, 20k, 50k, 100k, 200k and
+500k stops (about 208M connections in all), answered by one persistent launch
+of the relaxation kernel per step into per-query int32 result slabs.  Graphs,
+query descriptors and slabs are resident in HBM before the timed region; steps
+alternate over a few streams, each with its own prepared batch and slabs.
 
-Printed (one JSON line): queries/s of the batched path, the plain path (one
-launch per query, queries one after another) beside it, the relaxation
-kernel's algorithmic bytes against the HBM roofline, and the CPU oracle
-(connection scan) timed on the host.  Every answer of the last timed step is
-compared bit-exactly with the oracle.
+Printed (one JSON line):
+  value         batched queries/s over the timed steps
+  plain         the same queries as one single-query launch each, one after another
+  roofline      the relaxation kernel: algorithmic relaxation bytes per launch
+                (per-unit model below) / mean launch time from HIP events on the
+                launch stream, against the 8 TB/s HBM peak and a measured copy;
+                the slab fill is reported beside it, not in it
+  cpu_baseline  the oracle (connection scan) over every query, on the host cores
+  served        continuous batching over the 10k/50k/500k cities at two Poisson rates
+Every answer of every stream's batch, and of the plain run, is compared element
+by element with the oracle's.
 
-    python bench.py [--steps K] [--warmup W] [--workload city-50k] [--layout hybrid]
+    python bench.py [--steps K] [--warmup W] [--workload mixed|city-50k|city-1k|region-500k]
+    python bench.py --serve            (full serving report, its own JSON line)
 """
 import argparse
 import json
@@ -26,34 +35,29 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
+# Algorithmic bytes per unit of relaxation work (what the method must move,
+# counted by the kernel's own device-side counters):
+#   activation   16  the stop's type range 8, its arrival 4, its frontier entry 4
+#   type eval    40  type record 20, cluster header 12, arr[v] 4, array probes 4
+#   improvement   8  atomic minimum (read-modify-write)
+# and per query, reported separately (Algorithm 2's initialisation and the
+# result): 4 * V (slab filled with infinity) + 4 * reached (final values).
+BYTES_ACTIVATION, BYTES_TYPE_EVAL, BYTES_IMPROVEMENT = 16, 40, 8
 
-def algorithmic_bytes(stats, n_vertices, slab_only=False, grid=False):
-    """HBM bytes the relaxation must move per launch, from its operation counts.
 
-    per query      : 4 * V (result slab written with infinity) + 4 * reached
-                     (final arrival times scattered from the on-chip table)
-    per activation : 8 (the stop's type range, vt_off[u] and vt_off[u+1])
-    per type eval  : 16 (type record)
-    per header     : 8 (compact cluster header; a second one only when the
-                     next cluster is needed), or 12 (header-grid entry: the
-                     cluster's header and the next cluster's first departure)
-    per pool word  : 4 (array-cluster chunks, flat departures)
-    A query whose arrivals live in the slab (table overflow, or no table) also
-    moves 4 (arr[u]) per activation, 4 (arr[v]) per type eval and 8 (atomic
-    minimum) per improvement.
-    """
-    total = 0
-    for st in stats:
-        total += 4 * n_vertices + 8 * st["activations"] + 16 * st["type_evals"]
-        total += (12 if grid else 8) * st["header_loads"] + 4 * st["pool_loads"]
-        if slab_only or st["spilled"]:
-            total += 4 * st["activations"] + 4 * st["type_evals"] + 8 * st["improvements"]
-        else:
-            total += 4 * st["reached"]
-    return total
+def algorithmic_bytes(stats, n_vertices):
+    """(relaxation bytes, fill bytes) of the queries in `stats`; n_vertices[i]
+    is the stop count of query i's graph."""
+    relax = fill = 0
+    for st, V in zip(stats, n_vertices):
+        relax += (BYTES_ACTIVATION * st["activations"] + BYTES_TYPE_EVAL * st["type_evals"]
+                  + BYTES_IMPROVEMENT * st["improvements"])
+        fill += 4 * V + 4 * st["reached"]
+    return relax, fill
 
 
 MODES = {"auto": 0, "topology": 2}  # eat_mode values
+HEADERS = {"auto": 0, "grid": 1, "compact": 2}  # eat_headers values
 # Overlapping consecutive batches pays when a batch is shorter than its slowest
 # query (few queries per CU); a batch that fills the chip for its whole launch
 # only loses L2 locality to it.  Measured on MI355X.
@@ -62,7 +66,6 @@ DEFAULT_STREAMS = {"city-1k": 4, "city-50k": 4, "region-500k": 2, "mixed": 2}
 # flight, the heavy ones still with many waves), 1024 finishes one long query
 # sooner and keeps the whole LDS for its table (region-500k).
 DEFAULT_THREADS = {"city-1k": 1024, "city-50k": 768, "region-500k": 1024, "mixed": 768}
-HEADERS = {"auto": 0, "grid": 1, "compact": 2}  # eat_headers values
 
 
 def profile_traffic_for(args):
@@ -74,14 +77,24 @@ def profile_traffic_for(args):
     if not defaults:
         return None
     name = f"k_relax_{args.workload}" + ("-topology" if args.mode == "topology" else "") + ".md"
-    return profiled_traffic(os.path.join(ROOT, "profiles", name),
-                            os.path.join(ROOT, "paper_1912_00966_amd", "csrc", "kernels.hip"))
+    return profiled_traffic(os.path.join(ROOT, "profiles", name))
 
 
-def profiled_traffic(path, kernel_source):
-    """Bytes per launch measured by the rocprofv3 counter runs recorded in
-    `path`, or None when the kernel source changed since they were taken."""
+# The sources whose code the relaxation kernel's traffic depends on.
+KERNEL_SOURCES = ("relax.hpp", "relax_grid.hip", "kernels.hip", "device.hpp")
+
+
+def kernel_source_digest():
     import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1912_00966_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def profiled_traffic(path):
+    """Bytes per launch measured by the rocprofv3 counter runs recorded in
+    `path`, or None when the kernel sources changed since they were taken."""
     if not os.path.exists(path):
         return None
     fields = {}
@@ -90,236 +103,274 @@ def profiled_traffic(path, kernel_source):
         if ":" in line and line.startswith(("traffic_bytes_per_launch", "kernel_source_sha256")):
             k, v = line.split(":", 1)
             fields[k.strip().strip("`")] = v.strip().strip("` ")
-    digest = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
+    digest = kernel_source_digest()
     if fields.get("kernel_source_sha256") != digest or "traffic_bytes_per_launch" not in fields:
         return None
     return int(fields["traffic_bytes_per_launch"])
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="city-50k",
-                    help="city-1k, city-50k, region-500k (one graph), or mixed (eight graphs, 4,096 queries)")
-    ap.add_argument("--layout", default="hybrid", choices=["hybrid", "flat"])
-    ap.add_argument("--reading", default="S", choices=["S", "F"])
-    ap.add_argument("--tpv", type=int, default=0, help="threads per active stop (0 = auto)")
-    ap.add_argument("--window", type=int, default=0,
-                    help="arrival window of a round in seconds (0 = auto, -1 = none)")
-    ap.add_argument("--types-per-lane", type=int, default=0,
-                    help="load-balanced expansion: connection types in flight per lane (0 = auto)")
-    ap.add_argument("--table", type=int, default=0,
-                    help="on-chip arrival-table slots (0 = auto, -1 = arrivals in HBM only)")
-    ap.add_argument("--mode", default="auto", choices=sorted(MODES),
-                    help="relaxation schedule: frontier rounds (auto) or topology sweeps")
-    ap.add_argument("--headers", default="auto", choices=sorted(HEADERS),
-                    help="hybrid layout on the device: header grid (auto when built) or compact headers")
-    ap.add_argument("--streams", type=int, default=0,
-                    help="streams the timed steps alternate between (each with its own prepared "
-                         "batch), so one launch's tail overlaps the next launch; 0 = per workload "
-                         "(%s)" % ", ".join(f"{k} {v}" for k, v in DEFAULT_STREAMS.items()))
-    ap.add_argument("--threads", type=int, default=0, choices=(0, 512, 768, 1024),
-                    help="threads per query (work-group size); 0 = per workload (%s)"
-                         % ", ".join(f"{k} {v}" for k, v in DEFAULT_THREADS.items()))
-    ap.add_argument("--fcap", type=int, default=0, help="frontier list entries (0 = default)")
-    ap.add_argument("--graph", action="store_true",
-                    help="capture each stream's batch run into a HIP graph and replay it in the timed steps")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-query comparison")
-    ap.add_argument("--no-verify", action="store_true")
-    ap.add_argument("--dump-stats", default="", metavar="PATH",
-                    help="write the per-query statistics of the last timed launch as JSON")
-    ap.add_argument("--serve", action="store_true",
-                    help="serving mode: Poisson arrivals over resident 10k/50k/500k-stop cities, "
-                         "p50/p99 latency and sustained queries/s per rate (prints its own JSON line)")
-    ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000")
-    ap.add_argument("--requests", type=int, default=20000, help="requests per rate (serving mode)")
-    ap.add_argument("--serve-sizes", default="10000,50000,500000")
-    ap.add_argument("--serve-checks", type=int, default=200,
-                    help="serving: answers per rate and graph (<= 100k stops) checked against the oracle")
-    ap.add_argument("--serve-certs", type=int, default=8,
-                    help="serving: answers per rate and graph (> 100k stops) certified")
-    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
-                    help="before the timed region, run one device-to-device copy of MIB MiB "
-                         "(a kernel of known traffic, to scale profiler byte counters)")
-    args = ap.parse_args()
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: queries are independent, so several GPUs would each "
-              "run this same single-GPU batch on their own share of the queries; run with --gpus 1.",
-              file=sys.stderr)
-        sys.exit(2)
 
+def host_threads():
+    """Threads for the oracle: the cores this process may use, at most 16 (the
+    GPU machine's CPU share)."""
+    return max(1, min(len(os.sched_getaffinity(0)), 16))
+
+
+def _opts(args):
+    threads = args.threads or DEFAULT_THREADS.get(args.workload, 1024)
+    if args.tpv:
+        threads = 1024  # virtual warps run in 1024-thread work-groups
+    return {"threads_per_vertex": args.tpv, "types_per_lane": args.types_per_lane,
+            "time_window": args.window, "table_cap": args.table, "mode": MODES[args.mode],
+            "headers": HEADERS[args.headers], "threads_per_query": threads, "frontier_cap": args.fcap}
+
+
+def calibrate_copy(torch, mib, log):
+    """Device-to-device copy of `mib` MiB: a kernel of known traffic (it also
+    scales the profiler's byte counters) and the measured copy bandwidth
+    (bytes read + written per second, best of three)."""
+    n = mib * 2**20 // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    best = None
+    for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    gbs = 2 * n * 4 / (best / 1e3) / 1e9
+    log(f"[bench] calibration copy: {mib} MiB read + {mib} MiB written, {gbs:.0f} GB/s")
+    del src, dst
+    torch.cuda.synchronize()
+    return gbs
+
+
+def build_workload(args, log):
+    """(timetables, q_graph, q_src, q_ts, name) of the chosen workload."""
+    from paper_1912_00966_amd import synth
+
+    t0 = time.time()
+    if args.workload == "mixed":
+        tts, qsets = synth.mixed_batch(reading=args.reading)
+        qg = np.concatenate([np.full(len(qs), i, np.int32) for i, qs in enumerate(qsets)])
+        qs_ = np.concatenate([qs.s for qs in qsets])
+        qt = np.concatenate([qs.ts for qs in qsets])
+        perm = np.random.default_rng(4).permutation(len(qg))  # interleave the graphs
+        qg, qs_, qt = qg[perm], qs_[perm], qt[perm]
+        name = f"mixed batch: 8 cities of 2k..500k stops, 512 queries each ({args.reading} reading)"
+    else:
+        tt, q = synth.workload(args.workload, reading=args.reading)
+        tts = [tt]
+        qg, qs_, qt = np.zeros(len(q), np.int32), q.s, q.ts
+        name = f"{args.workload} ({args.reading} reading)"
+    log(f"[bench] {name}: {len(tts)} graphs, sum C={sum(t.n_conn for t in tts)}, Q={len(qg)} "
+        f"generated in {time.time() - t0:.1f}s")
+    return tts, qg.astype(np.int32), qs_.astype(np.int32), qt.astype(np.int32), name
+
+
+class Slabs:
+    """One device buffer holding a result slab per query (query k's slab holds
+    V(graph of k) int32 at a 256-byte aligned offset); the slabs of one graph's
+    queries are laid out one after another, in query order."""
+
+    def __init__(self, torch, sizes, group):
+        self.sizes = np.asarray(sizes, dtype=np.int64)
+        words = (self.sizes + 63) // 64 * 64
+        order = np.argsort(np.asarray(group), kind="stable")
+        self.off = np.empty(len(words), np.int64)
+        self.off[order] = np.concatenate([[0], np.cumsum(words[order])[:-1]])
+        self.buf = torch.full((int(words.sum()),), -7, dtype=torch.int32, device="cuda")
+        self.views = [self.buf[int(o):int(o) + int(n)] for o, n in zip(self.off, self.sizes)]
+
+    def host(self, ks):
+        """Host copies of the slabs of queries ks (one device-to-host copy)."""
+        lo = int(min(self.off[k] for k in ks))
+        hi = int(max(self.off[k] + self.sizes[k] for k in ks))
+        h = self.buf[lo:hi].cpu().numpy()
+        return [h[int(self.off[k]) - lo:int(self.off[k] + self.sizes[k]) - lo] for k in ks]
+
+
+def time_steps(torch, batches, streams, steps, graphs=None):
+    """K steps alternating over the streams; returns (wall seconds, per-launch ms)."""
+    S = len(batches)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for i in range(steps):
+        st = streams[i % S]
+        starts[i].record(st)
+        if graphs is not None:
+            with torch.cuda.stream(st):
+                graphs[i % S].replay()
+        else:
+            batches[i % S].run(st)
+        ends[i].record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    return wall, [a.elapsed_time(b) for a, b in zip(starts, ends)]
+
+
+def run_batched(args, log):
     import torch
 
-    from paper_1912_00966_amd import eat, synth
+    import oracle
+    from paper_1912_00966_amd import eat
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    log = lambda m: print(m, file=sys.stderr, flush=True)
-    if args.calibrate_copy:
-        n = args.calibrate_copy * 2**20 // 4
-        src = torch.ones(n, dtype=torch.int32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy: {args.calibrate_copy} MiB read + {args.calibrate_copy} MiB written")
-        del src, dst
-    if args.serve:
-        return run_serving(args, log)
-    if args.workload == "mixed":
-        return run_mixed(args, log)
-
-    t0 = time.time()
-    tt, q = synth.workload(args.workload, reading=args.reading)
-    log(f"[bench] {tt.name}: V={tt.n_vertices} E={tt.n_edges} C={tt.n_conn} Q={len(q)} "
-        f"digest={tt.digest()} ({time.time() - t0:.1f}s)")
+    copy_gbs = calibrate_copy(torch, args.copy_mib, log)
+    tts, qg, qs_, qt, wname = build_workload(args, log)
     layout = eat.EAT_LAYOUT_HYBRID if args.layout == "hybrid" else eat.EAT_LAYOUT_FLAT
     t0 = time.time()
-    g = eat.graph_from_timetable(tt, layout=layout)
+    graphs = [eat.graph_from_timetable(t, layout=layout) for t in tts]
     prep_s = time.time() - t0
-    info = g.info
-    log(f"[bench] preprocess+upload {prep_s:.2f}s: T={info.n_types} K={info.n_headers} "
-        f"ap={info.n_ap_clusters} array={info.n_array_clusters} device={info.device_bytes / 2**20:.1f} MiB")
-
-    V, Q = tt.n_vertices, len(q)
+    log(f"[bench] preprocess+upload {prep_s:.1f}s, device "
+        f"{sum(g.info.device_bytes for g in graphs) / 2**30:.2f} GiB")
+    Q = len(qg)
+    Vq = np.array([graphs[int(gi)].n_vertices for gi in qg], np.int64)
     opts = _opts(args)
-    grid = args.layout == "hybrid" and args.headers != "compact" and info.n_grid_entries > 0
-    # One prepared batch (own result slabs and device counters) per stream:
-    # step i runs on stream i % S, so a launch's tail overlaps the next
-    # launch's start (the steps are independent batches of the same queries).
     S = args.streams or DEFAULT_STREAMS.get(args.workload, 1)
-    slabs = [torch.empty((Q, V), dtype=torch.int32, device=dev) for _ in range(S)]
-    batches = [eat.Batch([g], np.zeros(Q, np.int32), q.s, q.ts, [sl[i] for i in range(Q)], options=opts)
-               for sl in slabs]
-    # the current stream and S - 1 more: with the runtime's 4 hardware queues,
-    # 4 new streams besides the current one share queues (1.36M q/s against
-    # 2.4M with this set on city-50k)
+    slabs = [Slabs(torch, Vq, qg) for _ in range(S)]
+    batches = [eat.Batch(graphs, qg, qs_, qt, sl.views, options=opts) for sl in slabs]
+    # the current stream and S - 1 more (with the runtime's 4 hardware queues,
+    # streams beyond that share queues)
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(S - 1)]
-    slab, batch, stream = slabs[0], batches[0], streams[0]
-
     for w in range(max(args.warmup, 1)):
         batches[w % S].run(streams[w % S])
     torch.cuda.synchronize()
-    batch.run(stream)
-    stats = batch.wait(stats=True)
+    batches[0].run(streams[0])
+    stats = batches[0].wait(stats=True)
     torch.cuda.synchronize()
     if args.dump_stats:
         with open(args.dump_stats, "w") as f:
-            json.dump([dict(st, s=int(q.s[i]), ts=int(q.ts[i])) for i, st in enumerate(stats)], f)
-
-    # With --graph each stream's batch run is captured once into a HIP graph
-    # and the timed steps replay the graphs (same kernel, no per-step launch
-    # call through the library).
-    graphs = None
+            json.dump([dict(st, graph=int(qg[i]), s=int(qs_[i]), ts=int(qt[i])) for i, st in enumerate(stats)], f)
+    hip_graphs = None
     if args.graph:
-        graphs = []
-        cap = torch.cuda.Stream()  # capture needs a stream other than the default one
+        # each stream's batch run captured once into a HIP graph, replayed in the timed steps
+        hip_graphs = []
+        cap = torch.cuda.Stream()
         for k in range(S):
             gr = torch.cuda.CUDAGraph()
             cap.wait_stream(torch.cuda.current_stream())
             with torch.cuda.graph(gr, stream=cap):
                 batches[k].run(cap)
-            graphs.append(gr)
+            hip_graphs.append(gr)
         torch.cuda.synchronize()
 
     # ---- timed region: K batched steps ------------------------------------------------
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    for i in range(args.steps):
-        st_ = streams[i % S]
-        starts[i].record(st_)
-        if graphs is not None:
-            with torch.cuda.stream(st_):
-                graphs[i % S].replay()
-        else:
-            batches[i % S].run(st_)
-        ends[i].record(st_)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
+    wall, launch_ms = time_steps(torch, batches, streams, args.steps, hip_graphs)
     ms_per_step = wall * 1e3 / args.steps
     value = Q / (ms_per_step / 1e3)
-    # The same steps on one stream: each launch runs alone, so HIP events on
-    # its stream give the kernel's own duration (what the roofline divides by,
-    # and what a profiler that serializes dispatches reports).
+    # The same steps on one stream: each launch runs alone, so HIP events on its
+    # stream give the kernel's own duration (what a profiler that serializes
+    # dispatches reports, and what the roofline divides by).
     one_stream = None
-    launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     if S > 1:
-        torch.cuda.synchronize()
-        w0 = time.perf_counter()
-        for i in range(args.steps):
-            starts[i].record(stream)
-            batch.run(stream)
-            ends[i].record(stream)
-        torch.cuda.synchronize()
-        one_stream = round(Q / ((time.perf_counter() - w0) / args.steps), 1)
-        launch_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+        w1, launch_ms = time_steps(torch, batches[:1], streams[:1], args.steps)
+        one_stream = round(Q / (w1 / args.steps), 1)
     kernel_ms = float(np.mean(launch_ms))
-
-    bit_exact = None
-    if not args.no_verify:
-        import oracle
-        exp = oracle.Csa(tt.u, tt.v, tt.t, tt.lam, V).query_many(q.s, q.ts)
-        bit_exact = all(bool(np.array_equal(sl.cpu().numpy(), exp)) for sl in slabs)
-        log(f"[bench] verify vs oracle: {'bit-exact' if bit_exact else 'MISMATCH'}")
+    log(f"[bench] {value:.0f} queries/s ({ms_per_step:.4f} ms per step on {S} streams), "
+        f"launch {kernel_ms:.4f} ms")
 
     # ---- plain path: one launch per query, one query after another ---------------------
     plain = None
+    plain_slabs = None
     if not args.no_plain:
+        plain_slabs = Slabs(torch, Vq, qg)
+        st0 = streams[0]
         for i in range(min(Q, 8)):
-            eat.eat_query(g, int(q.s[i]), int(q.ts[i]), slab[i], stream=stream, options=opts)
+            eat.eat_query(graphs[int(qg[i])], int(qs_[i]), int(qt[i]), plain_slabs.views[i], stream=st0,
+                          options=opts)
         torch.cuda.synchronize()
         p0 = time.perf_counter()
         for i in range(Q):
-            eat.eat_query(g, int(q.s[i]), int(q.ts[i]), slab[i], stream=stream, options=opts)
+            eat.eat_query(graphs[int(qg[i])], int(qs_[i]), int(qt[i]), plain_slabs.views[i], stream=st0,
+                          options=opts)
         torch.cuda.synchronize()
         p_s = time.perf_counter() - p0
-        plain = {"value": Q / p_s, "unit": "queries/s", "ms_per_query": p_s * 1e3 / Q}
-        if not args.no_verify:
-            plain["bit_exact"] = bool(np.array_equal(slab.cpu().numpy(), exp))
+        plain = {"value": round(Q / p_s, 1), "unit": "queries/s", "ms_per_query": round(p_s * 1e3 / Q, 4)}
+        log(f"[bench] plain: {plain['value']:.0f} queries/s")
+
+    # ---- CPU oracle on the host, and the check of every answer --------------------------
+    cpu = None
+    bit_exact = None
+    checked = 0
+    if not (args.no_cpu and args.no_verify):
+        from concurrent.futures import ThreadPoolExecutor
+        n_thr = host_threads()
+        prep = scan_s = 0.0
+        bit_exact = True
+        with ThreadPoolExecutor(n_thr) as ex:
+            for gi, t in enumerate(tts):
+                ks = np.flatnonzero(qg == gi)
+                c0 = time.perf_counter()
+                csa = oracle.Csa(t.u, t.v, t.t, t.lam, t.n_vertices)
+                c1 = time.perf_counter()
+                exp = list(ex.map(lambda k: csa.query(int(qs_[k]), int(qt[k])), ks))
+                c2 = time.perf_counter()
+                prep += c1 - c0
+                scan_s += c2 - c1
+                csa.close()
+                if not args.no_verify:
+                    sets = slabs + ([plain_slabs] if plain_slabs is not None else [])
+                    for c in range(0, len(ks), 128):
+                        chunk = list(ks[c:c + 128])
+                        for sl in sets:
+                            for k, got in zip(chunk, sl.host(chunk)):
+                                ok = np.array_equal(got, exp[int(np.searchsorted(ks, k))])
+                                if not ok:
+                                    log(f"[bench] MISMATCH query {k} (graph {gi}, s={qs_[k]}, ts={qt[k]})")
+                                bit_exact &= bool(ok)
+                    checked += len(ks)
+                del exp
+                log(f"[bench] oracle graph {gi} ({t.n_vertices} stops): {len(ks)} queries, "
+                    f"{c2 - c1:.2f}s on {n_thr} threads")
+        if not args.no_cpu:
+            cpu = {"value": round(Q / scan_s, 2), "unit": "queries/s", "cores": n_thr, "kind": "oracle",
+                   "sample": f"every one of the {Q} queries of the timed batch (no sampling): the "
+                             f"connection scan, one query per thread at a time over {n_thr} threads, "
+                             f"graph after graph; the scan's sort by departure time is excluded",
+                   "cpu_model": cpu_model(), "host_cores_visible": os.cpu_count(),
+                   "sort_s": round(prep, 2)}
+        if args.no_verify:
+            bit_exact = None
+        else:
+            log(f"[bench] verify vs oracle: {checked} queries x {len(slabs)} streams"
+                f"{' + plain' if plain_slabs is not None else ''}: {'bit-exact' if bit_exact else 'MISMATCH'}")
 
     # ---- roofline of the relaxation kernel ---------------------------------------------
-    bytes_per_launch = algorithmic_bytes(stats, V, slab_only=args.table == -1, grid=grid)
-    achieved = bytes_per_launch / (kernel_ms / 1e3) / 1e9
-    traffic = profile_traffic_for(args)
+    relax_b, fill_b = algorithmic_bytes(stats, Vq)
+    achieved = relax_b / (kernel_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profile_traffic_for(args),
                 "kernel": "k_relax", "kernel_ms": round(kernel_ms, 4),
-                "algorithmic_bytes_per_launch": int(bytes_per_launch),
-                # launches overlap on several streams: bytes of all steps over the wall time
-                "sustained_gbs": round(bytes_per_launch / (ms_per_step / 1e3) / 1e9, 1)}
+                "relax_bytes_per_launch": int(relax_b), "fill_bytes_per_launch": int(fill_b),
+                "frac_with_fill": round((relax_b + fill_b) / (kernel_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+                # launches overlap on several streams: relaxation bytes of all steps over the wall time
+                "sustained_gbs": round(relax_b / (ms_per_step / 1e3) / 1e9, 1)}
 
-    # ---- CPU oracle on the host ----------------------------------------------------------
-    cpu = None
-    if not args.no_cpu:
-        import oracle
-        from concurrent.futures import ThreadPoolExecutor
-        c = oracle.Csa(tt.u, tt.v, tt.t, tt.lam, V)
-        c0 = time.perf_counter()
-        c.query_many(q.s, q.ts)
-        one_s = time.perf_counter() - c0
-        # the same queries spread over the host cores this process may use (each
-        # query is one native call that releases the interpreter lock)
-        n_thr = max(1, min(len(os.sched_getaffinity(0)), 16))
-        with ThreadPoolExecutor(n_thr) as ex:
-            c0 = time.perf_counter()
-            list(ex.map(lambda i: c.query(q.s[i], q.ts[i]), range(Q)))
-            all_s = time.perf_counter() - c0
-        cpu = {"value": round(Q / all_s, 2), "unit": "queries/s", "cores": n_thr, "kind": "oracle",
-               "sample": f"all {Q} queries of the timed batch, connection scan, one query per "
-                         f"thread at a time over {n_thr} threads ({os.cpu_count()} host cores visible)",
-               "single_thread": round(Q / one_s, 2)}
+    served = None
+    if args.workload == "mixed" and not args.no_serve:
+        served = serving_record(args, log, rates=[float(r) for r in args.served_rates.split(",")],
+                                requests=args.served_requests, checks=args.served_checks)
 
-    per_q = {k: float(np.mean([s[k] for s in stats])) for k in
+    per_q = {k: round(float(np.mean([s[k] for s in stats])), 2) for k in
              ("rounds", "activations", "type_evals", "header_loads", "pool_loads", "improvements",
               "reached", "spilled")}
-    per_q["elapsed_us_p50"] = float(np.median([s["elapsed_ns"] for s in stats]) / 1e3)
-    per_q["elapsed_us_max"] = float(np.max([s["elapsed_ns"] for s in stats]) / 1e3)
+    per_q["elapsed_us_p50"] = round(float(np.median([s["elapsed_ns"] for s in stats]) / 1e3), 2)
+    per_q["elapsed_us_max"] = round(float(np.max([s["elapsed_ns"] for s in stats]) / 1e3), 2)
     out = {
         "metric": "EAT queries/sec & relax-kernel HBM GB/s (% peak), batched vs plain, bit-exact",
         "value": round(value, 1),
@@ -333,220 +384,162 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload} ({args.reading} reading)", "stops": V,
-                   "connections": tt.n_conn, "queries_per_step": Q, "layout": args.layout,
-                   "headers": ("grid" if grid else "compact") if args.layout == "hybrid" else None,
-                   "mode": args.mode, "time_window": args.window, "streams": S,
+        "config": {"workload": wname, "graphs": [t.n_vertices for t in tts],
+                   "connections": int(sum(t.n_conn for t in tts)), "queries_per_step": Q,
+                   "layout": args.layout, "mode": args.mode, "streams": S,
                    "threads_per_query": opts["threads_per_query"], "hip_graph": bool(args.graph),
-                   "graphs": 1, "digest": tt.digest()},
+                   "digests": [t.digest() for t in tts]},
         "bit_exact": bit_exact,
+        "checked_answers": checked * (len(slabs) + (1 if plain_slabs is not None else 0)),
         "one_stream": one_stream,
         "plain": plain,
+        "batched_vs_plain": round(value / plain["value"], 1) if plain else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "served": served,
         "per_query_mean": per_q,
         "preprocess_s": round(prep_s, 3),
     }
     print(json.dumps(out), flush=True)
 
 
-def _opts(args):
-    threads = args.threads or DEFAULT_THREADS.get(args.workload, 1024)
-    if args.tpv:
-        threads = 1024  # virtual warps run in 1024-thread work-groups
-    return {"threads_per_vertex": args.tpv, "types_per_lane": args.types_per_lane,
-            "time_window": args.window, "table_cap": args.table, "mode": MODES[args.mode],
-            "headers": HEADERS[args.headers], "threads_per_query": threads, "frontier_cap": args.fcap}
-
-
-def run_mixed(args, log):
-    """Batched mode over eight cities of 2k..500k stops: 4,096 queries (512 per
-    graph, interleaved) in one launch, against the same queries as 4,096
-    sequential single-query launches."""
+def serving_record(args, log, rates, requests, checks):
+    """Continuous batching over the resident 10k/50k/500k-stop cities at the
+    given Poisson rates: sustained queries/s and p50/p99 latency per rate;
+    `checks` served answers per graph and rate compared with the oracle (the
+    connection scan on the 10k and 50k cities, the certificate on the 500k
+    city), and a few with the same query run alone."""
     import torch
-
-    import oracle
-    from paper_1912_00966_amd import eat, synth
-
-    t0 = time.time()
-    tts, qsets = synth.mixed_batch(reading=args.reading)
-    graphs = [eat.graph_from_timetable(t) for t in tts]
-    log(f"[bench] mixed: {len(tts)} graphs, sum C={sum(t.n_conn for t in tts)} built in {time.time() - t0:.0f}s")
-    qg = np.concatenate([np.full(len(qs), i, np.int32) for i, qs in enumerate(qsets)])
-    qs_ = np.concatenate([qs.s for qs in qsets])
-    qt = np.concatenate([qs.ts for qs in qsets])
-    perm = np.random.default_rng(4).permutation(len(qg))
-    qg, qs_, qt = qg[perm], qs_[perm], qt[perm]
-    Q = len(qg)
-    S = args.streams or DEFAULT_STREAMS["mixed"]
-    outsets = [[torch.empty(graphs[gi].n_vertices, dtype=torch.int32, device="cuda") for gi in qg]
-               for _ in range(S)]
-    batches = [eat.Batch(graphs, qg, qs_, qt, o, options=_opts(args)) for o in outsets]
-    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(S - 1)]
-    outs, batch, stream = outsets[0], batches[0], streams[0]
-    for w in range(max(args.warmup, 1)):
-        batches[w % S].run(streams[w % S])
-    torch.cuda.synchronize()
-    batch.run(stream)
-    stats = batch.wait(stats=True)
-    torch.cuda.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    wall0 = time.perf_counter()
-    for i in range(args.steps):
-        starts[i].record(streams[i % S])
-        batches[i % S].run(streams[i % S])
-        ends[i].record(streams[i % S])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_per_step = wall * 1e3 / args.steps
-    launch_ms = [a.elapsed_time(b) for a, b in zip(starts, ends)]
-    # the same steps on one stream: each launch alone gives the kernel's own
-    # duration (what the roofline divides by, and what a profiler reports)
-    one_stream = None
-    if S > 1:
-        torch.cuda.synchronize()
-        w0 = time.perf_counter()
-        for i in range(args.steps):
-            starts[i].record(stream)
-            batch.run(stream)
-            ends[i].record(stream)
-        torch.cuda.synchronize()
-        one_stream = round(Q / ((time.perf_counter() - w0) / args.steps), 1)
-        launch_ms = [a.elapsed_time(b) for a, b in zip(starts, ends)]
-    kernel_ms = float(np.mean(launch_ms))
-    # the same queries, one launch each
-    plain = None
-    if not args.no_plain:
-        p0 = time.perf_counter()
-        for i in range(Q):
-            eat.eat_query(graphs[int(qg[i])], int(qs_[i]), int(qt[i]), outs[i], stream=stream,
-                          options=_opts(args))
-        torch.cuda.synchronize()
-        p_s = time.perf_counter() - p0
-        plain = {"value": round(Q / p_s, 1), "unit": "queries/s", "ms_per_query": round(p_s * 1e3 / Q, 4)}
-    # checks: every answer on the graphs up to 10k stops against the scan, a
-    # sample of the others against the certificate
-    checked = certified = 0
-    exact = True
-    if not args.no_verify:
-        csa = {}
-        per_graph = {gi: 0 for gi in range(len(graphs))}
-        for k in range(Q):
-            gi = int(qg[k])
-            t = tts[gi]
-            if t.n_vertices <= 10_000:
-                if gi not in csa:
-                    csa[gi] = oracle.Csa(t.u, t.v, t.t, t.lam, t.n_vertices)
-                exact &= bool(np.array_equal(outs[k].cpu().numpy(), csa[gi].query(qs_[k], qt[k])))
-                checked += 1
-            elif per_graph[gi] < 4:
-                got = outs[k].cpu().numpy()
-                exact &= oracle.certify(t.u, t.v, t.t, t.lam, t.n_vertices, qs_[k], qt[k], got) == 0
-                per_graph[gi] += 1
-                certified += 1
-        log(f"[bench] mixed: {checked} answers vs the scan, {certified} certified: "
-            f"{'bit-exact' if exact else 'MISMATCH'}")
-    V = {gi: g.n_vertices for gi, g in enumerate(graphs)}
-    grid = args.headers != "compact" and all(g.info.n_grid_entries > 0 for g in graphs)
-    total = 0
-    for k, st in enumerate(stats):
-        total += algorithmic_bytes([st], V[int(qg[k])], slab_only=args.table == -1, grid=grid)
-    achieved = total / (kernel_ms / 1e3) / 1e9
-    out = {
-        "metric": "EAT queries/sec, batched (8 graphs, one launch) vs plain",
-        "value": round(Q / (ms_per_step / 1e3), 1), "unit": "queries/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
-        "data": "synthetic",
-        "config": {"workload": f"mixed batch ({args.reading} reading)",
-                   "graphs": [t.n_vertices for t in tts], "queries_per_step": Q,
-                   "connections": int(sum(t.n_conn for t in tts)), "time_window": args.window,
-                   "streams": S, "threads_per_query": _opts(args)["threads_per_query"]},
-        "bit_exact": exact if not args.no_verify else None, "one_stream": one_stream, "checked_vs_scan": checked,
-        "certified": certified, "plain": plain,
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profile_traffic_for(args),
-                     "kernel": "k_relax",
-                     "kernel_ms": round(kernel_ms, 4), "algorithmic_bytes_per_launch": int(total),
-                     "sustained_gbs": round(total / (ms_per_step / 1e3) / 1e9, 1)},
-        "per_query_mean": {k: float(np.mean([st[k] for st in stats]))
-                           for k in ("rounds", "activations", "type_evals", "reached", "spilled")},
-    }
-    print(json.dumps(out), flush=True)
-
-
-def run_serving(args, log):
-    """Open-loop serving benchmark: continuous batching over resident graphs."""
-    import torch
+    from concurrent.futures import ThreadPoolExecutor
 
     import oracle
     from paper_1912_00966_amd import eat, serve, synth
 
-    sizes = [int(x) for x in args.serve_sizes.split(",")]
-    tts, graphs = [], []
-    for i, n in enumerate(sizes):
-        t0 = time.time()
-        tt = synth.scaled_city(n, seed=501 + i)
-        g = eat.graph_from_timetable(tt)
-        log(f"[serve] graph {i}: {tt.name} V={tt.n_vertices} C={tt.n_conn} built in {time.time() - t0:.1f}s")
-        tts.append(tt)
-        graphs.append(g)
+    t0 = time.time()
+    tts = synth.serving_cities(reading=args.reading)
+    graphs = [eat.graph_from_timetable(t) for t in tts]
+    log(f"[serve] cities {[t.n_vertices for t in tts]} ready in {time.time() - t0:.0f}s")
     sess = eat.Session(graphs, pool_bytes=1 << 30, n_streams=2)
-    out = {"metric": "served EAT queries/s and latency (Poisson arrivals)", "unit": "queries/s",
-           "graphs": [{"stops": t.n_vertices, "connections": t.n_conn} for t in tts], "rates": []}
+    n_thr = host_threads()
     csa = {}
-    for rate in [float(r) for r in args.rates.split(",")]:
-        reqs = serve.poisson_requests(rate, args.requests, [g.n_vertices for g in graphs], seed=599)
-        check_ids = set(range(0, len(reqs), max(1, len(reqs) // 32)))
-        kept = {}
-
-        def on_done(r, slot):
-            if r.id in check_ids:
-                kept[r.id] = sess.result(slot).cpu().numpy()
-
-        rep = serve.serve(sess, reqs, on_done=on_done, min_batch=64, max_delay_s=50e-6)
-        # spot checks of the timed run: served == alone on the GPU
-        ok_alone = all(np.array_equal(kept[i], graphs[reqs[i].graph].query(reqs[i].s, reqs[i].ts).cpu().numpy())
-                       for i in kept)
-        # checking run (untimed, same arrivals and batching): every result of a
-        # sample is copied out as it completes and checked against the oracle --
-        # the connection scan on the smaller graphs, the certificate (source,
-        # closure, witness) on graphs above 100k stops
-        per_graph = {gi: (args.serve_checks if graphs[gi].n_vertices <= 100_000 else args.serve_certs)
-                     for gi in range(len(graphs))}
-        want, seen = set(), {gi: 0 for gi in per_graph}
-        for r in reqs:
-            if seen[r.graph] < per_graph[r.graph]:
+    rows = []
+    exact = True
+    for rate in rates:
+        reqs = serve.poisson_requests(rate, requests, [g.n_vertices for g in graphs], seed=599)
+        want = set()
+        seen = {gi: 0 for gi in range(len(graphs))}
+        for r in reqs[::7]:
+            if seen[r.graph] < checks:
                 want.add(r.id)
                 seen[r.graph] += 1
         got = {}
 
-        def keep_all(r, slot):
+        def keep(r, slot):
             if r.id in want:
                 got[r.id] = sess.result(slot).cpu().numpy()
 
-        serve.serve(sess, reqs, on_done=keep_all, min_batch=64, max_delay_s=50e-6)
-        n_csa = n_cert = 0
-        ok_oracle = True
-        for i in sorted(got):
-            r = reqs[i]
-            t = tts[r.graph]
-            if graphs[r.graph].n_vertices <= 100_000:
-                if r.graph not in csa:
-                    csa[r.graph] = oracle.Csa(t.u, t.v, t.t, t.lam, t.n_vertices)
-                ok_oracle &= bool(np.array_equal(got[i], csa[r.graph].query(r.s, r.ts)))
-                n_csa += 1
-            else:
-                ok_oracle &= oracle.certify(t.u, t.v, t.t, t.lam, t.n_vertices, r.s, r.ts, got[i]) == 0
-                n_cert += 1
-        row = {"offered_qps": rate, **rep.as_dict(), "checked_vs_alone": len(kept),
-               "bit_exact_vs_alone": bool(ok_alone), "checked_vs_oracle_scan": n_csa,
-               "certified": n_cert, "bit_exact_vs_oracle": bool(ok_oracle)}
+        rep = serve.serve(sess, reqs, on_done=keep, min_batch=64, max_delay_s=50e-6)
+        with ThreadPoolExecutor(n_thr) as ex:
+            for gi, t in enumerate(tts):
+                mine = [reqs[i] for i in sorted(got) if reqs[i].graph == gi]
+                if t.n_vertices <= 100_000:
+                    if gi not in csa:
+                        csa[gi] = oracle.Csa(t.u, t.v, t.t, t.lam, t.n_vertices)
+                    exp = list(ex.map(lambda r: csa[gi].query(r.s, r.ts), mine))
+                    exact &= all(np.array_equal(got[r.id], e) for r, e in zip(mine, exp))
+                else:
+                    rc = list(ex.map(lambda r: oracle.certify(t.u, t.v, t.t, t.lam, t.n_vertices, r.s, r.ts,
+                                                              got[r.id]), mine))
+                    exact &= all(x == 0 for x in rc)
+                for r in mine[:4]:
+                    exact &= bool(np.array_equal(got[r.id], graphs[gi].query(r.s, r.ts).cpu().numpy()))
+        row = {"offered_qps": rate, "sustained_qps": round(rep.qps, 1), "p50_ms": round(rep.percentile_ms(50), 4),
+               "p99_ms": round(rep.percentile_ms(99), 4), "requests": rep.n,
+               "mean_step_queries": round(rep.mean_step_queries, 2), "checked": len(got)}
         log(f"[serve] {row}")
-        out["rates"].append(row)
+        rows.append(row)
     sess.free()
-    print(json.dumps(out), flush=True)
+    return {"graphs": [t.n_vertices for t in tts], "rates": rows, "bit_exact": bool(exact),
+            "check": "connection scan on the 10k and 50k cities, certificate on the 500k city, "
+                     "a few also against the query alone"}
+
+
+def run_serving(args, log):
+    """Open-loop serving report over all rates (--serve)."""
+    import torch
+
+    from paper_1912_00966_amd import eat  # noqa: F401  (loads the library first)
+
+    rates = [float(r) for r in args.rates.split(",")]
+    rec = serving_record(args, log, rates, args.requests, args.serve_checks)
+    print(json.dumps({"metric": "served EAT queries/s and latency (Poisson arrivals)", "unit": "queries/s",
+                      "device": torch.cuda.get_device_name(), **rec}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="mixed",
+                    help="mixed (eight cities, 4,096 queries; default), city-1k, city-50k, region-500k")
+    ap.add_argument("--layout", default="hybrid", choices=["hybrid", "flat"])
+    ap.add_argument("--reading", default="S", choices=["S", "F"])
+    ap.add_argument("--tpv", type=int, default=0, help="threads per active stop (0 = wave claims)")
+    ap.add_argument("--window", type=int, default=0,
+                    help="arrival window of a round in seconds (0 = auto, -1 = none)")
+    ap.add_argument("--types-per-lane", type=int, default=0,
+                    help="wave claims: connection types in flight per lane (0 = auto)")
+    ap.add_argument("--table", type=int, default=0,
+                    help="on-chip arrival-table slots (0 = auto, -1 = arrivals in HBM only)")
+    ap.add_argument("--mode", default="auto", choices=sorted(MODES),
+                    help="relaxation schedule: frontier rounds (auto) or topology sweeps")
+    ap.add_argument("--headers", default="auto", choices=sorted(HEADERS),
+                    help="hybrid layout on the device: header grid (auto when built) or compact headers")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="streams the timed steps alternate between (each with its own prepared "
+                         "batch); 0 = per workload (%s)" % ", ".join(f"{k} {v}" for k, v in DEFAULT_STREAMS.items()))
+    ap.add_argument("--threads", type=int, default=0, choices=(0, 512, 768, 1024),
+                    help="threads per query (work-group size); 0 = per workload (%s)"
+                         % ", ".join(f"{k} {v}" for k, v in DEFAULT_THREADS.items()))
+    ap.add_argument("--fcap", type=int, default=0, help="frontier list entries (0 = default)")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture each stream's batch run into a HIP graph and replay it in the timed steps")
+    ap.add_argument("--copy-mib", type=int, default=1024,
+                    help="size of the calibration copy (measured copy bandwidth; scales profiler counters)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-query comparison")
+    ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="mixed workload: skip the served record")
+    ap.add_argument("--served-rates", default="10000,50000", help="served record: Poisson rates (queries/s)")
+    ap.add_argument("--served-requests", type=int, default=20000, help="served record: requests per rate")
+    ap.add_argument("--served-checks", type=int, default=64,
+                    help="served record: answers per graph and rate checked against the oracle")
+    ap.add_argument("--dump-stats", default="", metavar="PATH",
+                    help="write the per-query statistics of one launch as JSON")
+    ap.add_argument("--serve", action="store_true",
+                    help="full serving report: Poisson arrivals over the resident 10k/50k/500k-stop "
+                         "cities at every rate of --rates (prints its own JSON line)")
+    ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000")
+    ap.add_argument("--requests", type=int, default=20000, help="requests per rate (--serve)")
+    ap.add_argument("--serve-checks", type=int, default=200,
+                    help="--serve: answers per graph and rate checked against the oracle")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: queries are independent, so several GPUs would each "
+              "run this same single-GPU batch on their own share of the queries; run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    if args.serve:
+        return run_serving(args, log)
+    return run_batched(args, log)
 
 
 if __name__ == "__main__":

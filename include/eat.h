@@ -155,25 +155,37 @@ eat_status eat_graph_build(const int32_t *u, const int32_t *v, const int32_t *t,
  * opt (nullable) only header_grid is used.
  *
  * Header grid (hybrid layout, device side).  Besides the compact headers, the
- * device holds one 32-byte entry per (type, cluster) -- empty clusters
+ * device holds one 16-byte entry per (type, cluster) -- empty clusters
  * included -- so that the entry a lookup needs has an address computable from
  * the type index, the cluster index k = x / width and the tail stop's type
  * range, without reading the type record first.  The entries of stop u (types
  * b .. b+n-1) form one block ordered by cluster, then type:
- *   grid[b * n_clusters + k * n + (j - b)] = {t0, c, next, m}, {d2, d3, d4, d5}
- * where {t0, c} is the cluster's header (same encoding as hdr below) and next
- * the type's first departure in a later cluster (EAT_INF if none).  For a
- * progression, m is a multiplier that replaces the division by its step; for
- * a sorted array, m is its length and d2..d5 its departures 2..5 (EAT_INF past
- * the length), so arrays of up to 5 departures need no further read.  An
- * empty cluster holds {next, (1 << 16) | 1, next, 0}: a one-term progression
- * at the next departure, which is the answer of Section II-D for any x inside
- * that cluster.  Lanes that expand the types of one stop at one cluster read
- * consecutive entries.  Costs 32 * n_types * n_clusters bytes of HBM; built
- * only when n_types * n_clusters < 2^31. */
+ *   grid[b * n_clusters + k * n + (j - b)] = {t0, c, next, m}
+ * where t0 is the cluster's first departure and next the type's first
+ * departure in a later cluster (EAT_INF if none), and by the top bits of c:
+ *   c >= 0          a progression t0 + i*d, i < n, c = (n << 16) | d (as in
+ *                   hdr below); m = ceil(2^32 / d) replaces the division by d
+ *                   (0 for d = 1);
+ *   c >> 30 == 2    a sorted array of three to five departures d1 = t0 < d2 <
+ *                   .. : c holds o2 = d2 - t0 (bits 15..29) and o3 (bits 0..14),
+ *                   m holds o4 (bits 15..29) and o5 (bits 0..14), 0 past the
+ *                   array's end -- no further read is needed;
+ *   c >> 30 == 3    a longer sorted array at pool[~c] (as in hdr below), m = n.
+ * An empty cluster holds {next, (1 << 16) | 1, next, 0}: a one-term
+ * progression at the next departure, which is the answer of Section II-D for
+ * any x inside that cluster.  Lanes that expand the types of one stop at one
+ * cluster read consecutive entries.  Costs 16 * n_types * n_clusters bytes of
+ * HBM; built only when n_types * n_clusters < 2^31 and the pool holds fewer
+ * than 2^30 words. */
 eat_status eat_graph_upload(const eat_layout *layout, const eat_build_options *opt, eat_graph **out);
 void eat_graph_free(eat_graph *g); /* NULL-safe; waits for the device */
 eat_status eat_graph_info(const eat_graph *g, eat_graph_info_t *out);
+/* *count receives the number of eat_query calls on g, made without stats,
+ * that hit their round limit (EAT_ERR_NOT_CONVERGED would have been their
+ * status; their arr is then incomplete) since g was built.  The count covers
+ * the queries that have finished: synchronize their streams first.  Queries
+ * with stats report the status themselves and are not counted here. */
+eat_status eat_graph_failures(const eat_graph *g, int32_t *count);
 
 /* ---------------------------------------------------------------------------
  * Queries
@@ -266,12 +278,59 @@ eat_status eat_batch_run(eat_batch *b, void *stream);
 eat_status eat_batch_wait(eat_batch *b, eat_query_stats *stats);
 void eat_batch_free(eat_batch *b); /* NULL-safe; waits for the last run */
 
+/* The run options a batch was created with: the caller's, or with NULL
+ * options the tuned record (eat_batch_tune) or the defaults. */
+eat_status eat_batch_options(const eat_batch *b, eat_run_options *out);
+
 /* create + run + wait + free.  Returns after the batch has finished. */
 eat_status eat_query_batch(const eat_graph *const *graphs, int32_t n_graphs,
                            const int32_t *q_graph, const int32_t *q_src,
                            const int32_t *q_ts, int32_t n_q, int32_t *const *arr,
                            void *stream, const eat_run_options *ro,
                            eat_query_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Autotuning of batched launches.
+ *
+ * Run options change the speed of a batch, never its answers (the answer of a
+ * query is unique).  eat_batch_tune runs the batch (same arguments as
+ * eat_batch_create) under each of a fixed set of candidates -- threads per
+ * query 1024 / 768 / 512, connection types in flight per lane (a wave
+ * evaluates 64 x that many (type, cluster) lookups at once: the clusters in
+ * flight per wave), virtual warps of 16 / 32 lanes per active stop (threads
+ * per edge, Sections II-F and IV-B), arrival windows, the topology-driven
+ * schedule and the compact header form -- fingerprints every result slab on
+ * the device and requires all candidates to agree (EAT_ERR_DEVICE otherwise),
+ * times each with HIP events on `stream`, and returns the fastest in *best.
+ * The choice is recorded for this device, these graphs (their sizes and
+ * layout) and n_q; eat_batch_create with NULL options uses the record.  With
+ * the environment variable EAT_TUNE_FILE naming a file, records are appended
+ * to it and read back by later processes.  Without a record, NULL options
+ * mean 768-thread queries when n_q exceeds the device's CU count, else the
+ * eat_run_options defaults.  On return the slabs hold the batch's answers.
+ * Synchronous; allocates device memory for the candidates' batches.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t reps;        /* timed runs per candidate (per stream); 0 = 3 */
+  int32_t n_streams;   /* timed runs alternate over this many streams (1..4), each
+                          with its own prepared batch, as a caller that overlaps
+                          consecutive batches issues them; 0 = 1 */
+  int32_t reserved[6]; /* must be zero */
+} eat_tune_options;
+
+typedef struct {
+  eat_run_options options;
+  float ms;            /* mean time per run */
+  int32_t reserved;
+} eat_tune_result;
+
+/* results (host array of results_cap, nullable when results_cap = 0) receives
+ * every candidate's time; *n_results (nullable) their count. */
+eat_status eat_batch_tune(const eat_graph *const *graphs, int32_t n_graphs,
+                          const int32_t *q_graph, const int32_t *q_src, const int32_t *q_ts,
+                          int32_t n_q, int32_t *const *arr, void *stream,
+                          const eat_tune_options *opt, eat_run_options *best,
+                          eat_tune_result *results, int32_t results_cap, int32_t *n_results);
 
 /* ---------------------------------------------------------------------------
  * Serving sessions: continuous batching over device-resident graphs.

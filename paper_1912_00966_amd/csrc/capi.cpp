@@ -36,17 +36,39 @@ eat_status hip_err(hipError_t e, const char *what) {
   return set_err(EAT_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Device properties are read once per device and kept for the process: a
+// plain query then costs no property query (hipGetDeviceProperties is slow).
 eat_status device_limits(int dev, DeviceLimits *out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static DeviceLimits cache[kMaxDevices];
+  static bool known[kMaxDevices] = {};
+  if (dev < 0) return set_err(EAT_ERR_DEVICE, "no current HIP device");
+  if (dev < kMaxDevices) {
+    std::lock_guard<std::mutex> lk(mu);
+    if (known[dev]) {
+      *out = cache[dev];
+      return EAT_OK;
+    }
+  }
   hipDeviceProp_t p;
   HIP_TRY(hipGetDeviceProperties(&p, dev));
-  out->cus = p.multiProcessorCount;
+  DeviceLimits lim;
+  lim.cus = p.multiProcessorCount;
   // leave room for the kernel's static shared variables
-  out->lds = p.sharedMemPerBlock > 1024 ? p.sharedMemPerBlock - 1024 : p.sharedMemPerBlock;
+  lim.lds = p.sharedMemPerBlock > 1024 ? p.sharedMemPerBlock - 1024 : p.sharedMemPerBlock;
   int xcc = 0;
-  if (hipDeviceGetAttribute(&xcc, hipDeviceAttributeNumberOfXccs, dev) == hipSuccess && xcc > 0) out->xccs = xcc;
+  if (hipDeviceGetAttribute(&xcc, hipDeviceAttributeNumberOfXccs, dev) == hipSuccess && xcc > 0) lim.xccs = xcc;
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
-    out->ns_per_tick = (int64_t)((1000000.0 / khz) * 1024.0);
+    lim.ns_per_tick = (int64_t)((1000000.0 / khz) * 1024.0);
+  std::snprintf(lim.name, sizeof(lim.name), "%s", p.gcnArchName);
+  if (dev < kMaxDevices) {
+    std::lock_guard<std::mutex> lk(mu);
+    cache[dev] = lim;
+    known[dev] = true;
+  }
+  *out = lim;
   return EAT_OK;
 }
 
@@ -61,16 +83,6 @@ using eat::device_limits;
 using eat::make_plan;
 
 
-struct eat_batch {
-  int device = 0;
-  int32_t n_q = 0;
-  int tpv = 0, ub = 1, kind = 0, block = 1024, grid = 0;
-  size_t lds = 0;
-  RunArgs args{};
-  void *d_buf = nullptr;
-  hipEvent_t done = nullptr;
-  bool ran = false;
-};
 
 // ---------------------------------------------------------------------------
 // status / version
@@ -186,7 +198,7 @@ GraphBytes graph_bytes(const eat_layout &L, bool with_grid) {
   b.pool = align_up(std::max<size_t>(L.pool.size(), 1) * 4);
   b.side = with_grid ? align_up(T * 16) : 0;
   b.tail = with_grid ? align_up(T * 4) : 0;
-  b.grid = with_grid ? align_up(T * (size_t)L.n_clusters * 32) : 0;
+  b.grid = with_grid ? align_up(T * (size_t)L.n_clusters * 16) : 0;
   b.desc = align_up(sizeof(GraphDev));
   b.stats = align_up(sizeof(eat_query_stats)) + align_up(4);
   b.total = b.vt + b.ty + b.hdr + b.pool + b.side + b.tail + b.grid + b.desc + b.stats;
@@ -213,7 +225,9 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, const eat_build_opti
   const bool hybrid = L->kind == EAT_LAYOUT_HYBRID;
   const bool need_hi = hybrid && L->n_clusters > 32;
   const int64_t T = L->n_types;
-  bool with_grid = hybrid && header_grid == 0 && T > 0 && T * (int64_t)L->n_clusters < ((int64_t)1 << 31);
+  // grid entries address pool arrays with 30 bits and are indexed with 31
+  bool with_grid = hybrid && header_grid == 0 && T > 0 && T * (int64_t)L->n_clusters < ((int64_t)1 << 31) &&
+                   (int64_t)L->pool.size() < ((int64_t)1 << 30);
   GraphBytes b = graph_bytes(*L, with_grid);
   hipError_t e = hipMalloc(&g->d_buf, b.total);
   if (e != hipSuccess && with_grid) {  // the grid is an accelerator: go without it
@@ -307,6 +321,7 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, const eat_build_opti
   }
   if (ue == hipSuccess) ue = up(g->desc.pool, L->pool.data(), L->pool.size() * 4);
   if (ue == hipSuccess) ue = up(g->d_desc, &g->desc, sizeof(GraphDev));
+  if (ue == hipSuccess) ue = hipMemset(g->d_failed, 0, sizeof(int32_t));
   if (ue == hipSuccess && with_grid) ue = eat::launch_build_grid(g->desc, nullptr);
   if (ue == hipSuccess) ue = hipDeviceSynchronize();
   if (ue != hipSuccess) {
@@ -345,6 +360,17 @@ extern "C" void eat_graph_free(eat_graph *g) {
 extern "C" eat_status eat_graph_info(const eat_graph *g, eat_graph_info_t *out) {
   if (!g || !out) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL argument");
   *out = g->info;
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_graph_failures(const eat_graph *g, int32_t *count) {
+  if (!g || !count) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL argument");
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != g->device) HIP_TRY(hipSetDevice(g->device));
+  const hipError_t e = hipMemcpy(count, g->d_failed, sizeof(int32_t), hipMemcpyDeviceToHost);
+  if (cur != g->device) (void)hipSetDevice(cur);
+  if (e != hipSuccess) return hip_err(e, "reading the failure count");
   return EAT_OK;
 }
 
@@ -408,6 +434,8 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   pl->block = o.threads_per_query ? o.threads_per_query : kBlock;
   if (pl->block != kBlock && o.threads_per_vertex != 0)
     return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query 512 or 768 needs threads_per_vertex 0");
+  if (pl->block == kBlockMid && pl->ub != 1)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query 768 runs one connection type per lane");
   pl->window = o.time_window == 0 ? 7200 : (o.time_window < 0 ? 0 : o.time_window);
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;
@@ -451,18 +479,27 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   return EAT_OK;
 }
 
+bool query_before(const eat_graph *const *graphs, const QueryDev &a, const QueryDev &b) {
+  const eat_graph *ga = graphs[(size_t)a.graph], *gb = graphs[(size_t)b.graph];
+  if (ga->info.n_vertices != gb->info.n_vertices) return ga->info.n_vertices > gb->info.n_vertices;
+  if (a.graph != b.graph) return a.graph < b.graph;
+  const int32_t ra = ga->rank[(size_t)a.s], rb = gb->rank[(size_t)b.s];
+  if (ra != rb) return ra < rb;
+  return a.index < b.index;
+}
+
+int32_t bucket_offsets(int64_t n, int n_buckets, int32_t *off) {
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(n_buckets, std::max<int64_t>(n, 1)));
+  for (int b = 0; b <= nb; ++b) off[b] = (int32_t)(n * b / nb);
+  return nb;
+}
+
 void order_queries(const std::vector<const eat_graph *> &graphs, std::vector<QueryDev> &qs,
                    int n_buckets, std::vector<int32_t> &off) {
-  std::stable_sort(qs.begin(), qs.end(), [&](const QueryDev &a, const QueryDev &b) {
-    const eat_graph *ga = graphs[(size_t)a.graph], *gb = graphs[(size_t)b.graph];
-    if (ga->info.n_vertices != gb->info.n_vertices) return ga->info.n_vertices > gb->info.n_vertices;
-    if (a.graph != b.graph) return a.graph < b.graph;
-    return ga->rank[(size_t)a.s] < gb->rank[(size_t)b.s];
-  });
-  const int64_t n = (int64_t)qs.size();
-  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(n_buckets, std::max<int64_t>(n, 1)));
-  off.assign((size_t)nb + 1, 0);
-  for (int b = 0; b <= nb; ++b) off[(size_t)b] = (int32_t)(n * b / nb);
+  const eat_graph *const *g = graphs.data();
+  std::sort(qs.begin(), qs.end(), [&](const QueryDev &a, const QueryDev &b) { return query_before(g, a, b); });
+  off.assign((size_t)std::max(1, n_buckets) + 1, 0);
+  off.resize((size_t)bucket_offsets((int64_t)qs.size(), n_buckets, off.data()) + 1);
 }
 
 void apply_plan(const Plan &pl, RunArgs *a) {
@@ -510,7 +547,7 @@ extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32
   eat_graph *gm = const_cast<eat_graph *>(g);
   if (!stats) {
     a.stats = nullptr;
-    a.n_failed = nullptr;
+    a.n_failed = g->d_failed;  // read by eat_graph_failures
     hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, kind, pl.block, 1, pl.lds, hs);
     if (e != hipSuccess) return hip_err(e, "relaxation launch");
     return EAT_OK;
@@ -559,8 +596,13 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
     qs[(size_t)i] = QueryDev{gi, q_src[i], q_ts[i], i, arr[i]};
     max_v = std::max(max_v, g->info.n_vertices);
   }
+  // no options: the tuned record for this device, graph set and batch size,
+  // else the defaults
+  eat_run_options chosen{};
+  if (ro) chosen = *ro;
+  else if (!eat::tuned_options(dev, graphs, n_graphs, n_q, &chosen)) chosen = eat::default_batch_options(dev, n_q);
   Plan pl;
-  eat_status st = make_plan(ro, max_v, dev, &pl);
+  eat_status st = make_plan(&chosen, max_v, dev, &pl);
   if (st != EAT_OK) return st;
   int kind = 0;
   st = eat::exec_kind(graphs, n_graphs, pl.headers, &kind);
@@ -582,6 +624,7 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   b->kind = kind;
   b->block = pl.block;
   b->lds = pl.lds;
+  b->options = chosen;
   const size_t b_g = align_up((size_t)n_graphs * sizeof(GraphDev));
   const size_t b_q = align_up(std::max<size_t>((size_t)n_q, 1) * sizeof(QueryDev));
   const size_t b_s = align_up(std::max<size_t>((size_t)n_q, 1) * sizeof(eat_query_stats));
@@ -623,6 +666,12 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   a.stats = d_s;
   a.n_failed = d_c + 1;
   *out = b;
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_batch_options(const eat_batch *b, eat_run_options *out) {
+  if (!b || !out) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL argument");
+  *out = b->options;
   return EAT_OK;
 }
 

@@ -19,9 +19,9 @@ struct GraphDev {
   const int2 *hdr;         // [K + 1] hybrid (one padding entry)
   const int32_t *pool;     // departures
   // Hybrid header grid (nullptr when not built): side[T] per type
-  // {v, lam, first type of v, type count of v}; grid[2 * T * n_clusters]:
-  // two int4 per (type, cluster), {t0, c, next, m} {d2, d3, d4, d5},
-  // stop-blocked and cluster-major (spelled out at eat_graph_upload in eat.h);
+  // {v, lam, first type of v, type count of v}; grid[T * n_clusters]: one
+  // int4 per (type, cluster), {t0, c, next, m}, stop-blocked and cluster-major
+  // (spelled out at eat_graph_upload in eat.h);
   // tail[T] the tail stop of each type (diagnostics only).
   const int4 *side;
   const int4 *grid;
@@ -78,6 +78,11 @@ struct RunArgs {
   eat_query_stats *stats;    // per query, indexed by QueryDev::index; nullable
   int32_t *n_failed;         // == work + 1 in a batch; nullable
   int64_t ns_per_tick;       // device wall clock period in ns (x 1024)
+  // Per-query completion words (serving sessions; nullable): when a query has
+  // finished -- its slab and statistics written and released at system scope
+  // -- done[QueryDev::index] = epoch.  Host-visible (pinned) memory.
+  int32_t *done;
+  int32_t epoch;
 };
 
 constexpr int kBlock = 1024;      // threads per query (work-group), default
@@ -94,6 +99,9 @@ hipError_t launch_next_departure(const GraphDev *g_dev, int kind, const int32_t 
                                  const int32_t *x, int32_t *out, int32_t n, hipStream_t stream);
 // Fills g.grid from the compact headers (g as on the host: device pointers).
 hipError_t launch_build_grid(const GraphDev &g, hipStream_t stream);
+// out[qs[q].index] += fingerprint of query q's result slab (qs, graphs: device).
+hipError_t launch_slab_hash(const QueryDev *qs, const GraphDev *graphs, int32_t nq, unsigned long long *out,
+                            hipStream_t stream);
 // Work-groups of the relaxation kernel that fit on one CU with lds_bytes of LDS.
 int relax_blocks_per_cu(int tpv, int ub, int kind, int block, size_t lds_bytes);
 

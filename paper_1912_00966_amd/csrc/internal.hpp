@@ -22,6 +22,20 @@ struct eat_graph {
   std::vector<int32_t> rank;       // position of each stop in the layout order
 };
 
+// A prepared batch: device descriptors of its graphs and queries, per-query
+// statistics, launch counters, and the launch shape.
+struct eat_batch {
+  int device = 0;
+  int32_t n_q = 0;
+  int tpv = 0, ub = 1, kind = 0, block = 1024, grid = 0;
+  size_t lds = 0;
+  eat::RunArgs args{};
+  eat_run_options options{};  // the options the batch was created with (after tuning lookup)
+  void *d_buf = nullptr;
+  hipEvent_t done = nullptr;
+  bool ran = false;
+};
+
 namespace eat {
 
 // Thread-local error text returned by eat_last_error().
@@ -42,6 +56,7 @@ struct DeviceLimits {
   int xccs = 1;  // L2 domains (XCDs) that work-groups are dealt to in turn
   size_t lds = 0;
   int64_t ns_per_tick = 10 << 10;  // wall clock period in ns, fixed point x 1024
+  char name[64] = {};              // architecture name (tuning key)
 };
 eat_status device_limits(int dev, DeviceLimits *out);
 
@@ -69,6 +84,22 @@ eat_status exec_kind(const eat_graph *const *g, int32_t n, int headers, int *kin
 eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan *pl);
 // RunArgs fields that come from a plan.
 void apply_plan(const Plan &pl, RunArgs *a);
+
+// Tuned launch options recorded by eat_batch_tune for a device, a set of
+// graphs and a batch size (tune.cpp): true and *out filled if there is a record.
+bool tuned_options(int device, const eat_graph *const *graphs, int32_t n_graphs, int32_t n_q,
+                   eat_run_options *out);
+// Launch options eat_batch_create uses when the caller passes none and no
+// tuning record exists: 768-thread queries (two per CU) when the batch has
+// more queries than the device has CUs, else 1024-thread ones.
+eat_run_options default_batch_options(int device, int32_t n_q);
+
+// Launch order of two queries (see order_queries); ties broken by the query
+// index, so any sort gives the same order.
+bool query_before(const eat_graph *const *graphs, const QueryDev &a, const QueryDev &b);
+// Splits n ordered queries into min(n_buckets, n) (at least 1) contiguous
+// buckets of nearly equal size: off[0..nb] receives the offsets; returns nb.
+int32_t bucket_offsets(int64_t n, int n_buckets, int32_t *off);
 
 // Orders queries for a launch: larger graphs first, then by the layout
 // position of the source (nearby sources touch nearby data), and splits them

@@ -4,8 +4,17 @@
 // n_vertices int32 slab per admitted query), with coalescing on release.
 // Launches: each step copies the descriptors of the newly admitted queries from
 // pinned host memory to the device and launches the relaxation kernel over
-// them on one of n_streams streams; a step block (descriptors, statistics,
-// counters, event) is reused only after its previous launch has finished.
+// them on one of n_streams streams; a step block (descriptors, counters,
+// completion words, statistics, event) is reused only after its previous
+// launch has finished.  When every block is in flight, a step returns
+// EAT_ERR_BUSY instead of waiting.
+// Completion: each query's work-group writes its statistics and then its
+// completion word (system-scope release) into pinned host memory as soon as
+// the query is done, so a slot finishes on its own, not when its whole step
+// launch does; eat_session_poll reads those words without any HIP call.
+// Result copies: eat_session_copy records an event on the caller's stream; a
+// slot released before that event has passed keeps its slab range out of the
+// pool until it has, so no later query overwrites a slab still being copied.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,20 +45,32 @@ struct Slot {
   int64_t off = 0;    // words into the pool
   int64_t words = 0;  // reserved words
   eat_query_stats stats{};
+  hipEvent_t copy = nullptr;  // recorded by eat_session_copy on the caller's stream
 };
 
 struct StepBlock {
   QueryDev *d_q = nullptr;
-  eat_query_stats *d_stats = nullptr;
   int32_t *d_ctr = nullptr;
   int32_t *d_b = nullptr;               // bucket offsets
   QueryDev *h_q = nullptr;              // pinned
   int32_t *h_b = nullptr;               // pinned
-  eat_query_stats *h_stats = nullptr;   // pinned
+  eat_query_stats *h_stats = nullptr;   // pinned, written by the kernel
+  eat_query_stats *k_stats = nullptr;   // ... its device-side address
+  int32_t *h_done = nullptr;            // pinned completion words, written by the kernel
+  int32_t *k_done = nullptr;            // ... their device-side address
+  int32_t epoch = 0;                    // value of a completion word of the current launch
   hipEvent_t done = nullptr;
   hipStream_t stream = nullptr;
   std::vector<int32_t> slots;
+  std::vector<char> retired;
+  size_t n_retired = 0;
   bool in_flight = false;
+};
+
+// A released slot's slab range whose result copy may still be pending.
+struct Deferred {
+  int64_t off, words;
+  hipEvent_t copy;
 };
 
 constexpr int64_t kSlotAlignWords = 64;  // 256-byte aligned slabs
@@ -74,7 +95,9 @@ struct eat_session {
   std::deque<int32_t> finished;
   std::vector<StepBlock> blocks;
   size_t next_block = 0;
-  std::deque<size_t> order;  // in-flight blocks, oldest first
+  std::vector<size_t> order;  // in-flight blocks, oldest first
+  std::vector<Deferred> deferred;
+  std::vector<hipEvent_t> spare_events;
 };
 
 namespace {
@@ -89,15 +112,38 @@ void destroy(eat_session *S) {
     if (b.h_q) (void)hipHostFree(b.h_q);
     if (b.h_b) (void)hipHostFree(b.h_b);
     if (b.h_stats) (void)hipHostFree(b.h_stats);
+    if (b.h_done) (void)hipHostFree(b.h_done);
     if (b.d_q) (void)hipFree(b.d_q);
   }
+  for (auto &sl : S->slots)
+    if (sl.copy) (void)hipEventDestroy(sl.copy);
+  for (auto &d : S->deferred) (void)hipEventDestroy(d.copy);
+  for (auto e : S->spare_events) (void)hipEventDestroy(e);
   if (S->d_graphs) (void)hipFree(S->d_graphs);
   if (S->d_pool) (void)hipFree(S->d_pool);
   delete S;
 }
 
+void pool_give(eat_session *S, int64_t off, int64_t words);
+
+// Returns to the pool the deferred ranges whose result copies have passed.
+void reclaim(eat_session *S) {
+  size_t k = 0;
+  for (size_t i = 0; i < S->deferred.size(); ++i) {
+    Deferred &d = S->deferred[i];
+    if (hipEventQuery(d.copy) == hipSuccess) {
+      pool_give(S, d.off, d.words);
+      S->spare_events.push_back(d.copy);
+    } else {
+      S->deferred[k++] = d;
+    }
+  }
+  S->deferred.resize(k);
+}
+
 // First-fit allocation of `words` from the pool; -1 if nothing fits.
 int64_t pool_take(eat_session *S, int64_t words) {
+  if (!S->deferred.empty()) reclaim(S);
   for (auto it = S->free_ranges.begin(); it != S->free_ranges.end(); ++it) {
     if (it->second < words) continue;
     const int64_t off = it->first, len = it->second;
@@ -124,28 +170,52 @@ void pool_give(eat_session *S, int64_t off, int64_t words) {
   }
 }
 
-// Marks the slots of a finished block done and takes their statistics.
-void retire(eat_session *S, StepBlock &b) {
-  for (size_t i = 0; i < b.slots.size(); ++i) {
-    Slot &sl = S->slots[(size_t)b.slots[i]];
-    sl.stats = b.h_stats[i];
-    sl.state = kDone;
-    S->finished.push_back(b.slots[i]);
-  }
-  b.slots.clear();
-  b.in_flight = false;
+void retire_slot(eat_session *S, StepBlock &b, size_t i) {
+  Slot &sl = S->slots[(size_t)b.slots[i]];
+  sl.stats = b.h_stats[i];
+  sl.state = kDone;
+  S->finished.push_back(b.slots[i]);
+  b.retired[i] = 1;
+  ++b.n_retired;
 }
 
-eat_status retire_ready(eat_session *S, bool wait_oldest) {
-  while (!S->order.empty()) {
-    StepBlock &b = S->blocks[S->order.front()];
-    hipError_t e = wait_oldest ? hipEventSynchronize(b.done) : hipEventQuery(b.done);
-    if (e == hipErrorNotReady) return EAT_OK;
-    if (e != hipSuccess) return hip_err(e, "step completion");
-    retire(S, b);
-    S->order.pop_front();
-    if (wait_oldest) return EAT_OK;
+// Retires every slot whose completion word the kernel has written, and frees
+// the blocks whose launches have ended.  Never blocks.
+eat_status retire_ready(eat_session *S) {
+  size_t k = 0;
+  for (size_t oi = 0; oi < S->order.size(); ++oi) {
+    StepBlock &b = S->blocks[S->order[oi]];
+    for (size_t i = 0; i < b.slots.size() && b.n_retired < b.slots.size(); ++i)
+      if (!b.retired[i] && __atomic_load_n(&b.h_done[i], __ATOMIC_ACQUIRE) == b.epoch) retire_slot(S, b, i);
+    bool free_now = false;
+    if (b.n_retired == b.slots.size()) {
+      const hipError_t e = hipEventQuery(b.done);
+      if (e == hipSuccess) free_now = true;
+      else if (e != hipErrorNotReady) return hip_err(e, "step completion");
+    }
+    if (free_now) {
+      b.slots.clear();
+      b.in_flight = false;
+    } else {
+      S->order[k++] = S->order[oi];
+    }
   }
+  S->order.resize(k);
+  return EAT_OK;
+}
+
+// Waits for every launch, then retires everything.
+eat_status retire_all(eat_session *S) {
+  for (size_t bi : S->order) {
+    StepBlock &b = S->blocks[bi];
+    const hipError_t e = hipEventSynchronize(b.done);
+    if (e != hipSuccess) return hip_err(e, "step completion");
+    for (size_t i = 0; i < b.slots.size(); ++i)
+      if (!b.retired[i]) retire_slot(S, b, i);
+    b.slots.clear();
+    b.in_flight = false;
+  }
+  S->order.clear();
   return EAT_OK;
 }
 
@@ -210,18 +280,25 @@ extern "C" eat_status eat_session_create(const eat_graph *const *graphs, int32_t
   S->blocks.resize((size_t)n_streams);
   const size_t bq = eat::align_up((size_t)max_step * sizeof(QueryDev));
   const size_t bs = eat::align_up((size_t)max_step * sizeof(eat_query_stats));
+  const size_t bd = eat::align_up((size_t)max_step * sizeof(int32_t));
   for (auto &b : S->blocks) {
     void *p = nullptr;
-    if (hipMalloc(&p, bq + bs + 512) != hipSuccess) return fail(EAT_ERR_OUT_OF_MEMORY, "step block");
+    if (hipMalloc(&p, bq + 512) != hipSuccess) return fail(EAT_ERR_OUT_OF_MEMORY, "step block");
     b.d_q = static_cast<QueryDev *>(p);
-    b.d_stats = reinterpret_cast<eat_query_stats *>(static_cast<char *>(p) + bq);
-    b.d_ctr = reinterpret_cast<int32_t *>(static_cast<char *>(p) + bq + bs);
-    b.d_b = reinterpret_cast<int32_t *>(static_cast<char *>(p) + bq + bs + 256);
+    b.d_ctr = reinterpret_cast<int32_t *>(static_cast<char *>(p) + bq);
+    b.d_b = reinterpret_cast<int32_t *>(static_cast<char *>(p) + bq + 256);
     if (hipMemset(b.d_ctr, 0, 256) != hipSuccess) return fail(EAT_ERR_DEVICE, "step counters");
+    // statistics and completion words: coherent pinned memory the kernel writes
+    const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
     if (hipHostMalloc((void **)&b.h_b, 256, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&b.h_q, bq, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&b.h_stats, bs, hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc((void **)&b.h_stats, bs, mapped) != hipSuccess ||
+        hipHostMalloc((void **)&b.h_done, bd, mapped) != hipSuccess)
       return fail(EAT_ERR_OUT_OF_MEMORY, "pinned step staging");
+    if (hipHostGetDevicePointer((void **)&b.k_stats, b.h_stats, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&b.k_done, b.h_done, 0) != hipSuccess)
+      return fail(EAT_ERR_DEVICE, "device address of pinned step memory");
+    std::memset(b.h_done, 0, bd);
     if (hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess)
       return fail(EAT_ERR_DEVICE, "stream or event creation");
@@ -266,8 +343,8 @@ extern "C" eat_status eat_session_step(eat_session *S, int32_t *n_launched) {
   if (n_launched) *n_launched = 0;
   if (S->admitted.empty()) return EAT_OK;
   HIP_TRY(hipSetDevice(S->device));
-  // a free block: the next one in turn, else wait for the oldest launch
-  eat_status st = retire_ready(S, false);
+  // a free block: the next one in turn; none free: busy (never waits)
+  eat_status st = retire_ready(S);
   if (st != EAT_OK) return st;
   size_t bi = S->blocks.size();
   for (size_t k = 0; k < S->blocks.size(); ++k) {
@@ -277,17 +354,14 @@ extern "C" eat_status eat_session_step(eat_session *S, int32_t *n_launched) {
       break;
     }
   }
-  if (bi == S->blocks.size()) {  // every block busy: wait for the oldest launch
-    st = retire_ready(S, true);
-    if (st != EAT_OK) return st;
-    for (size_t k = 0; k < S->blocks.size() && bi == S->blocks.size(); ++k)
-      if (!S->blocks[k].in_flight) bi = k;
-    if (bi == S->blocks.size()) return set_err(EAT_ERR_DEVICE, "no step block became free");
-  }
+  if (bi == S->blocks.size()) return set_err(EAT_ERR_BUSY, "every step of the session is in flight");
   S->next_block = (bi + 1) % S->blocks.size();
   StepBlock &b = S->blocks[bi];
   const int32_t n = (int32_t)std::min<size_t>(S->admitted.size(), (size_t)S->max_step);
   b.slots.assign(S->admitted.begin(), S->admitted.begin() + n);
+  b.retired.assign((size_t)n, 0);
+  b.n_retired = 0;
+  b.epoch = b.epoch == INT32_MAX ? 1 : b.epoch + 1;
   S->admitted.erase(S->admitted.begin(), S->admitted.begin() + n);
   std::vector<QueryDev> qs((size_t)n);
   for (int32_t i = 0; i < n; ++i) {
@@ -309,13 +383,13 @@ extern "C" eat_status eat_session_step(eat_session *S, int32_t *n_launched) {
   a.buckets = b.d_b;
   a.n_buckets = (int32_t)boff.size() - 1;
   a.work = b.d_ctr;
-  a.stats = b.d_stats;
+  a.stats = b.k_stats;
   a.n_failed = b.d_ctr + 1;
+  a.done = b.k_done;
+  a.epoch = b.epoch;
   const int grid = std::max(1, std::min(n, S->grid_cap));
   hipError_t e = eat::launch_relax(a, S->plan.tpv, S->plan.ub, S->kind, S->plan.block, grid, S->plan.lds, b.stream);
   if (e != hipSuccess) return hip_err(e, "relaxation launch");
-  HIP_TRY(hipMemcpyAsync(b.h_stats, b.d_stats, sizeof(eat_query_stats) * (size_t)n, hipMemcpyDeviceToHost,
-                         b.stream));
   HIP_TRY(hipEventRecord(b.done, b.stream));
   b.in_flight = true;
   S->order.push_back(bi);
@@ -326,7 +400,7 @@ extern "C" eat_status eat_session_step(eat_session *S, int32_t *n_launched) {
 extern "C" eat_status eat_session_poll(eat_session *S, int32_t *done, int32_t cap, int32_t *n) {
   if (!S || !n || cap < 0 || (cap > 0 && !done)) return set_err(EAT_ERR_INVALID_ARGUMENT, "bad argument");
   *n = 0;
-  eat_status st = retire_ready(S, false);
+  eat_status st = retire_ready(S);
   if (st != EAT_OK) return st;
   while (*n < cap && !S->finished.empty()) {
     done[(*n)++] = S->finished.front();
@@ -337,11 +411,7 @@ extern "C" eat_status eat_session_poll(eat_session *S, int32_t *done, int32_t ca
 
 extern "C" eat_status eat_session_sync(eat_session *S) {
   if (!S) return set_err(EAT_ERR_INVALID_ARGUMENT, "session is NULL");
-  while (!S->order.empty()) {
-    eat_status st = retire_ready(S, true);
-    if (st != EAT_OK) return st;
-  }
-  return EAT_OK;
+  return retire_all(S);
 }
 
 extern "C" eat_status eat_session_result(eat_session *S, int32_t slot, const int32_t **arr,
@@ -362,6 +432,16 @@ extern "C" eat_status eat_session_copy(eat_session *S, int32_t slot, int32_t *ds
   if (st != EAT_OK) return st;
   if (!dst) return set_err(EAT_ERR_INVALID_ARGUMENT, "dst is NULL");
   HIP_TRY(hipMemcpyAsync(dst, src, (size_t)n * 4, hipMemcpyDefault, static_cast<hipStream_t>(stream)));
+  Slot &sl = S->slots[(size_t)slot];
+  if (!sl.copy) {
+    if (!S->spare_events.empty()) {
+      sl.copy = S->spare_events.back();
+      S->spare_events.pop_back();
+    } else {
+      HIP_TRY(hipEventCreateWithFlags(&sl.copy, hipEventDisableTiming));
+    }
+  }
+  HIP_TRY(hipEventRecord(sl.copy, static_cast<hipStream_t>(stream)));
   return EAT_OK;
 }
 
@@ -386,7 +466,13 @@ extern "C" eat_status eat_session_release(eat_session *S, int32_t slot) {
   // a finished slot may still be listed as finished if it was never polled
   auto f = std::find(S->finished.begin(), S->finished.end(), slot);
   if (f != S->finished.end()) S->finished.erase(f);
-  pool_give(S, sl.off, sl.words);
+  if (sl.copy && hipEventQuery(sl.copy) == hipErrorNotReady) {
+    // a result copy may still read the slab: keep the range until it has passed
+    S->deferred.push_back(Deferred{sl.off, sl.words, sl.copy});
+    sl.copy = nullptr;
+  } else {
+    pool_give(S, sl.off, sl.words);
+  }
   sl.state = kFree;
   S->free_ids.push_back(slot);
   return EAT_OK;

@@ -39,8 +39,9 @@ EAT_HEADERS_COMPACT = 2
 # every function include/eat.h declares
 EXPORTS = (
     "eat_layout_build", "eat_layout_free", "eat_layout_info", "eat_layout_view_get",
-    "eat_graph_build", "eat_graph_upload", "eat_graph_free", "eat_graph_info",
+    "eat_graph_build", "eat_graph_upload", "eat_graph_free", "eat_graph_info", "eat_graph_failures",
     "eat_query", "eat_batch_create", "eat_batch_run", "eat_batch_wait", "eat_batch_free",
+    "eat_batch_options", "eat_batch_tune",
     "eat_query_batch", "eat_next_departure", "eat_status_string", "eat_last_error",
     "eat_version", "eat_session_create", "eat_session_admit", "eat_session_step",
     "eat_session_poll", "eat_session_sync", "eat_session_result", "eat_session_copy",
@@ -102,6 +103,14 @@ class QueryStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class TuneOptions(ctypes.Structure):
+    _fields_ = [("reps", ctypes.c_int32), ("n_streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("options", RunOptions), ("ms", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
 class SessionOptions(ctypes.Structure):
     _fields_ = [("pool_bytes", ctypes.c_int64), ("n_streams", ctypes.c_int32),
                 ("max_step_queries", ctypes.c_int32), ("run", RunOptions),
@@ -137,6 +146,7 @@ def lib():
     L.eat_graph_free.argtypes = [_vp]
     L.eat_graph_free.restype = None
     L.eat_graph_info.argtypes = [_vp, ctypes.POINTER(GraphInfo)]
+    L.eat_graph_failures.argtypes = [_vp, _i32p]
     L.eat_query.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
                             ctypes.POINTER(RunOptions), ctypes.POINTER(QueryStats)]
     L.eat_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, _i32p, _i32p, _i32p,
@@ -146,6 +156,10 @@ def lib():
     L.eat_batch_wait.argtypes = [_vp, ctypes.POINTER(QueryStats)]
     L.eat_batch_free.argtypes = [_vp]
     L.eat_batch_free.restype = None
+    L.eat_batch_options.argtypes = [_vp, ctypes.POINTER(RunOptions)]
+    L.eat_batch_tune.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, _i32p, _i32p, _i32p, ctypes.c_int32,
+                                 ctypes.POINTER(_vp), _vp, ctypes.POINTER(TuneOptions), ctypes.POINTER(RunOptions),
+                                 ctypes.POINTER(TuneResult), ctypes.c_int32, _i32p]
     L.eat_query_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, _i32p, _i32p, _i32p,
                                   ctypes.c_int32, ctypes.POINTER(_vp), _vp,
                                   ctypes.POINTER(RunOptions), ctypes.POINTER(QueryStats)]
@@ -198,6 +212,11 @@ def _build_opts(layout, cluster_seconds, n_threads, header_grid=0):
     o.n_threads = int(n_threads)
     o.header_grid = int(header_grid)
     return o
+
+
+def options_dict(o: RunOptions) -> dict:
+    """The fields of a RunOptions structure (reserved words left out)."""
+    return {name: int(getattr(o, name)) for name, _ in RunOptions._fields_ if name != "reserved"}
 
 
 def _run_opts(options):
@@ -312,6 +331,13 @@ class Graph:
         st = eat_query(self, s, ts, out, stream=stream, options=options, stats=stats)
         return (out, st) if stats else out
 
+    def failures(self) -> int:
+        """Plain queries (run without stats) on this graph that hit their round
+        limit since it was built (eat_graph_failures)."""
+        n = ctypes.c_int32()
+        _check(lib().eat_graph_failures(self._h, ctypes.byref(n)))
+        return int(n.value)
+
     def free(self):
         if getattr(self, "_h", None):
             lib().eat_graph_free(self._h)
@@ -386,6 +412,13 @@ class Batch:
     def run(self, stream=None):
         _check(lib().eat_batch_run(self._h, _stream_handle(stream)))
 
+    def options(self) -> dict:
+        """The run options the batch was created with (eat_batch_options): the
+        caller's, else the tuned record, else the defaults."""
+        o = RunOptions()
+        _check(lib().eat_batch_options(self._h, ctypes.byref(o)))
+        return options_dict(o)
+
     def wait(self, stats: bool = False):
         if stats:
             arr = (QueryStats * max(self.n, 1))()
@@ -419,6 +452,29 @@ def eat_query_batch(graphs: Sequence[Graph], q_graph, q_src, q_ts, outs, stream=
                                  _stream_handle(stream), ctypes.byref(ro) if ro is not None else None,
                                  st))
     return [st[i].as_dict() for i in range(n)] if stats else None
+
+
+def eat_batch_tune(graphs: Sequence[Graph], q_graph, q_src, q_ts, outs, stream=None, reps: int = 0,
+                   n_streams: int = 0):
+    """Runs the library's autotuner (eat_batch_tune) on this batch; returns
+    (best options dict, [(options dict, ms per run), ...]).  Batches created
+    afterwards with options=None for the same graphs and batch size use the
+    tuned options."""
+    q_graph, q_src, q_ts = _i32(q_graph), _i32(q_src), _i32(q_ts)
+    n = len(q_src)
+    gh = (_vp * len(graphs))(*[g.handle for g in graphs])
+    ptrs = [_dev_ptr(outs[i], graphs[int(q_graph[i])].n_vertices, f"outs[{i}]") for i in range(n)]
+    ah = (_vp * max(n, 1))(*ptrs)
+    to = TuneOptions()
+    to.reps = int(reps)
+    to.n_streams = int(n_streams)
+    best = RunOptions()
+    res = (TuneResult * 64)()
+    nres = ctypes.c_int32()
+    _check(lib().eat_batch_tune(gh, len(graphs), _ptr32(q_graph), _ptr32(q_src), _ptr32(q_ts), n, ah,
+                                _stream_handle(stream), ctypes.byref(to), ctypes.byref(best), res, 64,
+                                ctypes.byref(nres)))
+    return options_dict(best), [(options_dict(res[i].options), float(res[i].ms)) for i in range(nres.value)]
 
 
 def eat_next_departure(g: Graph, type_ids, x, out, headers=EAT_HEADERS_AUTO, stream=None):
@@ -456,9 +512,14 @@ class Session:
         _check(st)
         return int(slot.value)
 
-    def step(self) -> int:
+    def step(self):
+        """Launches the admitted queries; their count, or None when every step
+        of the session is still in flight (EAT_ERR_BUSY: nothing launched)."""
         n = ctypes.c_int32()
-        _check(lib().eat_session_step(self._h, ctypes.byref(n)))
+        st = lib().eat_session_step(self._h, ctypes.byref(n))
+        if st == EAT_ERR_BUSY:
+            return None
+        _check(st)
         return int(n.value)
 
     def poll(self):

@@ -13,8 +13,9 @@ Batching policy: a step is launched when the GPU has no step in flight, when
 ``max_delay_s``.
 
 The session object only needs ``admit(graph, s, ts) -> slot | None``,
-``step() -> int``, ``poll() -> [slot]`` and ``release(slot)``; the tests drive
-the loop with a CPU stand-in that computes nothing.
+``step() -> int | None`` (None: every launch slot busy, nothing launched),
+``poll() -> [slot]`` and ``release(slot)``; the tests drive the loop with a CPU
+stand-in that computes nothing.
 """
 from __future__ import annotations
 
@@ -102,14 +103,16 @@ def serve(session, requests: Sequence[Request],
             waiting.popleft()
             inflight[slot] = r
             pending.append((slot, now))
-        # launch policy
+        # launch policy (a step refused because every launch slot is busy is
+        # retried on a later pass, after completions)
         if pending and (not steps_open or len(pending) >= min_batch or now - pending[0][1] >= max_delay_s):
             k = session.step()
-            steps_open.append({s for s, _ in list(pending)[:k]})
-            for _ in range(k):
-                pending.popleft()
-            n_steps += 1
-            launched += k
+            if k:
+                steps_open.append({s for s, _ in list(pending)[:k]})
+                for _ in range(k):
+                    pending.popleft()
+                n_steps += 1
+                launched += k
         # completions
         finished = session.poll()
         if finished:

@@ -278,14 +278,29 @@ def workload(name: str, reading: str = "S"):
     return tt, queries(tt.n_vertices, nq, qseed)
 
 
-def mixed_batch(reading: str = "S"):
+def cities(sizes: Sequence[int], first_seed: int, reading: str = "S", workers: int = 8):
+    """scaled_city(sizes[i], first_seed + i) for every i, drawn on a few threads
+    (each city has its own seeded generator, so the result does not depend on
+    the thread count)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    jobs = list(enumerate(sizes))
+    if workers <= 1:
+        return [scaled_city(n, first_seed + i, reading) for i, n in jobs]
+    with ThreadPoolExecutor(min(workers, len(jobs))) as ex:
+        return list(ex.map(lambda j: scaled_city(j[1], first_seed + j[0], reading), jobs))
+
+
+def mixed_batch(reading: str = "S", workers: int = 8):
     """Eight cities of uneven size with 512 queries each."""
-    graphs, qs = [], []
-    for i, n in enumerate(MIXED_BATCH_SIZES):
-        g = scaled_city(n, 401 + i, reading)
-        graphs.append(g)
-        qs.append(queries(n, 512, 10401 + i))
+    graphs = cities(MIXED_BATCH_SIZES, 401, reading, workers)
+    qs = [queries(n, 512, 10401 + i) for i, n in enumerate(MIXED_BATCH_SIZES)]
     return graphs, qs
+
+
+def serving_cities(reading: str = "S", workers: int = 8):
+    """The three resident cities of the serving workload (10k, 50k, 500k stops)."""
+    return cities(SERVE_SIZES, 501, reading, workers)
 
 
 def random_tiny(rng: np.random.Generator, max_v: int = 7, max_c: int = 20,

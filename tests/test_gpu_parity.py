@@ -82,7 +82,8 @@ def _types_of(view):
     ("flat", 0, eat.EAT_HEADERS_AUTO)])
 def test_next_departure_matches_definition(layout, cw, headers):
     """Per-type lookup (Sections II-B..II-D, Algorithm 6) vs min{t >= x} computed
-    from the raw connection list, for both device forms of the hybrid layout
+    from the raw connection list, for every connection type of the 1k-stop
+    city, for both device forms of the hybrid layout
     (header grid, compact headers) and the flat layout; 1800-s clusters give 48
     clusters per type (occupancy bits above 32)."""
     tt, _ = _workload("city-1k")
@@ -101,24 +102,28 @@ def test_next_departure_matches_definition(layout, cw, headers):
     g = _graph("city-1k", layout, cw)
     if layout == "hybrid":
         assert g.info.n_grid_entries == g.info.n_types * g.info.n_clusters
-    picks = rng.choice(len(tu), size=600, replace=False)
-    ids, xs = [], []
-    offs, deps = [0], []
-    for j in picks:
+    # every connection type of the city, each probed around its departures,
+    # at cluster boundaries and at random times; a few at every second of the day
+    picks = np.arange(len(tu))
+    ids, xs, segs = [], [], []
+    n_probe = 0
+    for j in list(picks) + list(rng.choice(len(tu), size=4, replace=False)):
         b, e = index[(tu[j], tv[j], tl[j])]
         d = tt.t[order[b:e]]
-        probe = np.unique(np.concatenate([d - 1, d, d + 1, np.arange(0, 90001, 3600) - 1,
-                                          np.arange(0, 90001, 3600), rng.integers(0, 90000, 20),
-                                          [0, int(tt.t.max()) + 1, 2**31 - 2]]))
-        probe = probe[probe >= 0]
+        if len(segs) < len(picks):
+            probe = np.unique(np.concatenate([d - 1, d, d + 1, np.arange(0, 90001, 3600) - 1,
+                                              np.arange(0, 90001, 3600), rng.integers(0, 90000, 20),
+                                              [0, int(tt.t.max()) + 1, 2**31 - 2]]))
+            probe = probe[probe >= 0]
+        else:
+            probe = np.arange(90001)
         ids.append(np.full(len(probe), j))
         xs.append(probe)
-    # a few types probed at every second of the day
-    for j in picks[:4]:
-        ids.append(np.full(90001, j))
-        xs.append(np.arange(90001))
+        segs.append((j, n_probe, n_probe + len(probe)))
+        n_probe += len(probe)
     ids = np.concatenate(ids).astype(np.int32)
     xs = np.concatenate(xs).astype(np.int32)
+    _say(f"  {len(picks)} types, {len(ids)} probes")
     out = torch.empty(len(ids), dtype=torch.int32, device="cuda")
     eat.eat_next_departure(g, torch.from_numpy(ids).cuda(), torch.from_numpy(xs).cuda(), out,
                            headers=headers)
@@ -126,12 +131,11 @@ def test_next_departure_matches_definition(layout, cw, headers):
     got = out.cpu().numpy()
     # expected: definition on the raw departures of each probed type
     exp = np.empty_like(got)
-    for j in np.unique(ids):
+    for j, p0, p1 in segs:
         b, e = index[(tu[j], tv[j], tl[j])]
         d = np.sort(tt.t[order[b:e]])
-        sel = ids == j
-        pos = np.searchsorted(d, xs[sel], side="left")
-        exp[sel] = np.where(pos < len(d), d[np.minimum(pos, len(d) - 1)], INF)
+        pos = np.searchsorted(d, xs[p0:p1], side="left")
+        exp[p0:p1] = np.where(pos < len(d), d[np.minimum(pos, len(d) - 1)], INF)
     # spot-check the numpy expectation against the oracle's own definition
     for k in rng.choice(len(ids), size=300, replace=False):
         j = ids[k]
@@ -246,6 +250,13 @@ def test_two_queries_per_cu_are_exact(threads, opts):
     exp = _expected("city-1k")
     g = _graph("city-1k", "hybrid")
     _say(f"{threads} threads {opts}")
+    if threads == 768 and opts.get("types_per_lane", 1) > 1:
+        # 768-thread queries run at 80 VGPRs: only one type per lane fits
+        out = torch.empty(g.n_vertices, dtype=torch.int32, device="cuda")
+        with pytest.raises(eat.EatError) as ei:
+            eat.eat_query(g, int(q.s[0]), int(q.ts[0]), out, options=dict(opts, threads_per_query=768))
+        assert ei.value.status == eat.EAT_ERR_INVALID_ARGUMENT
+        return
     for i, (s, ts) in enumerate(zip(q.s, q.ts)):
         got, st = _query(g, s, ts, threads_per_query=threads, **opts)
         assert st["status"] == 0
@@ -478,6 +489,14 @@ def test_round_limit_reports_not_converged():
     with pytest.raises(eat.EatError) as ei:
         eat.eat_query(g, int(q.s[i]), int(q.ts[i]), out, options={"max_rounds": 2}, stats=True)
     assert ei.value.status == eat.EAT_ERR_NOT_CONVERGED
+    # without stats the call is asynchronous; the graph counts the failure
+    g2 = eat.graph_from_timetable(tt)
+    assert g2.failures() == 0
+    eat.eat_query(g2, int(q.s[i]), int(q.ts[i]), out)  # converges
+    eat.eat_query(g2, int(q.s[i]), int(q.ts[i]), out, options={"max_rounds": 2})
+    eat.eat_query(g2, int(q.s[i]), int(q.ts[i]), out, options={"max_rounds": 3})
+    torch.cuda.synchronize()
+    assert g2.failures() == 2
 
 
 def test_invalid_query_arguments_leave_arr_untouched():
@@ -493,25 +512,36 @@ def test_invalid_query_arguments_leave_arr_untouched():
     assert (out.cpu().numpy() == -7).all()
 
 
-def test_autotuner_picks_an_exact_configuration(tmp_path):
+def test_autotuner_on_the_product_path():
+    """The library's autotuner times every candidate on the 50k-stop city's
+    256-query batch (all must agree on the device); a batch created afterwards
+    without run options uses the tuned options and stays bit-exact; a batch of
+    another size has no record and takes the defaults."""
     from paper_1912_00966_amd import autotune
-    tt, q = _workload("city-1k")
-    g = _graph("city-1k", "hybrid")
-    cands = [{"threads_per_vertex": 0, "types_per_lane": 1}, {"threads_per_vertex": 16},
-             {"table_cap": -1}, {"mode": eat.EAT_MODE_TOPOLOGY}]
-    cache = str(tmp_path / "tune.json")
-    best, results = autotune.tune([g], np.zeros(len(q), np.int32), q.s, q.ts, reps=2,
-                                  cache_path=cache, cands=cands)
-    assert best in cands and len(results) == len(cands)
-    best2, _ = autotune.tune([g], np.zeros(len(q), np.int32), q.s, q.ts, cache_path=cache, cands=cands)
-    assert best2 == best  # served from the cache
-    got, _ = _query(g, int(q.s[3]), int(q.ts[3]), **best)
-    assert np.array_equal(got, _expected("city-1k")[3])
-    # timed over two streams, with 512-thread queries among the candidates
-    cands2 = [{"threads_per_query": 512}, {"threads_per_query": 1024}]
-    best3, results3 = autotune.tune([g], np.zeros(len(q), np.int32), q.s, q.ts, reps=2,
-                                    cache_path=None, cands=cands2, streams=2)
-    assert best3 in cands2 and len(results3) == 2
+    tt, q = _workload("city-50k")
+    g = _graph("city-50k", "hybrid")
+    exp = _expected("city-50k")
+    V, Q = tt.n_vertices, len(q)
+    slab = torch.full((Q, V), -7, dtype=torch.int32, device="cuda")
+    _say("autotune city-50k")
+    best, results = autotune.tune([g], np.zeros(Q, np.int32), q.s, q.ts, [slab[i] for i in range(Q)],
+                                  reps=2, streams=2, verbose=True)
+    assert len(results) >= 8 and best in [o for o, _ in results]
+    assert min(ms for _, ms in results) == [ms for o, ms in results if o == best][0]
+    assert np.array_equal(slab.cpu().numpy(), exp)  # the tuner leaves the answers in the slabs
+    slab.fill_(-7)
+    b = eat.Batch([g], np.zeros(Q, np.int32), q.s, q.ts, [slab[i] for i in range(Q)], options=None)
+    assert b.options() == best
+    b.run()
+    b.wait()
+    assert np.array_equal(slab.cpu().numpy(), exp)
+    b.free()
+    b2 = eat.Batch([g], np.zeros(17, np.int32), q.s[:17], q.ts[:17], [slab[i] for i in range(17)])
+    assert b2.options()["threads_per_query"] == 0  # no record for 17 queries: the defaults
+    b2.run()
+    b2.wait()
+    assert np.array_equal(slab[:17].cpu().numpy(), exp[:17])
+    b2.free()
 
 
 def test_concurrent_batches_on_several_streams():

@@ -89,3 +89,113 @@ def test_session_api_errors_and_stats():
     sess.release(s2)
     assert sess.step() == 0
     sess.free()
+
+
+@functools.lru_cache(maxsize=None)
+def _serve_graphs():
+    """The three resident cities of the serving workload: 10k, 50k and 500k stops."""
+    tts = synth.serving_cities()
+    return tts, [eat.graph_from_timetable(t) for t in tts]
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_serving_on_the_10k_50k_500k_cities():
+    """Poisson arrivals over the 10k/50k/500k-stop cities: at least 200 served
+    answers per graph; on the 10k and 50k cities every one of them against
+    the connection scan, on the 500k city every one of them certified (source,
+    closure, witness; exact, O(|C|)); a sample also against the query alone."""
+    import os
+    import time
+    from concurrent.futures import ThreadPoolExecutor
+
+    t0 = time.time()
+    tts, graphs = _serve_graphs()
+    print(f"serving cities built in {time.time() - t0:.0f}s", flush=True)
+    sess = eat.Session(graphs, pool_bytes=1 << 30, n_streams=2)
+    reqs = serve.poisson_requests(20_000, 900, [g.n_vertices for g in graphs], seed=599)
+    got = {}
+
+    def on_done(r, slot):
+        got[r.id] = sess.result(slot).cpu().numpy()
+
+    rep = serve.serve(sess, reqs, on_done=on_done, min_batch=64, max_delay_s=50e-6)
+    sess.free()
+    assert rep.n == len(reqs) and len(got) == len(reqs)
+    print(f"served {rep.n} in {rep.wall_s:.3f}s, p50 {rep.percentile_ms(50):.3f} ms, "
+          f"p99 {rep.percentile_ms(99):.3f} ms", flush=True)
+    n_thr = max(1, min(len(os.sched_getaffinity(0)), 16))
+    with ThreadPoolExecutor(n_thr) as ex:
+        for gi, t in enumerate(tts):
+            mine = [r for r in reqs if r.graph == gi]
+            assert len(mine) >= 200, (gi, len(mine))
+            if t.n_vertices <= 100_000:
+                csa = oracle.Csa(t.u, t.v, t.t, t.lam, t.n_vertices)
+                exp = list(ex.map(lambda r: csa.query(r.s, r.ts), mine))
+                for r, e in zip(mine, exp):
+                    assert np.array_equal(got[r.id], e), r
+            else:
+                rc = list(ex.map(lambda r: oracle.certify(t.u, t.v, t.t, t.lam, t.n_vertices, r.s, r.ts,
+                                                          got[r.id]), mine))
+                assert all(x == 0 for x in rc), [r for r, x in zip(mine, rc) if x][:3]
+            for r in mine[::25]:
+                alone = graphs[gi].query(r.s, r.ts).cpu().numpy()
+                assert np.array_equal(got[r.id], alone), r
+            print(f"  city {t.n_vertices}: {len(mine)} served answers exact ({time.time() - t0:.0f}s)",
+                  flush=True)
+
+
+def test_a_query_retires_before_its_step_launch_ends():
+    """Each query of a step writes its own completion word: a query that ends
+    in one round is reported by poll while a long query of the same launch is
+    still running (tried a few times: it is a race the short query should win
+    by hundreds of microseconds)."""
+    import time
+    tt, q = synth.workload("city-50k")
+    g = eat.graph_from_timetable(tt)
+    exp = oracle.Csa(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices).query_many(q.s, q.ts)
+    heavy = int(np.argmax((exp < oracle.INF).sum(1)))
+    late = int(tt.t.max()) + 1  # departs after the last connection: one round
+    sess = eat.Session([g], pool_bytes=64 << 20, n_streams=2)
+    early = False
+    for attempt in range(5):
+        sh = sess.admit(0, int(q.s[heavy]), int(q.ts[heavy]))
+        sq = sess.admit(0, 3, late)
+        assert sess.step() == 2
+        order = []
+        t_end = time.perf_counter() + 5.0
+        while len(order) < 2 and time.perf_counter() < t_end:
+            order += sess.poll()
+        assert sorted(order) == sorted([sh, sq])
+        assert np.array_equal(sess.result(sh).cpu().numpy(), exp[heavy])
+        quick = sess.result(sq).cpu().numpy()
+        assert quick[3] == late and (np.delete(quick, 3) == oracle.INF).all()
+        sess.release(sh)
+        sess.release(sq)
+        if order[0] == sq:
+            early = True
+            break
+    sess.free()
+    assert early
+
+
+def test_steps_are_refused_not_blocked_when_every_launch_is_in_flight():
+    """With one launch slot, a second step while the first is in flight
+    returns busy (nothing launched) instead of waiting."""
+    tts, graphs = _two_graphs()
+    sess = eat.Session(graphs, pool_bytes=8 << 20, n_streams=1)
+    q = synth.queries(graphs[1].n_vertices, 64, 31)
+    slots = [sess.admit(1, int(s), int(t)) for s, t in zip(q.s, q.ts)]
+    assert sess.step() == 64
+    extra = sess.admit(0, 1, 30_000)
+    refused = sess.step()  # the 64-query launch is very likely still running
+    sess.sync()
+    if refused is None:
+        assert sess.step() == 1
+        sess.sync()
+    done = set(sess.poll())
+    assert done == set(slots) | {extra}
+    exp = oracle.Csa(tts[1].u, tts[1].v, tts[1].t, tts[1].lam, tts[1].n_vertices)
+    for s_, (src, t) in zip(slots[:8], zip(q.s, q.ts)):
+        assert np.array_equal(sess.result(s_).cpu().numpy(), exp.query(int(src), int(t)))
+    sess.free()

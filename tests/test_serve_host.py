@@ -105,3 +105,32 @@ def test_poisson_stream_is_seeded_and_well_formed():
     assert 0.35 < arr[-1] < 0.65  # ~1000 / 2000 s
     for r in a:
         assert 0 <= r.s < (50, 80)[r.graph] and 0 <= r.ts < 86400
+
+
+class BusySession(FakeSession):
+    """A session with two launch slots: a step while both are in flight is
+    refused (None), as eat_session_step's EAT_ERR_BUSY."""
+
+    def __init__(self, capacity, polls_to_finish=5, launch_slots=2):
+        super().__init__(capacity, polls_to_finish)
+        self.launch_slots = launch_slots
+        self.refused = 0
+
+    def step(self):
+        in_flight = len({t for t, _ in self.running})
+        if in_flight >= self.launch_slots:
+            self.refused += 1
+            return None
+        return super().step()
+
+
+def test_refused_steps_are_retried_and_every_request_completes():
+    reqs = serve.poisson_requests(2e6, 400, [10, 20], seed=4)
+    fake = BusySession(capacity=64)
+    seen = []
+    rep = serve.serve(fake, reqs, on_done=lambda r, slot: seen.append(r.id), min_batch=1, max_delay_s=0.0,
+                      clock=TickClock(1e-6))
+    assert sorted(seen) == list(range(400))
+    assert fake.refused > 0
+    assert sum(fake.launches) == 400 and rep.steps == len(fake.launches)
+    assert not fake.used
