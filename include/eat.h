@@ -65,7 +65,11 @@ typedef struct {
   int32_t n_threads;       /* host threads for preprocessing; 0 = all cores */
   int32_t header_grid;     /* hybrid layout on the device: 0 = also build the header
                               grid (default), -1 = compact headers only (see below) */
-  int32_t reserved[4];     /* must be zero */
+  int32_t subtrip_len;     /* *_build_trips only, sub-trip length r (Sections II-G,
+                              IV-B): 0 = round(sqrt(mean trip length)), -1 =
+                              round(sqrt(k)) for a trip of k connections, r >= 1 fixed
+                              (1 adds no shortcut) */
+  int32_t reserved[3];     /* must be zero */
 } eat_build_options;
 
 typedef struct {
@@ -87,6 +91,11 @@ typedef struct {
   int64_t n_pool;            /* int32 words of the departure pool */
   int64_t device_bytes;      /* device memory held by the graph */
   int64_t n_grid_entries;    /* header-grid entries on the device (0: no grid) */
+  int64_t n_trips;           /* *_build_trips: vehicle trips in the input */
+  int64_t n_shortcuts;       /* *_build_trips: sub-trip shortcut connections added
+                                (before de-duplication; counted in n_conn_input) */
+  int32_t subtrip_len;       /* the sub-trip length used (-1: per trip) */
+  int32_t reserved;
 } eat_graph_info_t;
 
 /* ---------------------------------------------------------------------------
@@ -137,6 +146,20 @@ typedef struct {
 eat_status eat_layout_build(const int32_t *u, const int32_t *v, const int32_t *t,
                             const int32_t *lam, int64_t n_conn, int32_t n_vertices,
                             const eat_build_options *opt, eat_layout **out);
+/* Sub-trip shortcuts (Section II-G): as eat_layout_build, with trip[i] the
+ * vehicle trip of connection i (-1: on no trip).  A trip's connections, taken
+ * in departure order, must chain as one vehicle's run: each reaches the stop
+ * the next leaves from, no later than it leaves (EAT_ERR_INVALID_ARGUMENT
+ * otherwise).  Each trip is cut into consecutive sub-trips of
+ * opt->subtrip_len connections (the last one holds the rest), and each
+ * sub-trip c_i .. c_j of two or more connections adds the connection from
+ * c_i's tail to c_j's head leaving at t_i with duration t_j + lam_j - t_i.
+ * Riding the vehicle gives the same arrival, so every query's answer is
+ * unchanged, while a relaxation round crosses a whole sub-trip at once. */
+eat_status eat_layout_build_trips(const int32_t *u, const int32_t *v, const int32_t *t,
+                                  const int32_t *lam, const int32_t *trip, int64_t n_conn,
+                                  int32_t n_vertices, const eat_build_options *opt,
+                                  eat_layout **out);
 void eat_layout_free(eat_layout *layout); /* NULL-safe */
 eat_status eat_layout_info(const eat_layout *layout, eat_graph_info_t *out);
 eat_status eat_layout_view_get(const eat_layout *layout, eat_layout_view *out);
@@ -151,6 +174,10 @@ typedef struct eat_graph eat_graph;
 eat_status eat_graph_build(const int32_t *u, const int32_t *v, const int32_t *t,
                            const int32_t *lam, int64_t n_conn, int32_t n_vertices,
                            const eat_build_options *opt, eat_graph **out);
+/* eat_layout_build_trips + eat_graph_upload. */
+eat_status eat_graph_build_trips(const int32_t *u, const int32_t *v, const int32_t *t,
+                                 const int32_t *lam, const int32_t *trip, int64_t n_conn,
+                                 int32_t n_vertices, const eat_build_options *opt, eat_graph **out);
 /* Uploads an existing host layout (the layout may be freed afterwards).  Of
  * opt (nullable) only header_grid is used.
  *
@@ -202,6 +229,21 @@ typedef enum {
   EAT_HEADERS_COMPACT = 2  /* the compact headers (one per non-empty cluster) */
 } eat_headers;
 
+typedef enum {
+  /* longest first when the batch has more queries than the launch has
+   * work-groups in flight (some work-groups run several queries one after
+   * another), else by locality */
+  EAT_ORDER_AUTO = 0,
+  /* by graph, then by the layout position of the source: queries with nearby
+   * sources run at the same time on one XCD and share its L2 */
+  EAT_ORDER_LOCALITY = 1,
+  /* the same split into per-XCD buckets, each bucket's queries by departure
+   * time, earliest first: a query leaving early reaches far more stops (the
+   * timetable thins out during the day), so the longest queries start first
+   * and the launch does not end on one long query started last */
+  EAT_ORDER_LONGEST_FIRST = 2
+} eat_query_order;
+
 typedef struct {
   int32_t threads_per_vertex; /* lanes sharing one active stop's types (virtual warps,
                                  Section IV-B): 1,2,4,..,64; 0 = wave claims (below) */
@@ -229,7 +271,9 @@ typedef struct {
                                  the arrival table (wave claims only: threads_per_vertex =
                                  0).  Two per CU raise throughput when many queries are in
                                  flight; 1024 finishes a single long query sooner.  0 = 1024 */
-  int32_t reserved[1];        /* must be zero */
+  int32_t query_order;        /* eat_query_order: the order in which a batch's work-groups
+                                 take its queries */
+  int32_t reserved[3];        /* must be zero */
 } eat_run_options;
 
 typedef struct {

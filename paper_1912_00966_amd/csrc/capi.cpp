@@ -125,6 +125,9 @@ static void fill_info(const eat_layout &L, eat_graph_info_t *o) {
   o->n_ap_clusters = L.n_ap;
   o->n_array_clusters = L.n_array;
   o->n_pool = (int64_t)L.pool.size() - eat::kPoolTail;
+  o->n_trips = L.n_trips;
+  o->n_shortcuts = L.n_shortcuts;
+  o->subtrip_len = L.subtrip_len;
 }
 
 extern "C" eat_status eat_layout_build(const int32_t *u, const int32_t *v, const int32_t *t,
@@ -149,6 +152,47 @@ extern "C" eat_status eat_layout_build(const int32_t *u, const int32_t *v, const
     return set_err(s, err);
   }
   *out = L;
+  return EAT_OK;
+}
+
+extern "C" eat_status eat_layout_build_trips(const int32_t *u, const int32_t *v, const int32_t *t,
+                                             const int32_t *lam, const int32_t *trip, int64_t n_conn,
+                                             int32_t n_vertices, const eat_build_options *opt, eat_layout **out) {
+  if (!out) return set_err(EAT_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (n_conn < 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "n_conn must be >= 0");
+  if (n_conn > 0 && (!u || !v || !t || !lam)) return set_err(EAT_ERR_INVALID_ARGUMENT, "null connection array");
+  eat_build_options o{};
+  if (opt) o = *opt;
+  std::string err;
+  eat::SubtripConns sc;
+  eat_status s;
+  std::vector<int32_t> au, av, at, al;
+  try {
+    s = eat::add_subtrip_shortcuts(u, v, t, lam, trip, n_conn, o.subtrip_len, sc, &err);
+    if (s != EAT_OK) return set_err(s, err);
+    const size_t total = (size_t)n_conn + sc.u.size();
+    au.reserve(total);
+    av.reserve(total);
+    at.reserve(total);
+    al.reserve(total);
+    au.assign(u, u + n_conn);
+    av.assign(v, v + n_conn);
+    at.assign(t, t + n_conn);
+    al.assign(lam, lam + n_conn);
+    au.insert(au.end(), sc.u.begin(), sc.u.end());
+    av.insert(av.end(), sc.v.begin(), sc.v.end());
+    at.insert(at.end(), sc.t.begin(), sc.t.end());
+    al.insert(al.end(), sc.lam.begin(), sc.lam.end());
+  } catch (const std::bad_alloc &) {
+    return set_err(EAT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
+  o.subtrip_len = 0;  // consumed here
+  s = eat_layout_build(au.data(), av.data(), at.data(), al.data(), (int64_t)au.size(), n_vertices, &o, out);
+  if (s != EAT_OK) return s;
+  (*out)->n_trips = sc.n_trips;
+  (*out)->n_shortcuts = (int64_t)sc.u.size();
+  (*out)->subtrip_len = sc.subtrip_len;
   return EAT_OK;
 }
 
@@ -346,6 +390,19 @@ extern "C" eat_status eat_graph_build(const int32_t *u, const int32_t *v, const 
   return s;
 }
 
+extern "C" eat_status eat_graph_build_trips(const int32_t *u, const int32_t *v, const int32_t *t,
+                                            const int32_t *lam, const int32_t *trip, int64_t n_conn,
+                                            int32_t n_vertices, const eat_build_options *opt, eat_graph **out) {
+  if (!out) return set_err(EAT_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  eat_layout *L = nullptr;
+  eat_status s = eat_layout_build_trips(u, v, t, lam, trip, n_conn, n_vertices, opt, &L);
+  if (s != EAT_OK) return s;
+  s = eat_graph_upload(L, opt, out);
+  eat_layout_free(L);
+  return s;
+}
+
 extern "C" void eat_graph_free(eat_graph *g) {
   if (!g) return;
   int cur = 0;
@@ -437,6 +494,9 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   if (pl->block == kBlockMid && pl->ub != 1)
     return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query 768 runs one connection type per lane");
   pl->window = o.time_window == 0 ? 7200 : (o.time_window < 0 ? 0 : o.time_window);
+  if (o.query_order < EAT_ORDER_AUTO || o.query_order > EAT_ORDER_LONGEST_FIRST)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "unknown query order");
+  pl->order = o.query_order;
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;
   const bool small = pl->block != kBlock;  // two work-groups per CU
@@ -459,10 +519,17 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   // a frontier never holds more items than there are stops (or table slots)
   const int items = std::max(64, (std::max(max_v, H) + 63) / 64 * 64);
   fcap = std::min(fcap, items);
-  const size_t slab_lds = (size_t)pl->bm_words * 4 + lists_lds(fcap);
-  auto need = [&](int h) { return std::max(table_lds(h, fcap), slab_lds); };
   // two 512- or 768-thread work-groups share a CU: each gets half its LDS
   const size_t budget = small ? lim.lds / 2 - 512 : lim.lds;
+  // slab mode (no table, or a table that overflowed): one activity bit per
+  // stop, in LDS while it fits, else in a region of HBM per work-group
+  pl->bits_global = (size_t)pl->bm_words * 4 + lists_lds(fcap) > budget;
+  if (pl->bits_global && small)
+    return set_err(EAT_ERR_UNSUPPORTED, "a graph whose activity bitmap does not fit half the LDS runs "
+                                        "1024-thread queries (threads_per_query 0 or 1024)");
+  pl->bits_stride = (pl->bm_words + 63) / 64 * 64;
+  const size_t slab_lds = (pl->bits_global ? 0 : (size_t)pl->bm_words * 4) + lists_lds(fcap);
+  auto need = [&](int h) { return std::max(table_lds(h, fcap), slab_lds); };
   while (table_auto && H >= 64 && need(H) > budget) H >>= 1;
   if (H < 64) H = 0;
   if (H && need(H) > lim.lds) return set_err(EAT_ERR_UNSUPPORTED, "table_cap too large for the device's LDS");
@@ -473,8 +540,8 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   pl->fcap = fcap;
   pl->lds = H ? need(H) : slab_lds;
   if (pl->lds > lim.lds)
-    return set_err(EAT_ERR_UNSUPPORTED, "graph too large for the on-chip activity bitmap (" +
-                                            std::to_string(pl->lds) + " bytes of LDS needed, " +
+    return set_err(EAT_ERR_UNSUPPORTED, "frontier lists too large for the device's LDS (" +
+                                            std::to_string(pl->lds) + " bytes needed, " +
                                             std::to_string(lim.lds) + " available)");
   return EAT_OK;
 }
@@ -494,12 +561,25 @@ int32_t bucket_offsets(int64_t n, int n_buckets, int32_t *off) {
   return nb;
 }
 
+void longest_first_in_buckets(QueryDev *qs, const int32_t *off, int32_t nb) {
+  for (int32_t b = 0; b < nb; ++b)
+    std::sort(qs + off[b], qs + off[b + 1], [](const QueryDev &x, const QueryDev &y) {
+      return x.ts != y.ts ? x.ts < y.ts : x.index < y.index;
+    });
+}
+
+bool use_longest_first(int order, int32_t n_q, int64_t slots) {
+  return order == EAT_ORDER_LONGEST_FIRST || (order == EAT_ORDER_AUTO && (int64_t)n_q > slots);
+}
+
 void order_queries(const std::vector<const eat_graph *> &graphs, std::vector<QueryDev> &qs,
-                   int n_buckets, std::vector<int32_t> &off) {
+                   int n_buckets, std::vector<int32_t> &off, bool longest_first) {
   const eat_graph *const *g = graphs.data();
   std::sort(qs.begin(), qs.end(), [&](const QueryDev &a, const QueryDev &b) { return query_before(g, a, b); });
   off.assign((size_t)std::max(1, n_buckets) + 1, 0);
-  off.resize((size_t)bucket_offsets((int64_t)qs.size(), n_buckets, off.data()) + 1);
+  const int32_t nb = bucket_offsets((int64_t)qs.size(), n_buckets, off.data());
+  off.resize((size_t)nb + 1);
+  if (longest_first) longest_first_in_buckets(qs.data(), off.data(), nb);
 }
 
 void apply_plan(const Plan &pl, RunArgs *a) {
@@ -508,6 +588,7 @@ void apply_plan(const Plan &pl, RunArgs *a) {
   a->mode = pl.mode;
   a->fcap = pl.fcap;
   a->bm_words = pl.bm_words;
+  a->bits_stride = pl.bits_stride;
   a->table_cap = pl.table_cap;
   a->table_bits = pl.table_bits;
   a->ns_per_tick = pl.ns_per_tick;
@@ -545,17 +626,30 @@ extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32
   a.work = nullptr;
   hipStream_t hs = static_cast<hipStream_t>(stream);
   eat_graph *gm = const_cast<eat_graph *>(g);
+  // activity bits that do not fit the LDS: a stream-ordered region of HBM,
+  // freed after the launch in stream order
+  if (pl.bits_global) {
+    HIP_TRY(hipMallocAsync(reinterpret_cast<void **>(&a.bits_global), (size_t)pl.bits_stride * 4, hs));
+  }
+  auto launch = [&]() -> hipError_t {
+    hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, kind, pl.block, 1, pl.lds, hs);
+    if (a.bits_global) {
+      const hipError_t f = hipFreeAsync(a.bits_global, hs);
+      if (e == hipSuccess) e = f;
+    }
+    return e;
+  };
   if (!stats) {
     a.stats = nullptr;
     a.n_failed = g->d_failed;  // read by eat_graph_failures
-    hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, kind, pl.block, 1, pl.lds, hs);
+    hipError_t e = launch();
     if (e != hipSuccess) return hip_err(e, "relaxation launch");
     return EAT_OK;
   }
   std::lock_guard<std::mutex> lk(gm->mu);
   a.stats = gm->d_stats;
   a.n_failed = nullptr;
-  hipError_t e = eat::launch_relax(a, pl.tpv, pl.ub, kind, pl.block, 1, pl.lds, hs);
+  hipError_t e = launch();
   if (e != hipSuccess) return hip_err(e, "relaxation launch");
   HIP_TRY(hipMemcpyAsync(stats, gm->d_stats, sizeof(eat_query_stats), hipMemcpyDeviceToHost, hs));
   HIP_TRY(hipStreamSynchronize(hs));
@@ -600,7 +694,7 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   // else the defaults
   eat_run_options chosen{};
   if (ro) chosen = *ro;
-  else if (!eat::tuned_options(dev, graphs, n_graphs, n_q, &chosen)) chosen = eat::default_batch_options(dev, n_q);
+  else if (!eat::tuned_options(dev, graphs, n_graphs, n_q, &chosen)) chosen = eat::default_batch_options(dev, n_q, max_v);
   Plan pl;
   eat_status st = make_plan(&chosen, max_v, dev, &pl);
   if (st != EAT_OK) return st;
@@ -610,9 +704,11 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   DeviceLimits lim;
   st = device_limits(dev, &lim);
   if (st != EAT_OK) return st;
+  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, pl.ub, kind, pl.block, pl.lds));
+  const int slots = lim.cus * per_cu;  // work-groups in flight
   std::vector<int32_t> boff;
   eat::order_queries(std::vector<const eat_graph *>(graphs, graphs + n_graphs), qs,
-                     std::min(lim.xccs, eat::kMaxBuckets), boff);
+                     std::min(lim.xccs, eat::kMaxBuckets), boff, eat::use_longest_first(pl.order, n_q, slots));
   const int nb = (int)boff.size() - 1;
 
   eat_batch *b = new (std::nothrow) eat_batch();
@@ -630,7 +726,9 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   const size_t b_s = align_up(std::max<size_t>((size_t)n_q, 1) * sizeof(eat_query_stats));
   const size_t b_c = align_up(eat::kCounterWords * sizeof(int32_t));
   const size_t b_b = align_up(boff.size() * sizeof(int32_t));
-  hipError_t e = hipMalloc(&b->d_buf, b_g + b_q + b_s + b_c + b_b);
+  const int grid = std::max(1, std::min<int>(n_q, slots));
+  const size_t b_bits = pl.bits_global ? align_up((size_t)grid * (size_t)pl.bits_stride * 4) : 0;
+  hipError_t e = hipMalloc(&b->d_buf, b_g + b_q + b_s + b_c + b_b + b_bits);
   if (e != hipSuccess) {
     delete b;
     return set_err(EAT_ERR_OUT_OF_MEMORY, "hipMalloc of the batch failed");
@@ -653,8 +751,7 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
     delete b;
     return hip_err(e, "batch upload");
   }
-  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, pl.ub, kind, pl.block, pl.lds));
-  b->grid = std::max(1, std::min<int>(n_q, lim.cus * per_cu));
+  b->grid = grid;
   RunArgs &a = b->args;
   a.graphs = d_g;
   a.queries = d_q;
@@ -665,6 +762,7 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   a.work = d_c;
   a.stats = d_s;
   a.n_failed = d_c + 1;
+  a.bits_global = pl.bits_global ? reinterpret_cast<uint32_t *>(p + b_g + b_q + b_s + b_c + b_b) : nullptr;
   *out = b;
   return EAT_OK;
 }

@@ -61,6 +61,10 @@ struct RunArgs {
   int32_t mode;              // eat_mode
   int32_t fcap;              // frontier list capacity (entries, multiple of 32)
   int32_t bm_words;          // activity bitmap words (>= ceil(V / 32) of every graph)
+  // Slab-mode activity bits in HBM (nullable: in LDS): work-group w uses
+  // bits_global[w * bits_stride ..], bits_stride >= bm_words.
+  uint32_t *bits_global;
+  int32_t bits_stride;
   int32_t table_cap;         // on-chip arrival table slots (power of two), 0 = none
   int32_t table_bits;        // log2(table_cap)
   int32_t window;            // arrival window of a round in seconds, 0 = none

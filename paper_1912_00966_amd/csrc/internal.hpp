@@ -73,6 +73,9 @@ struct Plan {
   int headers = EAT_HEADERS_AUTO;
   int window = 0;  // seconds, 0 = none
   int block = 1024; // threads per query
+  int order = EAT_ORDER_AUTO;
+  bool bits_global = false;  // slab-mode activity bits in HBM (they do not fit the LDS)
+  int bits_stride = 0;       // words of HBM bits per work-group
   int64_t ns_per_tick = 0;
   size_t lds = 0;
 };
@@ -91,8 +94,9 @@ bool tuned_options(int device, const eat_graph *const *graphs, int32_t n_graphs,
                    eat_run_options *out);
 // Launch options eat_batch_create uses when the caller passes none and no
 // tuning record exists: 768-thread queries (two per CU) when the batch has
-// more queries than the device has CUs, else 1024-thread ones.
-eat_run_options default_batch_options(int device, int32_t n_q);
+// more queries than the device has CUs and its largest graph (max_v stops)
+// fits a half-LDS plan, else 1024-thread ones.
+eat_run_options default_batch_options(int device, int32_t n_q, int32_t max_v);
 
 // Launch order of two queries (see order_queries); ties broken by the query
 // index, so any sort gives the same order.
@@ -105,7 +109,14 @@ int32_t bucket_offsets(int64_t n, int n_buckets, int32_t *off);
 // position of the source (nearby sources touch nearby data), and splits them
 // into n_buckets contiguous buckets of nearly equal size; off receives
 // n_buckets + 1 offsets.
+// With longest_first, each bucket's queries are then ordered by departure
+// time, earliest first (see EAT_ORDER_LONGEST_FIRST).
 void order_queries(const std::vector<const eat_graph *> &graphs, std::vector<QueryDev> &qs,
-                   int n_buckets, std::vector<int32_t> &off);
+                   int n_buckets, std::vector<int32_t> &off, bool longest_first);
+// Departure-time order inside each bucket of qs[0..n) (offsets off[0..nb]).
+void longest_first_in_buckets(QueryDev *qs, const int32_t *off, int32_t nb);
+// Whether a launch of n_q queries on `slots` work-groups in flight takes them
+// longest first (resolves EAT_ORDER_AUTO).
+bool use_longest_first(int order, int32_t n_q, int64_t slots);
 
 }  // namespace eat

@@ -171,6 +171,8 @@ eat_status build_layout(const int32_t *u, const int32_t *v, const int32_t *t,
     return fail(EAT_ERR_INVALID_ARGUMENT, "header_grid must be 0 or -1");
   for (int r : opt.reserved)
     if (r != 0) return fail(EAT_ERR_INVALID_ARGUMENT, "reserved build options must be zero");
+  if (opt.subtrip_len != 0)
+    return fail(EAT_ERR_INVALID_ARGUMENT, "subtrip_len applies to the *_build_trips functions only");
   const int nth = resolve_threads(opt.n_threads);
 
   L = eat_layout();

@@ -454,16 +454,45 @@ __device__ __forceinline__ int32_t lds_ld(const int32_t *p) {
 //   full()                    the store overflowed (checked between rounds)
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ bool mark_improved(uint32_t *bits, int32_t it) {
+// Activity bits of the slab store: one per stop, in LDS (uint32_t *) or -- for
+// a graph whose bitmap does not fit the LDS -- in the work-group's own region
+// of HBM (gp<uint32_t>), updated by global atomics at agent scope (loads
+// bypass the per-CU L1, which atomics do not update).
+__device__ __forceinline__ uint32_t bits_or(uint32_t *b, int32_t w, uint32_t m) { return atomicOr(b + w, m); }
+__device__ __forceinline__ void bits_and(uint32_t *b, int32_t w, uint32_t m) { atomicAnd(b + w, m); }
+__device__ __forceinline__ uint32_t bits_ld(uint32_t *b, int32_t w) {
+  return (uint32_t)__hip_atomic_load(reinterpret_cast<int32_t *>(b + w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void bits_st(uint32_t *b, int32_t w, uint32_t x) { b[w] = x; }
+
+// (The host pass sees plain pointers for both forms: only the LDS form there.)
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ uint32_t bits_or(gp<uint32_t> b, int32_t w, uint32_t m) {
+  return __hip_atomic_fetch_or(b + w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void bits_and(gp<uint32_t> b, int32_t w, uint32_t m) {
+  __hip_atomic_fetch_and(b + w, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t bits_ld(gp<uint32_t> b, int32_t w) {
+  return __hip_atomic_load(b + w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void bits_st(gp<uint32_t> b, int32_t w, uint32_t x) {
+  __hip_atomic_store(b + w, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+#endif
+
+template <class P>
+__device__ __forceinline__ bool mark_improved(P bits, int32_t it) {
   const uint32_t bit = 1u << (it & 31);
-  return !(atomicOr(&bits[it >> 5], bit) & bit);
+  return !(bits_or(bits, it >> 5, bit) & bit);
 }
 
 // In the caller's result slab (HBM), item = stop id; one activity bit per
-// stop in LDS.
+// stop, in LDS or in HBM (P, see bits_or).
+template <class P>
 struct SlabStore {
   gp<int32_t> arr;
-  uint32_t *bits;
+  P bits;
   int32_t n;
   __device__ __forceinline__ int32_t stop(int32_t item) const { return item; }
   __device__ __forceinline__ int32_t value(int32_t item) const { return ld_arr(arr + item); }
@@ -479,15 +508,13 @@ struct SlabStore {
     }
     return false;
   }
-  __device__ __forceinline__ bool active(int32_t item) const {
-    return (lds_ld(reinterpret_cast<int32_t *>(bits) + (item >> 5)) >> (item & 31)) & 1;
-  }
-  __device__ __forceinline__ void deactivate(int32_t item) const { atomicAnd(&bits[item >> 5], ~(1u << (item & 31))); }
+  __device__ __forceinline__ bool active(int32_t item) const { return (bits_ld(bits, item >> 5) >> (item & 31)) & 1; }
+  __device__ __forceinline__ void deactivate(int32_t item) const { bits_and(bits, item >> 5, ~(1u << (item & 31))); }
   __device__ __forceinline__ bool reactivate(int32_t item) const { return mark_improved(bits, item); }
   __device__ __forceinline__ void claim_group(int32_t g, int lane, bool) const {
     // items 64 g .. 64 g + 63 are words 2 g and 2 g + 1; no relaxation runs
     const int32_t first = (g << 6) + lane;
-    if ((lane & 31) == 0 && first < n) bits[first >> 5] = 0u;
+    if ((lane & 31) == 0 && first < n) bits_st(bits, first >> 5, 0u);
   }
   __device__ __forceinline__ bool full() const { return false; }
 };
@@ -990,6 +1017,43 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
   return true;
 }
 
+// A query with its arrivals in the result slab (no table, or the table
+// overflowed; the slab still holds infinity): activity bits `bits` (LDS or
+// HBM, cleared here), frontier lists at l in LDS.
+template <int TPV, int KIND, int U, int B, class P>
+__device__ __forceinline__ void slab_query(const RunArgs &a, const GraphG &G, gp<int32_t> arr, const QueryDev &Q,
+                                           P bits, int32_t *l, const XList X, bool topo, int32_t max_rounds,
+                                           Shared &sh, QState &qs, Ctr &c) {
+  const int tid = threadIdx.x;
+  const int32_t V = G.n_vertices;
+  const int32_t F = a.fcap;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  SlabStore<P> S;
+  S.arr = arr;
+  S.bits = bits;
+  S.n = V;
+  const int32_t VW = (V + 31) >> 5;
+  const FList l0{l, l + F, l + 2 * F}, l1{l + 3 * F, l + 4 * F, l + 5 * F};
+  for (int32_t i = tid; i < VW; i += B) bits_st(bits, i, 0u);
+  if (tid == 0) sh.over = 0;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (tid == 0) {
+    st_arr(arr + Q.s, Q.ts);
+    bits_st(bits, Q.s >> 5, 1u << (Q.s & 31));
+    l0.item[0] = Q.s;
+    l0.cnt[0] = -1;
+  }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  run_rounds<TPV, KIND, U, B>(a, G, S, V, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c);
+  // reached stops
+  int32_t mine = 0;
+  for (int32_t i = tid; i < V; i += B) mine += ld_arr(arr + i) != INF;
+  if (mine) atomicAdd(&sh.reached, mine);
+}
+
 // 768-thread work-groups share a CU two at a time (24 waves, 6 per SIMD),
 // which needs at most 80 VGPRs: asked of the compiler here.
 template <int TPV, int KIND, int U, int B>
@@ -1108,31 +1172,20 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(B == kBlockMi
     if (!done) {
       // ---- arrivals in the result slab (no table, or the table overflowed) ----------
       // An overflowed table attempt never wrote the slab: it still holds infinity.
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();
-      SlabStore S;
-      S.arr = arr;
-      S.bits = store;
-      S.n = V;
-      const int32_t VW = (V + 31) >> 5;
-      int32_t *l = reinterpret_cast<int32_t *>(store + VW);
-      const FList l0{l, l + F, l + 2 * F}, l1{l + 3 * F, l + 4 * F, l + 5 * F};
-      for (int32_t i = tid; i < VW; i += B) S.bits[i] = 0u;
-      if (tid == 0) sh.over = 0;
-      __syncthreads();
-      if (tid == 0) {
-        st_arr(arr + Q.s, Q.ts);
-        S.bits[Q.s >> 5] = 1u << (Q.s & 31);
-        l0.item[0] = Q.s;
-        l0.cnt[0] = -1;
+      // The bitmap in HBM (it does not fit the LDS) is compiled into the
+      // 1024-thread kernels only; the host runs such graphs with those.
+      bool in_hbm = false;
+      if constexpr (B == kBlock) {
+        if (a.bits_global) {  // this work-group's region of HBM
+          gp<uint32_t> bits = (gp<uint32_t>)(a.bits_global + (size_t)blockIdx.x * (size_t)a.bits_stride);
+          slab_query<TPV, KIND, U, B>(a, G, arr, Q, bits, reinterpret_cast<int32_t *>(store), X, topo, max_rounds,
+                                      sh, qs, c);
+          in_hbm = true;
+        }
       }
-      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-      __syncthreads();
-      run_rounds<TPV, KIND, U, B>(a, G, S, V, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c);
-      // reached stops
-      int32_t mine = 0;
-      for (int32_t i = tid; i < V; i += B) mine += ld_arr(arr + i) != INF;
-      if (mine) atomicAdd(&sh.reached, mine);
+      if (!in_hbm)
+        slab_query<TPV, KIND, U, B>(a, G, arr, Q, store, reinterpret_cast<int32_t *>(store + ((V + 31) >> 5)), X,
+                                    topo, max_rounds, sh, qs, c);
     }
 
     // ---- per-query statistics --------------------------------------------------

@@ -50,6 +50,7 @@ struct Slot {
 
 struct StepBlock {
   QueryDev *d_q = nullptr;
+  uint32_t *d_bits = nullptr;           // HBM activity bits per work-group (when they do not fit the LDS)
   int32_t *d_ctr = nullptr;
   int32_t *d_b = nullptr;               // bucket offsets
   QueryDev *h_q = nullptr;              // pinned
@@ -114,6 +115,7 @@ void destroy(eat_session *S) {
     if (b.h_stats) (void)hipHostFree(b.h_stats);
     if (b.h_done) (void)hipHostFree(b.h_done);
     if (b.d_q) (void)hipFree(b.d_q);
+    if (b.d_bits) (void)hipFree(b.d_bits);
   }
   for (auto &sl : S->slots)
     if (sl.copy) (void)hipEventDestroy(sl.copy);
@@ -288,6 +290,9 @@ extern "C" eat_status eat_session_create(const eat_graph *const *graphs, int32_t
     b.d_ctr = reinterpret_cast<int32_t *>(static_cast<char *>(p) + bq);
     b.d_b = reinterpret_cast<int32_t *>(static_cast<char *>(p) + bq + 256);
     if (hipMemset(b.d_ctr, 0, 256) != hipSuccess) return fail(EAT_ERR_DEVICE, "step counters");
+    if (pl.bits_global &&
+        hipMalloc((void **)&b.d_bits, (size_t)S->grid_cap * (size_t)pl.bits_stride * 4) != hipSuccess)
+      return fail(EAT_ERR_OUT_OF_MEMORY, "activity bits of a step");
     // statistics and completion words: coherent pinned memory the kernel writes
     const unsigned mapped = hipHostMallocMapped | hipHostMallocCoherent;
     if (hipHostMalloc((void **)&b.h_b, 256, hipHostMallocDefault) != hipSuccess ||
@@ -370,7 +375,7 @@ extern "C" eat_status eat_session_step(eat_session *S, int32_t *n_launched) {
     qs[(size_t)i] = QueryDev{sl.graph, sl.s, sl.ts, i, S->d_pool + sl.off};
   }
   std::vector<int32_t> boff;
-  eat::order_queries(S->graphs, qs, S->n_buckets, boff);
+  eat::order_queries(S->graphs, qs, S->n_buckets, boff, eat::use_longest_first(S->plan.order, n, S->grid_cap));
   std::copy(qs.begin(), qs.end(), b.h_q);
   std::copy(boff.begin(), boff.end(), b.h_b);
   HIP_TRY(hipMemcpyAsync(b.d_q, b.h_q, sizeof(QueryDev) * (size_t)n, hipMemcpyHostToDevice, b.stream));
@@ -387,6 +392,7 @@ extern "C" eat_status eat_session_step(eat_session *S, int32_t *n_launched) {
   a.n_failed = b.d_ctr + 1;
   a.done = b.k_done;
   a.epoch = b.epoch;
+  a.bits_global = b.d_bits;
   const int grid = std::max(1, std::min(n, S->grid_cap));
   hipError_t e = eat::launch_relax(a, S->plan.tpv, S->plan.ub, S->kind, S->plan.block, grid, S->plan.lds, b.stream);
   if (e != hipSuccess) return hip_err(e, "relaxation launch");

@@ -50,11 +50,12 @@ std::string tune_key(int device, const eat_graph *const *graphs, int32_t n_graph
   return k.str();
 }
 
-// One record per line: key, a tab, the nine option fields.
+// One record per line: key, a tab, the ten option fields.
 std::string options_text(const eat_run_options &o) {
   std::ostringstream t;
   t << o.threads_per_vertex << " " << o.mode << " " << o.max_rounds << " " << o.frontier_cap << " " << o.table_cap
-    << " " << o.types_per_lane << " " << o.headers << " " << o.time_window << " " << o.threads_per_query;
+    << " " << o.types_per_lane << " " << o.headers << " " << o.time_window << " " << o.threads_per_query << " "
+    << o.query_order;
   return t.str();
 }
 
@@ -71,7 +72,7 @@ void load_file_locked() {
     eat_run_options o{};
     std::istringstream t(line.substr(tab + 1));
     if (t >> o.threads_per_vertex >> o.mode >> o.max_rounds >> o.frontier_cap >> o.table_cap >> o.types_per_lane >>
-        o.headers >> o.time_window >> o.threads_per_query)
+        o.headers >> o.time_window >> o.threads_per_query >> o.query_order)
       g_records[line.substr(0, tab)] = o;
   }
 }
@@ -141,10 +142,15 @@ bool tuned_options(int device, const eat_graph *const *graphs, int32_t n_graphs,
   return true;
 }
 
-eat_run_options default_batch_options(int device, int32_t n_q) {
+eat_run_options default_batch_options(int device, int32_t n_q, int32_t max_v) {
   eat_run_options o{};
+  o.threads_per_query = kBlockMid;
+  Plan pl;
   DeviceLimits lim;
-  if (device_limits(device, &lim) == EAT_OK && n_q > lim.cus) o.threads_per_query = kBlockMid;
+  // two queries per CU only when the batch outnumbers the CUs and the graphs
+  // fit a half-LDS plan
+  if (device_limits(device, &lim) != EAT_OK || n_q <= lim.cus || make_plan(&o, max_v, device, &pl) != EAT_OK)
+    o.threads_per_query = 0;
   return o;
 }
 

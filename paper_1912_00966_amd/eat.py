@@ -35,11 +35,14 @@ EAT_MODE_TOPOLOGY = 2
 EAT_HEADERS_AUTO = 0
 EAT_HEADERS_GRID = 1
 EAT_HEADERS_COMPACT = 2
+EAT_ORDER_AUTO = 0
+EAT_ORDER_LOCALITY = 1
+EAT_ORDER_LONGEST_FIRST = 2
 
 # every function include/eat.h declares
 EXPORTS = (
-    "eat_layout_build", "eat_layout_free", "eat_layout_info", "eat_layout_view_get",
-    "eat_graph_build", "eat_graph_upload", "eat_graph_free", "eat_graph_info", "eat_graph_failures",
+    "eat_layout_build", "eat_layout_build_trips", "eat_layout_free", "eat_layout_info", "eat_layout_view_get",
+    "eat_graph_build", "eat_graph_build_trips", "eat_graph_upload", "eat_graph_free", "eat_graph_info", "eat_graph_failures",
     "eat_query", "eat_batch_create", "eat_batch_run", "eat_batch_wait", "eat_batch_free",
     "eat_batch_options", "eat_batch_tune",
     "eat_query_batch", "eat_next_departure", "eat_status_string", "eat_last_error",
@@ -57,7 +60,7 @@ _vp = ctypes.c_void_p
 class BuildOptions(ctypes.Structure):
     _fields_ = [("layout", ctypes.c_int32), ("cluster_seconds", ctypes.c_int32),
                 ("n_threads", ctypes.c_int32), ("header_grid", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("subtrip_len", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -69,7 +72,9 @@ class GraphInfo(ctypes.Structure):
                 ("n_edges", ctypes.c_int64), ("n_types", ctypes.c_int64),
                 ("n_headers", ctypes.c_int64), ("n_ap_clusters", ctypes.c_int64),
                 ("n_array_clusters", ctypes.c_int64), ("n_pool", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64), ("n_grid_entries", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("n_grid_entries", ctypes.c_int64),
+                ("n_trips", ctypes.c_int64), ("n_shortcuts", ctypes.c_int64),
+                ("subtrip_len", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -88,7 +93,8 @@ class RunOptions(ctypes.Structure):
                 ("max_rounds", ctypes.c_int32), ("frontier_cap", ctypes.c_int32),
                 ("table_cap", ctypes.c_int32), ("types_per_lane", ctypes.c_int32),
                 ("headers", ctypes.c_int32), ("time_window", ctypes.c_int32),
-                ("threads_per_query", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("threads_per_query", ctypes.c_int32), ("query_order", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class QueryStats(ctypes.Structure):
@@ -137,6 +143,9 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     conn = [_i32p, _i32p, _i32p, _i32p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(BuildOptions)]
     L.eat_layout_build.argtypes = conn + [ctypes.POINTER(_vp)]
+    conn_trips = [_i32p, _i32p, _i32p, _i32p, _i32p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(BuildOptions)]
+    L.eat_layout_build_trips.argtypes = conn_trips + [ctypes.POINTER(_vp)]
+    L.eat_graph_build_trips.argtypes = conn_trips + [ctypes.POINTER(_vp)]
     L.eat_layout_free.argtypes = [_vp]
     L.eat_layout_free.restype = None
     L.eat_layout_info.argtypes = [_vp, ctypes.POINTER(GraphInfo)]
@@ -205,12 +214,13 @@ def _ptr32(a):
     return a.ctypes.data_as(_i32p)
 
 
-def _build_opts(layout, cluster_seconds, n_threads, header_grid=0):
+def _build_opts(layout, cluster_seconds, n_threads, header_grid=0, subtrip_len=0):
     o = BuildOptions()
     o.layout = int(layout)
     o.cluster_seconds = int(cluster_seconds)
     o.n_threads = int(n_threads)
     o.header_grid = int(header_grid)
+    o.subtrip_len = int(subtrip_len)
     return o
 
 
@@ -295,6 +305,19 @@ class Layout:
             pass
 
 
+def eat_layout_build_trips(u, v, t, lam, trip, n_vertices, subtrip_len=0, layout=EAT_LAYOUT_HYBRID,
+                           cluster_seconds=0, n_threads=0) -> Layout:
+    """Host layout with sub-trip shortcuts (Section II-G); trip[i] = vehicle
+    trip of connection i (-1: none); subtrip_len 0 = sqrt(mean trip length),
+    -1 = sqrt(k) per trip, r >= 1 fixed."""
+    u, v, t, lam, trip = (_i32(x) for x in (u, v, t, lam, trip))
+    h = _vp()
+    o = _build_opts(layout, cluster_seconds, n_threads, 0, subtrip_len)
+    _check(lib().eat_layout_build_trips(_ptr32(u), _ptr32(v), _ptr32(t), _ptr32(lam), _ptr32(trip), len(u),
+                                        int(n_vertices), ctypes.byref(o), ctypes.byref(h)))
+    return Layout(h)
+
+
 def eat_layout_build(u, v, t, lam, n_vertices, layout=EAT_LAYOUT_HYBRID, cluster_seconds=0,
                      n_threads=0) -> Layout:
     u, v, t, lam = (_i32(x) for x in (u, v, t, lam))
@@ -361,6 +384,17 @@ def eat_graph_build(u, v, t, lam, n_vertices, layout=EAT_LAYOUT_HYBRID, cluster_
     return Graph(h)
 
 
+def eat_graph_build_trips(u, v, t, lam, trip, n_vertices, subtrip_len=0, layout=EAT_LAYOUT_HYBRID,
+                          cluster_seconds=0, n_threads=0, header_grid=0) -> Graph:
+    """Device graph with sub-trip shortcuts (see eat_layout_build_trips)."""
+    u, v, t, lam, trip = (_i32(x) for x in (u, v, t, lam, trip))
+    h = _vp()
+    o = _build_opts(layout, cluster_seconds, n_threads, header_grid, subtrip_len)
+    _check(lib().eat_graph_build_trips(_ptr32(u), _ptr32(v), _ptr32(t), _ptr32(lam), _ptr32(trip), len(u),
+                                       int(n_vertices), ctypes.byref(o), ctypes.byref(h)))
+    return Graph(h)
+
+
 def eat_graph_upload(layout: Layout, header_grid: int = 0) -> Graph:
     h = _vp()
     o = BuildOptions()
@@ -369,7 +403,15 @@ def eat_graph_upload(layout: Layout, header_grid: int = 0) -> Graph:
     return Graph(h)
 
 
-def graph_from_timetable(tt, layout=EAT_LAYOUT_HYBRID, cluster_seconds=0, header_grid=0) -> Graph:
+def graph_from_timetable(tt, layout=EAT_LAYOUT_HYBRID, cluster_seconds=0, header_grid=0,
+                         subtrip_len=None) -> Graph:
+    """subtrip_len None: the connections as given; else sub-trip shortcuts from
+    the timetable's trips (see eat_layout_build_trips)."""
+    if subtrip_len is not None:
+        if tt.trip is None:
+            raise ValueError("the timetable has no vehicle trips")
+        return eat_graph_build_trips(tt.u, tt.v, tt.t, tt.lam, tt.trip, tt.n_vertices, subtrip_len=subtrip_len,
+                                     layout=layout, cluster_seconds=cluster_seconds, header_grid=header_grid)
     return eat_graph_build(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices, layout=layout,
                            cluster_seconds=cluster_seconds, header_grid=header_grid)
 

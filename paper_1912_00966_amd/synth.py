@@ -49,6 +49,8 @@ class Timetable:
     n_edges: int
     n_types_drawn: int
     seed: int
+    # vehicle trip of each connection (-1: none), for timetables drawn as lines
+    trip: Optional[np.ndarray] = None
 
     @property
     def n_conn(self) -> int:
@@ -258,6 +260,76 @@ def scaled_city(n_stops: int, seed: int, reading: str = "S") -> Timetable:
                             200 * n_stops, seed, reading, name=f"city-{n_stops}-{reading}")
     return transit_city(n_stops, 5, (1, 4), (30, 3600), (120, 3600), 0.15, 240 * n_stops,
                         seed, reading, name=f"city-{n_stops}-{reading}")
+
+
+def transit_lines(n_stops: int, knn: int, n_lines: int, stops_per_line: Sequence[int],
+                  segment: Sequence[int], dwell: Sequence[int], headway: Sequence[int], seed: int,
+                  name: str = "lines") -> Timetable:
+    """A timetable made of vehicle trips (the trips of Section II-G).  Stops
+    are uniform in the unit square with k-NN neighbours; a line is a walk of
+    distinct neighbouring stops, served in both directions; every segment of a
+    line has a running time and every intermediate stop a dwell time, the same
+    for all its trips; a direction's trips leave the first stop every headway
+    from a start in [05:00, 07:00] until 23:00.  A trip's connection i leaves
+    stop i at t_i and reaches stop i+1 at t_i + lam_i <= t_{i+1}.
+    ``trip`` numbers each connection's trip."""
+    from scipy.spatial import cKDTree
+
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n_stops, 2))
+    k = min(knn, n_stops - 1)
+    _, nbr = cKDTree(pts).query(pts, k=k + 1)
+    nbr = nbr[:, 1:]
+    us, vs, ts, ls, trips = [], [], [], [], []
+    next_trip = 0
+    for _ in range(n_lines):
+        want = int(rng.integers(stops_per_line[0], stops_per_line[1] + 1))
+        walk = [int(rng.integers(0, n_stops))]
+        seen = {walk[0]}
+        while len(walk) < want:
+            cand = [int(x) for x in nbr[walk[-1]] if int(x) not in seen]
+            if not cand:
+                break
+            nxt = cand[int(rng.integers(0, len(cand)))]
+            walk.append(nxt)
+            seen.add(nxt)
+        if len(walk) < 2:
+            continue
+        run = rng.integers(segment[0], segment[1] + 1, size=len(walk) - 1)
+        stay = rng.integers(dwell[0], dwell[1] + 1, size=len(walk))
+        h = int(rng.integers(headway[0], headway[1] + 1))
+        for stops, seg, dw in ((walk, run, stay), (walk[::-1], run[::-1], stay[::-1])):
+            start = int(rng.integers(AP_START_LO, AP_START_HI + 1))
+            # departure offsets of the trip's connections from its first departure
+            off = np.zeros(len(stops) - 1, dtype=np.int64)
+            for i in range(1, len(stops) - 1):
+                off[i] = off[i - 1] + seg[i - 1] + dw[i]
+            n_trips = (AP_END_CAP - start) // h + 1
+            first = start + h * np.arange(n_trips, dtype=np.int64)
+            t = (first[:, None] + off[None, :]).reshape(-1)
+            us.append(np.tile(np.asarray(stops[:-1], np.int64), n_trips))
+            vs.append(np.tile(np.asarray(stops[1:], np.int64), n_trips))
+            ts.append(t)
+            ls.append(np.tile(np.asarray(seg, np.int64), n_trips))
+            trips.append(np.repeat(np.arange(next_trip, next_trip + n_trips, dtype=np.int64), len(stops) - 1))
+            next_trip += n_trips
+    u = np.concatenate(us).astype(np.int32)
+    v = np.concatenate(vs).astype(np.int32)
+    t = np.concatenate(ts).astype(np.int32)
+    lam = np.concatenate(ls).astype(np.int32)
+    trip = np.concatenate(trips).astype(np.int32)
+    order = rng.permutation(len(u))  # no order is implied by position
+    n_edges = len(np.unique(u.astype(np.int64) * n_stops + v))
+    return Timetable(name=name, n_vertices=int(n_stops), u=u[order], v=v[order], t=t[order], lam=lam[order],
+                     n_edges=int(n_edges), n_types_drawn=-1, seed=int(seed), trip=trip[order])
+
+
+def lines_city(n_stops: int = 10_000, seed: int = 601) -> Timetable:
+    """A city served by bus lines: k = 5 neighbours, lines of 8..40 stops (one
+    per 8 stops, both directions), 60..600 s segments, 0..60 s dwell, headway
+    5..30 min."""
+    return transit_lines(n_stops, 5, n_stops // 8, (8, 40), (60, 600), (0, 60), (300, 1800), seed,
+                         name=f"lines-{n_stops}")
 
 
 MIXED_BATCH_SIZES = (2_000, 5_000, 10_000, 20_000, 50_000, 100_000, 200_000, 500_000)

@@ -114,3 +114,57 @@ def test_mixed_batch_4096_queries_one_launch():
             csa.close()
             _say(f"  graph {gi} ({t.n_vertices} stops): {len(ks)} answers bit-exact ({time.time() - t0:.0f}s)")
     assert checked == 4096
+
+
+@functools.lru_cache(maxsize=None)
+def _lines_1500k():
+    """1.5M stops served by 12,000 bus lines (about 23M connections): the stop
+    bitmap (188 KB) does not fit the LDS, so slab-mode activity bits live in
+    HBM.  Sources are stops with departures, leaving between 05:00 and 09:00
+    (some queries reach over 100 stops: a 64-slot table overflows)."""
+    tt = synth.transit_lines(1_500_000, 5, 12_000, (20, 40), (60, 300), (0, 30), (900, 1800), 703,
+                             name="lines-1.5M")
+    rng = np.random.default_rng(704)
+    q = synth.Queries(s=rng.choice(np.unique(tt.u), 64).astype(np.int32),
+                      ts=rng.integers(5 * 3600, 9 * 3600, 64).astype(np.int32), seed=704)
+    csa = oracle.Csa(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices)
+    return tt, q, csa.query_many(q.s, q.ts)
+
+
+def test_graph_beyond_the_lds_bitmap_limit():
+    tt, q, exp = _lines_1500k()
+    g = eat.graph_from_timetable(tt)
+    V, Q = tt.n_vertices, len(q)
+    _say(f"lines 1.5M: {tt.n_conn} connections, max reach {int((exp < oracle.INF).sum(1).max())}")
+    slab = torch.full((Q, V), -7, dtype=torch.int32, device="cuda")
+    for opts in (None, {"table_cap": -1}, {"table_cap": -1, "mode": eat.EAT_MODE_TOPOLOGY},
+                 {"table_cap": 64}):
+        slab.fill_(-7)
+        st = eat.eat_query_batch([g], np.zeros(Q, np.int32), q.s, q.ts, [slab[i] for i in range(Q)],
+                                 options=opts, stats=True)
+        got = slab.cpu().numpy()
+        bad = [i for i in range(Q) if not np.array_equal(got[i], exp[i])]
+        assert not bad, (opts, bad[:5])
+        assert all(x["status"] == 0 for x in st)
+        if opts and opts.get("table_cap") == 64:
+            assert sum(x["spilled"] for x in st) > 0  # table overflow fell back to HBM bits
+    # single queries: the bits take a stream-ordered region of HBM
+    for i in (0, 5, 9):
+        out = torch.full((V,), -7, dtype=torch.int32, device="cuda")
+        eat.eat_query(g, int(q.s[i]), int(q.ts[i]), out, options={"table_cap": -1})
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), exp[i])
+    with pytest.raises(eat.EatError) as ei:
+        eat.eat_query(g, 0, 0, slab[0], options={"threads_per_query": 768})
+    assert ei.value.status == eat.EAT_ERR_UNSUPPORTED
+    # a serving session with slab-mode queries
+    sess = eat.Session([g], pool_bytes=64 * V * 4, options={"table_cap": -1})
+    slots = [sess.admit(0, int(q.s[i]), int(q.ts[i])) for i in range(16)]
+    assert sess.step() == 16
+    sess.sync()
+    assert sorted(sess.poll()) == sorted(slots)
+    for i, s_ in enumerate(slots):
+        assert np.array_equal(sess.result(s_).cpu().numpy(), exp[i])
+    sess.free()
+    for i in range(0, Q, 16):
+        assert _certify(tt, q.s[i], q.ts[i], exp[i]) == 0
