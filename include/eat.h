@@ -322,6 +322,23 @@ eat_status eat_batch_run(eat_batch *b, void *stream);
 eat_status eat_batch_wait(eat_batch *b, eat_query_stats *stats);
 void eat_batch_free(eat_batch *b); /* NULL-safe; waits for the last run */
 
+/* eat_query_batch without any allocation, for callers that cannot allocate:
+ * code being captured into a HIP graph, tight serving loops, and harnesses
+ * that forbid hipMalloc.  Same arguments, checks, results and statistics as
+ * eat_query_batch; returns after the batch has finished.  Its device-side
+ * state lives in a fixed scratch array that each GPU the library runs on holds
+ * until the process ends (about 1 MiB), so at most 8192 queries over at most
+ * 64 graphs per call (EAT_ERR_INVALID_ARGUMENT beyond).  Every call on a GPU
+ * shares that GPU's array and rewrites it: calls that overlap on one GPU (from
+ * several processes, or on several streams without ordering) race; the calls
+ * of one process are serialized by a lock.  Calls no hipMalloc, hipFree or
+ * other allocating routine. */
+eat_status eat_query_batch_static(const eat_graph *const *graphs, int32_t n_graphs,
+                                  const int32_t *q_graph, const int32_t *q_src,
+                                  const int32_t *q_ts, int32_t n_q, int32_t *const *arr,
+                                  void *stream, const eat_run_options *ro,
+                                  eat_query_stats *stats);
+
 /* The run options a batch was created with: the caller's, or with NULL
  * options the tuned record (eat_batch_tune) or the defaults. */
 eat_status eat_batch_options(const eat_batch *b, eat_run_options *out);

@@ -44,7 +44,7 @@ EXPORTS = (
     "eat_layout_build", "eat_layout_build_trips", "eat_layout_free", "eat_layout_info", "eat_layout_view_get",
     "eat_graph_build", "eat_graph_build_trips", "eat_graph_upload", "eat_graph_free", "eat_graph_info", "eat_graph_failures",
     "eat_query", "eat_batch_create", "eat_batch_run", "eat_batch_wait", "eat_batch_free",
-    "eat_batch_options", "eat_batch_tune",
+    "eat_batch_options", "eat_batch_tune", "eat_query_batch_static",
     "eat_query_batch", "eat_next_departure", "eat_status_string", "eat_last_error",
     "eat_version", "eat_session_create", "eat_session_admit", "eat_session_step",
     "eat_session_poll", "eat_session_sync", "eat_session_result", "eat_session_copy",
@@ -172,6 +172,7 @@ def lib():
     L.eat_query_batch.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, _i32p, _i32p, _i32p,
                                   ctypes.c_int32, ctypes.POINTER(_vp), _vp,
                                   ctypes.POINTER(RunOptions), ctypes.POINTER(QueryStats)]
+    L.eat_query_batch_static.argtypes = L.eat_query_batch.argtypes
     L.eat_next_departure.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int32, _vp]
     L.eat_status_string.argtypes = [ctypes.c_int]
     L.eat_status_string.restype = ctypes.c_char_p
@@ -493,6 +494,26 @@ def eat_query_batch(graphs: Sequence[Graph], q_graph, q_src, q_ts, outs, stream=
     _check(lib().eat_query_batch(gh, len(graphs), _ptr32(q_graph), _ptr32(q_src), _ptr32(q_ts), n, ah,
                                  _stream_handle(stream), ctypes.byref(ro) if ro is not None else None,
                                  st))
+    return [st[i].as_dict() for i in range(n)] if stats else None
+
+
+def eat_query_batch_static(graphs: Sequence[Graph], q_graph, q_src, q_ts, outs, stream=None,
+                           options=None, stats: bool = False):
+    """eat_query_batch through the entry point that allocates nothing
+    (eat_query_batch_static): at most 8192 queries over 64 graphs."""
+    q_graph, q_src, q_ts = _i32(q_graph), _i32(q_src), _i32(q_ts)
+    n = len(q_src)
+    gh = (_vp * len(graphs))(*[g.handle for g in graphs])
+    ptrs = []
+    for i in range(n):
+        gi = int(q_graph[i])
+        nv = graphs[gi].n_vertices if 0 <= gi < len(graphs) else 0
+        ptrs.append(_dev_ptr(outs[i], nv, f"outs[{i}]"))
+    ah = (_vp * max(n, 1))(*ptrs)
+    ro = _run_opts(options)
+    st = (QueryStats * max(n, 1))() if stats else None
+    _check(lib().eat_query_batch_static(gh, len(graphs), _ptr32(q_graph), _ptr32(q_src), _ptr32(q_ts), n, ah,
+                                        _stream_handle(stream), ctypes.byref(ro) if ro is not None else None, st))
     return [st[i].as_dict() for i in range(n)] if stats else None
 
 
