@@ -13,6 +13,10 @@ Functions (plain C in this directory, loaded through ctypes):
   te_dijkstra      -- Dijkstra on the time-expanded model (Section I).
   td_dijkstra      -- Dijkstra on the time-dependent model (Section I).
   certify          -- source / closure / witness check of an arrival array.
+  parents          -- the parent connection of every reached stop (journeys).
+  Csa.profile      -- Pareto-optimal (departure, arrival) pairs of a source over
+                      an interval of departure times, one scan per departure.
+  brute_profile    -- the same profile by enumerating every journey.
   next_departure   -- min{t in a connection type : t >= x} (Section II-B).
 """
 import ctypes
@@ -59,6 +63,14 @@ def _load():
         f.restype = ctypes.c_int
     lib.oracle_certify.argtypes = conn + [ctypes.c_int32, ctypes.c_int32, _i32p, _i32p]
     lib.oracle_certify.restype = ctypes.c_int
+    lib.oracle_parents.argtypes = conn + [ctypes.c_int32, _i32p, _i32p, _i32p, _i32p]
+    lib.oracle_parents.restype = ctypes.c_int
+    lib.oracle_profile.argtypes = [ctypes.c_int64, _i32p, _i32p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p, _i32p]
+    lib.oracle_profile.restype = ctypes.c_int
+    lib.oracle_brute_profile.argtypes = conn + [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                                ctypes.c_int32, _i32p, _i32p, _i32p]
+    lib.oracle_brute_profile.restype = ctypes.c_int
     lib.oracle_next_departure.argtypes = [ctypes.c_int64, _i32p, ctypes.c_int32]
     lib.oracle_next_departure.restype = ctypes.c_int32
     _lib = lib
@@ -98,6 +110,7 @@ class Csa:
         self._h = lib.oracle_csa_new(len(u), _p32(u), _p32(v), _p32(t), _p32(lam), self.nv)
         if not self._h:
             raise OracleError("invalid connection list (need t>=0, lam>=1, t+lam<INF, 0<=u,v<nv)")
+        self._u, self._t = u, t  # the departures of a source (profiles)
         self._keep = None
 
     def query(self, s, ts):
@@ -115,6 +128,27 @@ class Csa:
         if rc != 0:
             raise OracleError(f"csa query failed ({rc})")
         return out
+
+    def profile(self, s, t_lo, t_hi):
+        """(dep, arr): dep = the k distinct departure times of connections
+        leaving s inside [t_lo, t_hi], increasing; arr (k x nv): row i holds,
+        per stop, the arrival of the Pareto-optimal journey leaving s at dep[i]
+        (among all journeys leaving s at or after t_lo), INF where there is none
+        (always at s)."""
+        lib = _load()
+        n_dep = np.zeros(1, dtype=np.int32)
+        rc = lib.oracle_profile(len(self._u), _p32(self._u), _p32(self._t), self._h, self.nv, int(s), int(t_lo),
+                                int(t_hi), 0, None, _p32(n_dep), None)
+        if rc not in (0, 3):
+            raise OracleError(f"profile failed ({rc})")
+        k = int(n_dep[0])
+        dep = np.empty(max(k, 1), dtype=np.int32)
+        out = np.empty((max(k, 1), self.nv), dtype=np.int32)
+        rc = lib.oracle_profile(len(self._u), _p32(self._u), _p32(self._t), self._h, self.nv, int(s), int(t_lo),
+                                int(t_hi), k, _p32(dep), _p32(n_dep), _p32(out))
+        if rc != 0:
+            raise OracleError(f"profile failed ({rc})")
+        return dep[:k], out[:k]
 
     def close(self):
         if getattr(self, "_h", None):
@@ -164,6 +198,39 @@ def certify(u, v, t, lam, nv, s, ts, arr):
     if rc < 0:
         raise OracleError("certify: invalid input")
     return rc
+
+
+def parents(u, v, t, lam, nv, s, arr):
+    """(par_u, par_t, par_lam): for each reached stop x != s, the connection
+    into x realising arr[x] with the smallest tail, then the smallest duration;
+    -1 elsewhere."""
+    u, v, t, lam = _conn(u, v, t, lam)
+    arr = _arr(arr)
+    pu, pt, pl = (np.empty(nv, dtype=np.int32) for _ in range(3))
+    rc = _load().oracle_parents(len(u), _p32(u), _p32(v), _p32(t), _p32(lam), int(nv), int(s), _p32(arr),
+                                _p32(pu), _p32(pt), _p32(pl))
+    if rc != 0:
+        raise OracleError(f"parents failed ({rc}): arr is not an EAT answer")
+    return pu, pt, pl
+
+
+def brute_profile(u, v, t, lam, nv, s, t_lo, t_hi, max_paths=2_000_000):
+    """Csa.profile computed by enumerating every journey (tiny inputs)."""
+    u, v, t, lam = _conn(u, v, t, lam)
+    lib = _load()
+    n_dep = np.zeros(1, dtype=np.int32)
+    args = (len(u), _p32(u), _p32(v), _p32(t), _p32(lam), int(nv), int(s), int(t_lo), int(t_hi),
+            ctypes.c_int64(max_paths))
+    rc = lib.oracle_brute_profile(*args, 0, None, _p32(n_dep), None)
+    if rc not in (0, 3):
+        raise OracleError(f"brute_profile failed ({rc})")
+    k = int(n_dep[0])
+    dep = np.empty(max(k, 1), dtype=np.int32)
+    out = np.empty((max(k, 1), nv), dtype=np.int32)
+    rc = lib.oracle_brute_profile(*args, k, _p32(dep), _p32(n_dep), _p32(out))
+    if rc != 0:
+        raise OracleError(f"brute_profile failed ({rc})")
+    return dep[:k], out[:k]
 
 
 def next_departure(deps, x):

@@ -8,7 +8,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csa.c", "brute.c", "dijkstra.c", "certify.c"]
+SOURCES = ["csa.c", "brute.c", "dijkstra.c", "certify.c", "journeys.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

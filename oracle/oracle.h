@@ -97,6 +97,34 @@ int oracle_certify(int64_t n, const int32_t *u, const int32_t *v,
                    int32_t s, int32_t ts, const int32_t *arr,
                    int32_t *bad_vertex);
 
+/* ---- Journeys and profiles (Section I: the query variants) ------------------- */
+/* Parent connection of every stop for an EAT answer arr of the query from s:
+ * for v != s with arr[v] < INF, among the connections (u, v, t, lam) with
+ * arr[u] <= t and t + lam == arr[v], the one with the smallest u, then the
+ * smallest lam: par_u[v] = u, par_t[v] = t, par_lam[v] = lam (-1 for s and for
+ * unreached stops).  ORACLE_EINVAL if some reached v != s has no such
+ * connection (arr is then not an EAT answer). */
+int oracle_parents(int64_t n, const int32_t *u, const int32_t *v, const int32_t *t,
+                   const int32_t *lam, int32_t nv, int32_t s, const int32_t *arr,
+                   int32_t *par_u, int32_t *par_t, int32_t *par_lam);
+/* Profile of s over departures in [t_lo, t_hi]: *n_dep = the number k of
+ * distinct departure times of connections leaving s inside the interval;
+ * dep[0..k) receives them in increasing order and arr (k x nv, row-major)
+ * receives in row i, for every stop x, the arrival of the Pareto-optimal
+ * journey to x that leaves s at dep[i] (optimal among all journeys leaving s
+ * at or after t_lo), or ORACLE_INF if there is none (always for x = s).
+ * ORACLE_ELIMIT (nothing written but *n_dep) when k > cap.  Computed with one
+ * connection scan per departure (h: the scan of the same connections, whose
+ * raw u and t are passed too). */
+int oracle_profile(int64_t n, const int32_t *u, const int32_t *t, const oracle_csa *h, int32_t nv,
+                   int32_t s, int32_t t_lo, int32_t t_hi, int32_t cap, int32_t *dep, int32_t *n_dep,
+                   int32_t *arr);
+/* The same profile by enumerating every journey from s (tiny inputs; gives up
+ * with ORACLE_ELIMIT after max_paths connection sequences). */
+int oracle_brute_profile(int64_t n, const int32_t *u, const int32_t *v, const int32_t *t,
+                         const int32_t *lam, int32_t nv, int32_t s, int32_t t_lo, int32_t t_hi,
+                         int64_t max_paths, int32_t cap, int32_t *dep, int32_t *n_dep, int32_t *arr);
+
 /* ---- Next departure of one connection type (Section II-B) ------------------- */
 /* min { d[i] : d[i] >= x } over n departures in any order, or ORACLE_INF. */
 int32_t oracle_next_departure(int64_t n, const int32_t *d, int32_t x);
