@@ -68,16 +68,21 @@ DEFAULT_STREAMS = {"city-1k": 4, "city-50k": 4, "region-500k": 2, "mixed": 2}
 DEFAULT_THREADS = {"city-1k": 1024, "city-50k": 768, "region-500k": 1024, "mixed": 768}
 
 
-def profile_traffic_for(args):
+def launch_key(o):
+    """The effective launch options of a batch (eat_batch_options), as text."""
+    return ",".join(str(x) for x in (o["threads_per_query"] or 1024, o["types_per_lane"] or 1,
+                                     o["threads_per_vertex"], o["time_window"] or 7200, o["mode"], o["headers"],
+                                     o["table_cap"], o["frontier_cap"]))
+
+
+def profile_traffic_for(args, options):
     """HBM bytes per launch from the committed rocprofv3 summary of this
-    workload (profiles/k_relax_<workload>[-topology].md), for the default
-    launch options only, and only while the kernel source is the profiled one."""
-    defaults = (args.layout == "hybrid" and args.table == 0 and args.headers == "auto" and args.window == 0
-                and args.tpv == 0 and args.types_per_lane == 0 and args.threads == 0 and args.fcap == 0)
-    if not defaults:
+    workload (profiles/k_relax_<workload>[-topology].md), only while the kernel
+    source and the launch options are the profiled ones."""
+    if args.layout != "hybrid":
         return None
     name = f"k_relax_{args.workload}" + ("-topology" if args.mode == "topology" else "") + ".md"
-    return profiled_traffic(os.path.join(ROOT, "profiles", name))
+    return profiled_traffic(os.path.join(ROOT, "profiles", name), launch_key(options))
 
 
 # The sources whose code the relaxation kernel's traffic depends on.
@@ -92,19 +97,22 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def profiled_traffic(path):
+def profiled_traffic(path, key):
     """Bytes per launch measured by the rocprofv3 counter runs recorded in
-    `path`, or None when the kernel sources changed since they were taken."""
+    `path`, or None when the kernel sources or the launch options (key) differ
+    from the profiled ones."""
     if not os.path.exists(path):
         return None
     fields = {}
     for line in open(path):
         line = line.strip().lstrip("-* ").strip()
-        if ":" in line and line.startswith(("traffic_bytes_per_launch", "kernel_source_sha256")):
+        if ":" in line and line.startswith(("traffic_bytes_per_launch", "kernel_source_sha256", "launch_key")):
             k, v = line.split(":", 1)
             fields[k.strip().strip("`")] = v.strip().strip("` ")
     digest = kernel_source_digest()
     if fields.get("kernel_source_sha256") != digest or "traffic_bytes_per_launch" not in fields:
+        return None
+    if fields.get("launch_key") != key:
         return None
     return int(fields["traffic_bytes_per_launch"])
 
@@ -123,6 +131,13 @@ def host_threads():
     """Threads for the oracle: the cores this process may use, at most 16 (the
     GPU machine's CPU share)."""
     return max(1, min(len(os.sched_getaffinity(0)), 16))
+
+
+def _explicit_options(args):
+    """True when a launch option was given on the command line."""
+    return not (args.layout == "hybrid" and args.table == 0 and args.headers == "auto" and args.window == 0
+                and args.tpv == 0 and args.types_per_lane == 0 and args.threads == 0 and args.fcap == 0
+                and args.mode == "auto")
 
 
 def _opts(args):
@@ -239,8 +254,26 @@ def run_batched(args, log):
         f"{sum(g.info.device_bytes for g in graphs) / 2**30:.2f} GiB")
     Q = len(qg)
     Vq = np.array([graphs[int(gi)].n_vertices for gi in qg], np.int64)
-    opts = _opts(args)
     S = args.streams or DEFAULT_STREAMS.get(args.workload, 1)
+    tuned = None
+    if args.no_tune or _explicit_options(args):
+        opts = _opts(args)
+    else:
+        # the library's autotuner picks the launch options for this device,
+        # these graphs and this batch size (every candidate's slabs must agree);
+        # batches created without options then use its record
+        tslab = Slabs(torch, Vq, qg)
+        t0 = time.time()
+        best, results = eat.eat_batch_tune(graphs, qg, qs_, qt, tslab.views, reps=3, n_streams=S)
+        del tslab
+        torch.cuda.synchronize()
+        tuned = {"best": best, "candidates": [[o["threads_per_query"], o["types_per_lane"], o["threads_per_vertex"],
+                                               o["time_window"], o["mode"], o["headers"], round(ms, 4)]
+                                              for o, ms in results],
+                 "candidate_fields": ["threads_per_query", "types_per_lane", "threads_per_vertex", "time_window",
+                                      "mode", "headers", "ms_per_run"], "tune_s": round(time.time() - t0, 2)}
+        log(f"[bench] autotuned in {tuned['tune_s']}s: {best}")
+        opts = None
     slabs = [Slabs(torch, Vq, qg) for _ in range(S)]
     batches = [eat.Batch(graphs, qg, qs_, qt, sl.views, options=opts) for sl in slabs]
     # the current stream and S - 1 more (with the runtime's 4 hardware queues,
@@ -353,7 +386,7 @@ def run_batched(args, log):
     relax_b, fill_b = algorithmic_bytes(stats, Vq)
     achieved = relax_b / (kernel_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profile_traffic_for(args),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": profile_traffic_for(args, batches[0].options()),
                 "kernel": "k_relax", "kernel_ms": round(kernel_ms, 4),
                 "relax_bytes_per_launch": int(relax_b), "fill_bytes_per_launch": int(fill_b),
                 "frac_with_fill": round((relax_b + fill_b) / (kernel_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -387,7 +420,8 @@ def run_batched(args, log):
         "config": {"workload": wname, "graphs": [t.n_vertices for t in tts],
                    "connections": int(sum(t.n_conn for t in tts)), "queries_per_step": Q,
                    "layout": args.layout, "mode": args.mode, "streams": S,
-                   "threads_per_query": opts["threads_per_query"], "hip_graph": bool(args.graph),
+                   "threads_per_query": batches[0].options()["threads_per_query"],
+                   "launch_options": batches[0].options(), "hip_graph": bool(args.graph),
                    "digests": [t.digest() for t in tts]},
         "bit_exact": bit_exact,
         "checked_answers": checked * (len(slabs) + (1 if plain_slabs is not None else 0)),
@@ -397,6 +431,7 @@ def run_batched(args, log):
         "roofline": roofline,
         "cpu_baseline": cpu,
         "served": served,
+        "autotune": tuned,
         "per_query_mean": per_q,
         "preprocess_s": round(prep_s, 3),
     }
@@ -464,6 +499,116 @@ def serving_record(args, log, rates, requests, checks):
                      "a few also against the query alone"}
 
 
+def run_ablation(args, log):
+    """The paper's algorithm ladder on one city (--ablation): mean ms per single
+    query of each variant (connection, connection type, connection type with
+    progressions, Cluster-AP, edge, warps, ESDG), with the change flag read
+    every iteration and every ~sqrt(iterations) (the reduced transfers of
+    Section IV-C), the share of connections each examines, the cluster-width
+    and virtual-warp sweeps, the production kernel (one launch per query, and
+    batched), and the serial connection scan -- every answer checked against
+    the oracle.  Prints its own JSON line."""
+    import torch
+
+    import oracle
+    from paper_1912_00966_amd import eat, synth
+
+    name = args.workload if args.workload != "mixed" else "city-50k"
+    tt, q = synth.workload(name, reading=args.reading)
+    nq = min(args.ablation_queries, len(q))
+    s_, ts_ = q.s[:nq], q.ts[:nq]
+    t0 = time.time()
+    csa = oracle.Csa(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices)
+    exp = [csa.query(int(s_[i]), int(ts_[i])) for i in range(nq)]
+    c0 = time.perf_counter()
+    for i in range(nq):
+        csa.query(int(s_[i]), int(ts_[i]))
+    serial_ms = (time.perf_counter() - c0) * 1e3 / nq
+    log(f"[ablation] {name}: {tt.n_conn} connections, {nq} queries, serial scan {serial_ms:.3f} ms/query")
+    out = torch.empty(tt.n_vertices, dtype=torch.int32, device="cuda")
+    exact = True
+
+    def timed(run):
+        """(mean ms per query, last stats); every answer compared."""
+        nonlocal exact
+        run(0)  # warm-up
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        st = None
+        for i in range(nq):
+            st = run(i)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - a) * 1e3 / nq
+        for i in range(nq):
+            run(i)
+            exact &= bool(np.array_equal(out.cpu().numpy(), exp[i]))
+        return ms, st
+
+    rows = []
+    vg = eat.VariantGraph(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices, esdg=True)
+    log(f"[ablation] variant arrays built in {time.time() - t0:.0f}s: {vg.info}")
+    C = vg.info["n_conn"]
+    for v in range(7):
+        ws = 32 if v == eat.EAT_VARIANT_WARPS else 0
+        # iterations of this variant (for the sqrt check interval) and its work
+        its, ex = [], []
+        for i in range(nq):
+            _, st = vg.query(int(s_[i]), int(ts_[i]), v, out=out, warp_size=ws, count=True)
+            its.append(st["iterations"])
+            ex.append(st["examined"])
+        every_r = max(1, int(round(np.sqrt(np.mean(its)))))
+        for every in ((1,) if v == eat.EAT_VARIANT_ESDG else (1, every_r)):
+            ms, _ = timed(lambda i: vg.query(int(s_[i]), int(ts_[i]), v, out=out, warp_size=ws,
+                                             check_every=every)[1])
+            rows.append({"variant": eat.VARIANT_NAMES[v], "warp_size": ws, "check_every": every,
+                         "ms_per_query": round(ms, 4), "speedup_vs_serial": round(serial_ms / ms, 2),
+                         "iterations_mean": round(float(np.mean(its)), 1),
+                         "examined_frac": round(float(np.mean(ex)) / max(C, 1), 5)})
+            log(f"[ablation] {rows[-1]}")
+    warps = []
+    for ws in (1, 2, 4, 8, 16, 32, 64):
+        ms, _ = timed(lambda i: vg.query(int(s_[i]), int(ts_[i]), eat.EAT_VARIANT_WARPS, out=out, warp_size=ws)[1])
+        warps.append({"warp_size": ws, "ms_per_query": round(ms, 4)})
+    log(f"[ablation] virtual warps: {warps}")
+    vg.free()
+    # the production kernel, one launch per query and batched
+    g = eat.graph_from_timetable(tt)
+    ms_plain, _ = timed(lambda i: eat.eat_query(g, int(s_[i]), int(ts_[i]), out))
+    tpv = []
+    for t_ in (0, 1, 4, 16, 64):
+        ms, _ = timed(lambda i: eat.eat_query(g, int(s_[i]), int(ts_[i]), out, options={"threads_per_vertex": t_}))
+        tpv.append({"threads_per_vertex": t_, "ms_per_query": round(ms, 4)})
+    slab = torch.empty((nq, tt.n_vertices), dtype=torch.int32, device="cuda")
+    b = eat.Batch([g], np.zeros(nq, np.int32), s_, ts_, [slab[i] for i in range(nq)])
+    b.run()
+    b.wait()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(5):
+        b.run()
+    b.wait()
+    batched_qps = 5 * nq / (time.perf_counter() - a)
+    exact &= all(np.array_equal(r, e) for r, e in zip(slab.cpu().numpy(), exp))
+    # cluster widths (Section IV-B): Cluster-AP variant and the production kernel
+    widths = []
+    for cw in (3600, 1800, 900, 300):
+        vg = eat.VariantGraph(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices, cluster_seconds=cw)
+        ms_v, _ = timed(lambda i: vg.query(int(s_[i]), int(ts_[i]), eat.EAT_VARIANT_CLUSTER_AP, out=out)[1])
+        vg.free()
+        gw = eat.graph_from_timetable(tt, cluster_seconds=cw)
+        ms_k, _ = timed(lambda i: eat.eat_query(gw, int(s_[i]), int(ts_[i]), out))
+        gw.free()
+        widths.append({"cluster_seconds": cw, "cluster_ap_ms": round(ms_v, 4), "kernel_ms": round(ms_k, 4)})
+        log(f"[ablation] width {widths[-1]}")
+    print(json.dumps({"metric": "paper algorithm ladder: ms per EAT query (one query at a time)",
+                      "workload": f"{name} ({args.reading} reading)", "queries": nq, "connections": int(C),
+                      "serial_scan_ms": round(serial_ms, 4), "variants": rows, "virtual_warps": warps,
+                      "kernel": {"ms_per_query": round(ms_plain, 4), "speedup_vs_serial": round(serial_ms / ms_plain, 2),
+                                 "threads_per_vertex": tpv, "batched_qps": round(batched_qps, 1)},
+                      "cluster_widths": widths, "bit_exact": bool(exact),
+                      "device": torch.cuda.get_device_name()}), flush=True)
+
+
 def run_serving(args, log):
     """Open-loop serving report over all rates (--serve)."""
     import torch
@@ -510,6 +655,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-query comparison")
     ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner: per-workload default launch options (with no option flags, the "
+                         "library's autotuner picks them)")
     ap.add_argument("--no-serve", action="store_true", help="mixed workload: skip the served record")
     ap.add_argument("--served-rates", default="10000,50000", help="served record: Poisson rates (queries/s)")
     ap.add_argument("--served-requests", type=int, default=20000, help="served record: requests per rate")
@@ -520,6 +668,10 @@ def main():
     ap.add_argument("--serve", action="store_true",
                     help="full serving report: Poisson arrivals over the resident 10k/50k/500k-stop "
                          "cities at every rate of --rates (prints its own JSON line)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="the paper's algorithm ladder, cluster widths and virtual warps on one city "
+                         "(--workload city-1k or city-50k; prints its own JSON line)")
+    ap.add_argument("--ablation-queries", type=int, default=64)
     ap.add_argument("--rates", default="1000,2000,5000,10000,20000,50000")
     ap.add_argument("--requests", type=int, default=20000, help="requests per rate (--serve)")
     ap.add_argument("--serve-checks", type=int, default=200,
@@ -539,6 +691,8 @@ def main():
     log = lambda m: print(m, file=sys.stderr, flush=True)
     if args.serve:
         return run_serving(args, log)
+    if args.ablation:
+        return run_ablation(args, log)
     return run_batched(args, log)
 
 

@@ -301,6 +301,19 @@ typedef struct {
 eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32_t *arr,
                      void *stream, const eat_run_options *ro, eat_query_stats *stats);
 
+/* Goal-directed query (Section I: the earliest arrival at one destination d).
+ * Same arguments, errors and stream semantics as eat_query, plus d in
+ * [0, n_vertices).  On completion arr[d] holds the earliest arrival at d from
+ * (s, ts), EAT_INF if unreachable; every other entry of arr holds an upper
+ * bound of that stop's earliest arrival (a real arrival time, or EAT_INF):
+ * the relaxation keeps only what can still improve the arrival at d -- a stop
+ * reached no earlier than the best arrival at d found so far is neither
+ * written nor expanded -- and ends when every listed stop is at or past it.
+ * Runs the wave-claim kernels with one connection type per lane
+ * (EAT_ERR_UNSUPPORTED if ro asks for threads_per_vertex > 0). */
+eat_status eat_query_goal(const eat_graph *g, int32_t s, int32_t ts, int32_t d, int32_t *arr,
+                          void *stream, const eat_run_options *ro, eat_query_stats *stats);
+
 /* A prepared batch of n_q queries over n_graphs graphs, run by one persistent
  * launch in which each work-group takes whole queries from a shared counter.
  * q_graph/q_src/q_ts: host arrays; arr: host array of n_q device pointers, slab
@@ -311,6 +324,13 @@ eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n_graphs,
                             const int32_t *q_graph, const int32_t *q_src,
                             const int32_t *q_ts, int32_t n_q, int32_t *const *arr,
                             const eat_run_options *ro, eat_batch **out);
+/* eat_batch_create with a destination per query: q_dst[i] in [0, n_vertices)
+ * makes query i goal-directed (its slab as in eat_query_goal), -1 asks for
+ * every stop (its slab as in eat_query).  q_dst: host array of n_q. */
+eat_status eat_batch_create_goal(const eat_graph *const *graphs, int32_t n_graphs,
+                                 const int32_t *q_graph, const int32_t *q_src,
+                                 const int32_t *q_ts, const int32_t *q_dst, int32_t n_q,
+                                 int32_t *const *arr, const eat_run_options *ro, eat_batch **out);
 /* Enqueues the whole batch on stream (asynchronous; repeatable): one
  * persistent kernel launch and an event record, no allocation, memset or
  * copy -- the launch re-arms its own device counters -- so a run can be
@@ -349,6 +369,46 @@ eat_status eat_query_batch(const eat_graph *const *graphs, int32_t n_graphs,
                            const int32_t *q_ts, int32_t n_q, int32_t *const *arr,
                            void *stream, const eat_run_options *ro,
                            eat_query_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Journeys and profiles (Section I: the earliest arrival path behind an
+ * arrival time, and the profile-search variant over an interval of departure
+ * times).
+ * ------------------------------------------------------------------------- */
+/* Parent connection of every stop for the EAT answer arr (device, n_vertices
+ * int32, as written by eat_query / a batch / a session for a query from s).
+ * par (device, 3 * n_vertices int32, caller-owned) receives per stop v
+ * (u, t, lam) at par[3v .. 3v+2]: among the connections (u, v, t, lam) with
+ * arr[u] <= t and t + lam == arr[v], the one with the smallest u, then the
+ * smallest lam; -1 three times for s, for unreached stops, and for any stop
+ * whose arrival no connection realises (arr is then not an EAT answer).
+ * Following parents from a reached stop back to s gives, read forwards, a
+ * journey that leaves s no earlier than arr[s] and arrives at arr[v]; parents
+ * strictly decrease the arrival (lam >= 1), so the walk ends.  On a graph
+ * built with sub-trip shortcuts a parent can be a shortcut (one vehicle's
+ * ride over several stops).  Asynchronous on stream (a stream-ordered scratch
+ * of 8 * n_vertices bytes).  EAT_ERR_INVALID_ARGUMENT for a NULL pointer or s
+ * out of range. */
+eat_status eat_parents(const eat_graph *g, int32_t s, const int32_t *arr, int32_t *par, void *stream);
+
+/* Profile of source s over departures in [t_lo, t_hi]: the Pareto-optimal
+ * (departure, arrival) pairs of every stop among all journeys that leave s at
+ * or after t_lo, restricted to those leaving no later than t_hi.
+ * *n_dep receives the number k of distinct departure times of connections
+ * leaving s inside the interval (every Pareto departure is one of them);
+ * dep (host, cap int32) receives them in increasing order; arr (device,
+ * cap * n_vertices int32, row-major, caller-owned) receives in row i, for
+ * every stop v, the arrival of the Pareto-optimal journey to v leaving s at
+ * dep[i], or EAT_INF if no such journey is Pareto-optimal (always at v = s).
+ * Computed as one batch of k + 1 queries -- one at each dep[i] and one at the
+ * first departure after t_hi -- whose row i keeps EAT(s, dep[i])[v] only
+ * where it beats row i + 1 (a journey leaving later does no better
+ * otherwise).  Synchronous.  If k > cap nothing is computed and
+ * EAT_ERR_UNSUPPORTED is returned, except that cap = 0 with arr = NULL asks
+ * for k alone (EAT_OK).  ro: run options of the batch (NULL: tuned/defaults). */
+eat_status eat_profile(const eat_graph *g, int32_t s, int32_t t_lo, int32_t t_hi, int32_t cap,
+                       int32_t *dep, int32_t *n_dep, int32_t *arr, void *stream,
+                       const eat_run_options *ro);
 
 /* ---------------------------------------------------------------------------
  * Autotuning of batched launches.
@@ -445,6 +505,109 @@ eat_status eat_session_query_stats(eat_session *sess, int32_t slot, eat_query_st
 /* Frees a finished (or admitted but not yet launched) slot. */
 eat_status eat_session_release(eat_session *sess, int32_t slot);
 void eat_session_free(eat_session *sess); /* NULL-safe; waits for the device */
+
+/* ---------------------------------------------------------------------------
+ * The paper's algorithm ladder, for comparison on the same GPU.
+ *
+ * Each variant answers the same EAT query (bit-identical results) the way the
+ * paper describes it: a topology-driven iteration, one kernel launch per
+ * iteration over every work item of the variant, a work item acting only if
+ * its tail stop is active (active / nextactive flags, Section III-B; atomic
+ * minimum, Section III-C; early termination, Section III-D), until an
+ * iteration improves nothing.  The host reads the device's change flag after
+ * every check_every-th iteration (1: every iteration, as in Table II; the
+ * reduced transfers of Section IV-C read it every ~sqrt(d(G)) iterations;
+ * iterations past convergence change nothing).
+ * ------------------------------------------------------------------------- */
+typedef enum {
+  EAT_VARIANT_CONNECTION = 0,         /* Algorithm 4: a thread per connection */
+  EAT_VARIANT_CONNECTION_TYPE = 1,    /* Algorithm 5: a thread per connection type, linear
+                                         search of its sorted departures (Section II-B) */
+  EAT_VARIANT_CONNECTION_TYPE_AP = 2, /* Algorithm 5 with Algorithm 6 over the greedy
+                                         progression cover of the type (Section II-C) */
+  EAT_VARIANT_CLUSTER_AP = 3,         /* Section II-D: the cover of the cluster of e[u]
+                                         (cluster_seconds wide), else the first departure
+                                         of the next non-empty cluster */
+  EAT_VARIANT_EDGE = 4,               /* Section II-E: a thread per edge (u, v), Cluster-AP
+                                         for each of its types */
+  EAT_VARIANT_WARPS = 5,              /* Sections II-F, IV-B: warp_size lanes per edge */
+  EAT_VARIANT_ESDG = 6                /* Section I-A: the edge-scan-dependency graph, one
+                                         launch per level (needs esdg at build time) */
+} eat_variant;
+
+typedef struct {
+  int32_t cluster_seconds; /* cluster width of EAT_VARIANT_CLUSTER_AP / EDGE / WARPS, 1..86400;
+                              0 = 3600 */
+  int32_t esdg;            /* 1: also build the ESDG levels (host work and memory ~ C) */
+  int32_t n_threads;       /* host threads; 0 = all cores */
+  int32_t reserved[5];     /* must be zero */
+} eat_variant_build_options;
+
+typedef struct {
+  int32_t n_vertices;
+  int32_t n_clusters;      /* clusters per type: max departure / cluster_seconds + 1 */
+  int32_t n_levels;        /* ESDG levels (0 if not built) */
+  int32_t reserved;
+  int64_t n_conn;          /* after removing self-loops and duplicates */
+  int64_t n_types;
+  int64_t n_edges;
+  int64_t n_type_aps;      /* progression tuples covering whole types */
+  int64_t n_cluster_aps;   /* progression tuples covering (type, cluster) parts */
+  int64_t n_esdg_edges;    /* dependency edges of the ESDG */
+  int64_t device_bytes;
+} eat_variant_info;
+
+typedef struct {
+  int32_t variant;         /* eat_variant */
+  int32_t warp_size;       /* EAT_VARIANT_WARPS: 1, 2, 4, .., 64 lanes per edge; 0 = 32 */
+  int32_t check_every;     /* iterations between host reads of the change flag; 0 = 1 */
+  int32_t count;           /* 1: count the departures / tuples / connections examined */
+  int32_t max_iterations;  /* 0 = n_vertices + 2 */
+  int32_t reserved[3];     /* must be zero */
+} eat_variant_options;
+
+typedef struct {
+  int32_t status;          /* EAT_OK or EAT_ERR_NOT_CONVERGED */
+  int32_t iterations;      /* kernel launches of the relaxation (ESDG: levels) */
+  int32_t host_checks;     /* device-to-host reads of the change flag */
+  int32_t reserved;
+  int64_t examined;        /* with count: departures, tuples or connections examined */
+} eat_variant_stats;
+
+/* Host only.  The greedy arithmetic-progression cover of Section I-A of the n
+ * strictly increasing values d: repeatedly the smallest uncovered value a and
+ * the progression from a, made only of values of d, that covers the most
+ * uncovered values (ties: the longest, then the smallest difference).  out
+ * (host, 3 * cap) receives {first, last, difference} per progression
+ * (difference 0: a single term), in increasing first terms; *n_out their
+ * count.  EAT_ERR_UNSUPPORTED if more than cap (cap = 0 with out = NULL asks
+ * for the count, EAT_OK). */
+eat_status eat_ap_cover(const int32_t *d, int64_t n, int32_t *out, int64_t cap, int64_t *n_out);
+/* Host only.  ESDG level of each of the n_conn connections as given (Section
+ * I-A: c -> c' when c' leaves c's head at or after c arrives and no
+ * connection of the same edge leaving then arrives earlier than c'; the
+ * level is the longest path from a connection without predecessors).
+ * level: host array of n_conn; *n_levels (nullable) the number of levels,
+ * *n_edges (nullable) the number of dependency edges. */
+eat_status eat_esdg_levels(const int32_t *u, const int32_t *v, const int32_t *t, const int32_t *lam,
+                           int64_t n_conn, int32_t n_vertices, int32_t *level, int32_t *n_levels,
+                           int64_t *n_edges);
+
+typedef struct eat_variant_graph eat_variant_graph;
+
+/* Preprocesses n_conn connections (same rules as eat_layout_build) into the
+ * arrays of every variant, on the current device. */
+eat_status eat_variant_graph_build(const int32_t *u, const int32_t *v, const int32_t *t,
+                                   const int32_t *lam, int64_t n_conn, int32_t n_vertices,
+                                   const eat_variant_build_options *opt, eat_variant_graph **out);
+eat_status eat_variant_graph_info(const eat_variant_graph *g, eat_variant_info *out);
+/* One query (s, ts) by the chosen variant into arr (device, >= n_vertices
+ * int32, caller-owned): the EAT answer.  Synchronous (the host drives the
+ * iterations on stream).  stats nullable.  EAT_ERR_UNSUPPORTED for
+ * EAT_VARIANT_ESDG on a graph built without it. */
+eat_status eat_variant_query(const eat_variant_graph *g, int32_t s, int32_t ts, int32_t *arr, void *stream,
+                             const eat_variant_options *opt, eat_variant_stats *stats);
+void eat_variant_graph_free(eat_variant_graph *g); /* NULL-safe */
 
 /* ---------------------------------------------------------------------------
  * Diagnostics

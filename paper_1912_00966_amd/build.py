@@ -16,8 +16,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libeat.so")
 OBJ_DIR = os.path.join(HERE, "_build")
-SOURCES = ["layout.cpp", "subtrips.cpp", "capi.cpp", "session.cpp", "tune.cpp", "kernels.hip", "batch_static.hip",
-           "relax_grid.hip", "relax_compact.hip", "relax_flat.hip"]
+SOURCES = ["layout.cpp", "subtrips.cpp", "capi.cpp", "queries.cpp", "variants.cpp", "session.cpp", "tune.cpp",
+           "kernels.hip", "batch_static.hip", "journeys.hip", "variant_kernels.hip", "relax_grid.hip", "relax_compact.hip",
+           "relax_flat.hip"]
 ARCH = "gfx950"
 
 

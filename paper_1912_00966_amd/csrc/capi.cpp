@@ -600,18 +600,31 @@ void apply_plan(const Plan &pl, RunArgs *a) {
 // ---------------------------------------------------------------------------
 // single query
 // ---------------------------------------------------------------------------
-extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32_t *arr,
-                                void *stream, const eat_run_options *ro, eat_query_stats *stats) {
+// Goal-directed queries run the wave-claim kernels with one connection type
+// per lane.
+static eat_status goal_plan(Plan *pl) {
+  if (pl->tpv != 0)
+    return set_err(EAT_ERR_UNSUPPORTED, "goal-directed queries run with threads_per_vertex 0 (wave claims)");
+  pl->ub = 1;
+  return EAT_OK;
+}
+
+// One query; target = -1: every stop, else a goal-directed query.
+static eat_status query_impl(const eat_graph *g, int32_t s, int32_t ts, int32_t target, int32_t *arr,
+                             void *stream, const eat_run_options *ro, eat_query_stats *stats) {
   if (!g) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph is NULL");
   if (!arr) return set_err(EAT_ERR_INVALID_ARGUMENT, "arr is NULL");
   if (s < 0 || s >= g->info.n_vertices) return set_err(EAT_ERR_INVALID_ARGUMENT, "source out of range");
   if (ts < 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "ts must be >= 0");
+  if (target < -1 || target >= g->info.n_vertices)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "destination out of range");
   int cur = -1;
   HIP_TRY(hipGetDevice(&cur));
   if (cur != g->device) return set_err(EAT_ERR_INVALID_ARGUMENT, "graph lives on another device than the current one");
   Plan pl;
   eat_status st = make_plan(ro, g->info.n_vertices, g->device, &pl);
   if (st != EAT_OK) return st;
+  if (target >= 0 && (st = goal_plan(&pl)) != EAT_OK) return st;
   int kind = 0;
   st = eat::exec_kind(&g, 1, pl.headers, &kind);
   if (st != EAT_OK) return st;
@@ -619,6 +632,8 @@ extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32
   a.graphs = g->d_desc;
   a.queries = nullptr;
   a.single = QueryDev{0, s, ts, 0, arr};
+  a.goal = target >= 0 ? 1 : 0;
+  a.single_target = target;
   a.buckets = nullptr;
   a.n_buckets = 1;
   a.nq = 1;
@@ -657,13 +672,24 @@ extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32
   return EAT_OK;
 }
 
+extern "C" eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32_t *arr,
+                                void *stream, const eat_run_options *ro, eat_query_stats *stats) {
+  return query_impl(g, s, ts, -1, arr, stream, ro, stats);
+}
+
+extern "C" eat_status eat_query_goal(const eat_graph *g, int32_t s, int32_t ts, int32_t d, int32_t *arr,
+                                     void *stream, const eat_run_options *ro, eat_query_stats *stats) {
+  if (g && (d < 0 || d >= g->info.n_vertices)) return set_err(EAT_ERR_INVALID_ARGUMENT, "destination out of range");
+  return query_impl(g, s, ts, d, arr, stream, ro, stats);
+}
+
 // ---------------------------------------------------------------------------
 // batches
 // ---------------------------------------------------------------------------
-extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n_graphs,
-                                       const int32_t *q_graph, const int32_t *q_src,
-                                       const int32_t *q_ts, int32_t n_q, int32_t *const *arr,
-                                       const eat_run_options *ro, eat_batch **out) {
+// q_dst (nullable): per query a destination, or -1 for every stop.
+static eat_status batch_create(const eat_graph *const *graphs, int32_t n_graphs, const int32_t *q_graph,
+                               const int32_t *q_src, const int32_t *q_ts, const int32_t *q_dst, int32_t n_q,
+                               int32_t *const *arr, const eat_run_options *ro, eat_batch **out) {
   if (!out) return set_err(EAT_ERR_INVALID_ARGUMENT, "out is NULL");
   *out = nullptr;
   if (!graphs || n_graphs < 1) return set_err(EAT_ERR_INVALID_ARGUMENT, "need at least one graph");
@@ -679,6 +705,7 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
       return set_err(EAT_ERR_INVALID_ARGUMENT, "graph " + std::to_string(i) + " lives on another device");
   }
   std::vector<QueryDev> qs((size_t)n_q);
+  bool goal = false;
   for (int32_t i = 0; i < n_q; ++i) {
     const int32_t gi = q_graph[i];
     if (gi < 0 || gi >= n_graphs) return set_err(EAT_ERR_INVALID_ARGUMENT, "query " + std::to_string(i) + ": graph index out of range");
@@ -687,7 +714,11 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
       return set_err(EAT_ERR_INVALID_ARGUMENT, "query " + std::to_string(i) + ": source out of range");
     if (q_ts[i] < 0) return set_err(EAT_ERR_INVALID_ARGUMENT, "query " + std::to_string(i) + ": ts < 0");
     if (!arr[i]) return set_err(EAT_ERR_INVALID_ARGUMENT, "query " + std::to_string(i) + ": arr is NULL");
+    const int32_t d = q_dst ? q_dst[i] : -1;
+    if (d < -1 || d >= g->info.n_vertices)
+      return set_err(EAT_ERR_INVALID_ARGUMENT, "query " + std::to_string(i) + ": destination out of range");
     qs[(size_t)i] = QueryDev{gi, q_src[i], q_ts[i], i, arr[i]};
+    goal = goal || d >= 0;
     max_v = std::max(max_v, g->info.n_vertices);
   }
   // no options: the tuned record for this device, graph set and batch size,
@@ -695,16 +726,18 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   eat_run_options chosen{};
   if (ro) chosen = *ro;
   else if (!eat::tuned_options(dev, graphs, n_graphs, n_q, &chosen)) chosen = eat::default_batch_options(dev, n_q, max_v);
+  if (goal && !ro && chosen.threads_per_vertex != 0) chosen = eat::default_batch_options(dev, n_q, max_v);
   Plan pl;
   eat_status st = make_plan(&chosen, max_v, dev, &pl);
   if (st != EAT_OK) return st;
+  if (goal && (st = goal_plan(&pl)) != EAT_OK) return st;
   int kind = 0;
   st = eat::exec_kind(graphs, n_graphs, pl.headers, &kind);
   if (st != EAT_OK) return st;
   DeviceLimits lim;
   st = device_limits(dev, &lim);
   if (st != EAT_OK) return st;
-  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, pl.ub, kind, pl.block, pl.lds));
+  const int per_cu = std::max(1, eat::relax_blocks_per_cu(pl.tpv, pl.ub, kind, pl.block, pl.lds, goal));
   const int slots = lim.cus * per_cu;  // work-groups in flight
   std::vector<int32_t> boff;
   eat::order_queries(std::vector<const eat_graph *>(graphs, graphs + n_graphs), qs,
@@ -728,7 +761,8 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   const size_t b_b = align_up(boff.size() * sizeof(int32_t));
   const int grid = std::max(1, std::min<int>(n_q, slots));
   const size_t b_bits = pl.bits_global ? align_up((size_t)grid * (size_t)pl.bits_stride * 4) : 0;
-  hipError_t e = hipMalloc(&b->d_buf, b_g + b_q + b_s + b_c + b_b + b_bits);
+  const size_t b_t = goal ? align_up((size_t)n_q * sizeof(int32_t)) : 0;  // destinations, in query order
+  hipError_t e = hipMalloc(&b->d_buf, b_g + b_q + b_s + b_c + b_b + b_bits + b_t);
   if (e != hipSuccess) {
     delete b;
     return set_err(EAT_ERR_OUT_OF_MEMORY, "hipMalloc of the batch failed");
@@ -745,6 +779,8 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   if (e == hipSuccess && n_q > 0) e = hipMemcpy(d_q, qs.data(), qs.size() * sizeof(QueryDev), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(d_s, 0, b_s + b_c);
   if (e == hipSuccess) e = hipMemcpy(d_b, boff.data(), boff.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  int32_t *d_t = goal ? reinterpret_cast<int32_t *>(p + b_g + b_q + b_s + b_c + b_b + b_bits) : nullptr;
+  if (e == hipSuccess && goal) e = hipMemcpy(d_t, q_dst, (size_t)n_q * sizeof(int32_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
   if (e != hipSuccess) {
     (void)hipFree(b->d_buf);
@@ -763,8 +799,28 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
   a.stats = d_s;
   a.n_failed = d_c + 1;
   a.bits_global = pl.bits_global ? reinterpret_cast<uint32_t *>(p + b_g + b_q + b_s + b_c + b_b) : nullptr;
+  a.goal = goal ? 1 : 0;
+  a.targets = d_t;
   *out = b;
   return EAT_OK;
+}
+
+extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n_graphs,
+                                       const int32_t *q_graph, const int32_t *q_src,
+                                       const int32_t *q_ts, int32_t n_q, int32_t *const *arr,
+                                       const eat_run_options *ro, eat_batch **out) {
+  return batch_create(graphs, n_graphs, q_graph, q_src, q_ts, nullptr, n_q, arr, ro, out);
+}
+
+extern "C" eat_status eat_batch_create_goal(const eat_graph *const *graphs, int32_t n_graphs,
+                                            const int32_t *q_graph, const int32_t *q_src,
+                                            const int32_t *q_ts, const int32_t *q_dst, int32_t n_q,
+                                            int32_t *const *arr, const eat_run_options *ro, eat_batch **out) {
+  if (n_q > 0 && !q_dst) {
+    if (out) *out = nullptr;
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "q_dst is NULL");
+  }
+  return batch_create(graphs, n_graphs, q_graph, q_src, q_ts, q_dst, n_q, arr, ro, out);
 }
 
 extern "C" eat_status eat_batch_options(const eat_batch *b, eat_run_options *out) {

@@ -87,6 +87,12 @@ struct RunArgs {
   // -- done[QueryDev::index] = epoch.  Host-visible (pinned) memory.
   int32_t *done;
   int32_t epoch;
+  // Goal-directed queries (nonzero: the goal-directed kernel variant runs):
+  // the destination of query i is targets[QueryDev::index] in a batch, or
+  // single_target, -1 for every stop (answered in full by that variant too).
+  int32_t goal;
+  int32_t single_target;
+  const int32_t *targets;    // device array (batch only)
 };
 
 constexpr int kBlock = 1024;      // threads per query (work-group), default
@@ -96,6 +102,7 @@ constexpr int kMaxBuckets = 32;
 constexpr int kCounterWords = 4 + kMaxBuckets;
 
 // Host-side launchers (kernels.hip).
+// The kernel variant follows a.goal.
 hipError_t launch_relax(const RunArgs &a, int tpv, int ub, int kind, int block, int grid, size_t lds_bytes,
                         hipStream_t stream);
 hipError_t launch_zero(int32_t *p, int n, hipStream_t stream);
@@ -107,6 +114,6 @@ hipError_t launch_build_grid(const GraphDev &g, hipStream_t stream);
 hipError_t launch_slab_hash(const QueryDev *qs, const GraphDev *graphs, int32_t nq, unsigned long long *out,
                             hipStream_t stream);
 // Work-groups of the relaxation kernel that fit on one CU with lds_bytes of LDS.
-int relax_blocks_per_cu(int tpv, int ub, int kind, int block, size_t lds_bytes);
+int relax_blocks_per_cu(int tpv, int ub, int kind, int block, size_t lds_bytes, bool goal = false);
 
 }  // namespace eat

@@ -104,11 +104,11 @@ __global__ void k_build_grid(GraphDev Gd) {
   }
 }
 
-RelaxFn pick(int tpv, int ub, int kind, int block) {
+RelaxFn pick(int tpv, int ub, int kind, int block, bool goal) {
   switch (kind) {
-    case kKindCompact: return relax_fn_compact(tpv, ub, block);
-    case kKindFlat: return relax_fn_flat(tpv, ub, block);
-    case kKindGrid: return relax_fn_grid(tpv, ub, block);
+    case kKindCompact: return relax_fn_compact(tpv, ub, block, goal);
+    case kKindFlat: return relax_fn_flat(tpv, ub, block, goal);
+    case kKindGrid: return relax_fn_grid(tpv, ub, block, goal);
     default: return nullptr;
   }
 }
@@ -131,7 +131,7 @@ hipError_t allow_lds(RelaxFn f, size_t bytes) {
 
 hipError_t launch_relax(const RunArgs &a, int tpv, int ub, int kind, int block, int grid, size_t lds_bytes,
                         hipStream_t stream) {
-  RelaxFn f = pick(tpv, ub, kind, block);
+  RelaxFn f = pick(tpv, ub, kind, block, a.goal != 0);
   if (!f) return hipErrorInvalidValue;
   hipError_t e = allow_lds(f, lds_bytes);
   if (e != hipSuccess) return e;
@@ -139,8 +139,8 @@ hipError_t launch_relax(const RunArgs &a, int tpv, int ub, int kind, int block, 
   return hipGetLastError();
 }
 
-int relax_blocks_per_cu(int tpv, int ub, int kind, int block, size_t lds_bytes) {
-  RelaxFn f = pick(tpv, ub, kind, block);
+int relax_blocks_per_cu(int tpv, int ub, int kind, int block, size_t lds_bytes, bool goal) {
+  RelaxFn f = pick(tpv, ub, kind, block, goal);
   if (!f) return 0;
   if (allow_lds(f, lds_bytes) != hipSuccess) return 0;
   int nb = 0;

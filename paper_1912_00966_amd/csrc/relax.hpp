@@ -491,6 +491,7 @@ __device__ __forceinline__ bool mark_improved(P bits, int32_t it) {
 // stop, in LDS or in HBM (P, see bits_or).
 template <class P>
 struct SlabStore {
+  static constexpr bool kGoal = false;
   gp<int32_t> arr;
   P bits;
   int32_t n;
@@ -532,6 +533,7 @@ constexpr uint32_t IDLE = 0x80000000u;
 constexpr uint32_t NO_KEY = 0xffffffffu;  // low half of an empty slot (idle, no stop)
 constexpr unsigned long long EMPTY_SLOT = ((unsigned long long)(uint32_t)INF << 32) | NO_KEY;
 struct TableStore {
+  static constexpr bool kGoal = false;
   unsigned long long *kv;
   int32_t *count;  // slots in use
   int32_t *over;   // set when a stop found no slot
@@ -637,6 +639,38 @@ struct TableStore {
   __device__ __forceinline__ bool full() const { return lds_ld(count) > limit; }
 };
 
+// Goal-directed queries (one destination, Section I): a store that only keeps
+// what can still lead to an earlier arrival at the target.  bound (LDS) is the
+// earliest arrival at the target found so far.  Any journey through a stop
+// reached at x arrives at the target later than x (lam >= 1), so a candidate
+// >= bound is not written, a listed stop whose arrival is >= bound is dropped
+// when taken, and the query ends once every listed stop is at or past bound:
+// entry target of the result is then exact (every prefix of an optimal
+// journey to the target arrives before bound, so none of it is pruned).  The
+// target itself is never expanded: its types give arrivals after bound.
+// Destination of query Q of a launch (-1: every stop).
+__device__ __forceinline__ int32_t batch_target(const RunArgs &a, const QueryDev &Q) {
+  return a.queries ? a.targets[Q.index] : a.single_target;
+}
+
+template <class Inner>
+struct GoalStore : Inner {
+  static constexpr bool kGoal = true;
+  int32_t *bound;
+  int32_t target;
+  __device__ __forceinline__ int32_t goal_bound() const { return lds_ld(bound); }
+  __device__ __forceinline__ bool improve(int32_t v, int32_t pos, int32_t av, int32_t cand, int32_t &item,
+                                          Ctr &c) const {
+    if (cand >= lds_ld(bound)) return false;
+    if (v == target) {
+      atomicMin(bound, cand);
+      Inner::improve(v, pos, av, cand, item, c);
+      return false;
+    }
+    return Inner::improve(v, pos, av, cand, item, c);
+  }
+};
+
 // Relax (Algorithm 3) U connection types per lane, with their memory reads
 // overlapped: all type records (and, for the grid, the grid entries, whose
 // addresses need no record), then the (speculative) cluster headers, then the
@@ -720,6 +754,7 @@ __device__ __forceinline__ void relax(const GraphG &G, const Store &S, int64_t j
 
 struct Shared {
   int32_t q, cnt, count, over, reached;
+  int32_t bound;                // goal-directed queries: best arrival at the target so far
   int32_t nmin[3];              // smallest arrival pushed in round r: nmin[r % 3]
   int32_t cur[3];               // wave-claim cursor of round r: cur[r % 3]
   int32_t wcur, resume;         // sweep: next group to claim, first group of the next chunk
@@ -752,6 +787,13 @@ __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, con
     beg = cur.beg[e];
     cnt = cur.cnt[e];
     x = S.value(item);
+    if constexpr (Store::kGoal) {
+      if (x >= S.goal_bound()) {  // cannot lead to an earlier arrival at the target
+        defer = false;
+        if (clear) S.deactivate(item);
+        return false;
+      }
+    }
     defer = thr != INF && x >= thr;
     if (defer) {
       // list mode: still active; after a sweep, active again unless an
@@ -1005,6 +1047,12 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
     }
     ++rounds;
     if (nnv == 0) break;
+    if constexpr (Store::kGoal) {
+      // every stop of the next round is at or past the target's arrival.  No
+      // thread changes bound before every thread has passed the next round's
+      // first barrier, so all threads read the same value here.
+      if (base >= S.goal_bound()) break;
+    }
     qs.maxf = max(qs.maxf, nnv);
     const bool next_sweep = topo || nnv > a.fcap;  // an overflowed list: its flags still name every item
     FList tmp = cur;
@@ -1020,7 +1068,7 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
 // A query with its arrivals in the result slab (no table, or the table
 // overflowed; the slab still holds infinity): activity bits `bits` (LDS or
 // HBM, cleared here), frontier lists at l in LDS.
-template <int TPV, int KIND, int U, int B, class P>
+template <int TPV, int KIND, int U, int B, bool GOAL, class P>
 __device__ __forceinline__ void slab_query(const RunArgs &a, const GraphG &G, gp<int32_t> arr, const QueryDev &Q,
                                            P bits, int32_t *l, const XList X, bool topo, int32_t max_rounds,
                                            Shared &sh, QState &qs, Ctr &c) {
@@ -1041,13 +1089,22 @@ __device__ __forceinline__ void slab_query(const RunArgs &a, const GraphG &G, gp
   __syncthreads();
   if (tid == 0) {
     st_arr(arr + Q.s, Q.ts);
+    if constexpr (GOAL) sh.bound = batch_target(a, Q) == Q.s ? Q.ts : INF;  // a fresh start after a table overflow too
     bits_st(bits, Q.s >> 5, 1u << (Q.s & 31));
     l0.item[0] = Q.s;
     l0.cnt[0] = -1;
   }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  run_rounds<TPV, KIND, U, B>(a, G, S, V, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c);
+  if constexpr (GOAL) {
+    GoalStore<SlabStore<P>> GS;
+    static_cast<SlabStore<P> &>(GS) = S;
+    GS.bound = &sh.bound;
+    GS.target = batch_target(a, Q);
+    run_rounds<TPV, KIND, U, B>(a, G, GS, V, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c);
+  } else {
+    run_rounds<TPV, KIND, U, B>(a, G, S, V, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c);
+  }
   // reached stops
   int32_t mine = 0;
   for (int32_t i = tid; i < V; i += B) mine += ld_arr(arr + i) != INF;
@@ -1056,7 +1113,7 @@ __device__ __forceinline__ void slab_query(const RunArgs &a, const GraphG &G, gp
 
 // 768-thread work-groups share a CU two at a time (24 waves, 6 per SIMD),
 // which needs at most 80 VGPRs: asked of the compiler here.
-template <int TPV, int KIND, int U, int B>
+template <int TPV, int KIND, int U, int B, bool GOAL>
 __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(B == kBlockMid ? 6 : 1))) void k_relax(RunArgs a) {
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ Shared sh;
@@ -1153,11 +1210,22 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(B == kBlockMi
         const uint32_t p = T.home(Q.s);  // empty table: the home slot is free
         T.kv[p] = ((unsigned long long)(uint32_t)Q.ts << 32) | (uint32_t)Q.s;  // active
         sh.count = 1;
+        if constexpr (GOAL) sh.bound = batch_target(a, Q) == Q.s ? Q.ts : INF;
         l0.item[0] = (int32_t)p;
         l0.cnt[0] = -1;
       }
       __syncthreads();
-      if (run_rounds<TPV, KIND, U, B>(a, G, T, H, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c)) {
+      bool ok;
+      if constexpr (GOAL) {
+        GoalStore<TableStore> GS;
+        static_cast<TableStore &>(GS) = T;
+        GS.bound = &sh.bound;
+        GS.target = batch_target(a, Q);
+        ok = run_rounds<TPV, KIND, U, B>(a, G, GS, H, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c);
+      } else {
+        ok = run_rounds<TPV, KIND, U, B>(a, G, T, H, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c);
+      }
+      if (ok) {
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the infinity fill has landed
         __syncthreads();
         for (int32_t p = tid; p < H; p += B) {
@@ -1178,13 +1246,13 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(B == kBlockMi
       if constexpr (B == kBlock) {
         if (a.bits_global) {  // this work-group's region of HBM
           gp<uint32_t> bits = (gp<uint32_t>)(a.bits_global + (size_t)blockIdx.x * (size_t)a.bits_stride);
-          slab_query<TPV, KIND, U, B>(a, G, arr, Q, bits, reinterpret_cast<int32_t *>(store), X, topo, max_rounds,
+          slab_query<TPV, KIND, U, B, GOAL>(a, G, arr, Q, bits, reinterpret_cast<int32_t *>(store), X, topo, max_rounds,
                                       sh, qs, c);
           in_hbm = true;
         }
       }
       if (!in_hbm)
-        slab_query<TPV, KIND, U, B>(a, G, arr, Q, store, reinterpret_cast<int32_t *>(store + ((V + 31) >> 5)), X,
+        slab_query<TPV, KIND, U, B, GOAL>(a, G, arr, Q, store, reinterpret_cast<int32_t *>(store + ((V + 31) >> 5)), X,
                                     topo, max_rounds, sh, qs, c);
     }
 
@@ -1235,28 +1303,36 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(B == kBlockMi
 
 
 // TPV = 0: wave-claim expansion with ub connection types in flight per lane
-// (1..3); TPV > 0: virtual warps of TPV lanes.
+// (1..3); TPV > 0: virtual warps of TPV lanes.  Goal-directed queries (goal)
+// run the wave-claim kernels with one type per lane.
 template <int KIND>
-RelaxFn relax_fn(int tpv, int ub, int block) {
+RelaxFn relax_fn(int tpv, int ub, int block, bool goal) {
+  if (goal) {
+    if (tpv != 0 || ub != 1) return nullptr;
+    return block == kBlockSmall ? k_relax<0, KIND, 1, kBlockSmall, true>
+         : block == kBlockMid   ? k_relax<0, KIND, 1, kBlockMid, true>
+         : block == kBlock      ? k_relax<0, KIND, 1, kBlock, true> : nullptr;
+  }
   if (block == kBlockSmall) {  // wave claims only
     if (tpv != 0) return nullptr;
-    return ub == 1 ? k_relax<0, KIND, 1, kBlockSmall>
-                   : ub == 3 ? k_relax<0, KIND, 3, kBlockSmall> : k_relax<0, KIND, 2, kBlockSmall>;
+    return ub == 1 ? k_relax<0, KIND, 1, kBlockSmall, false>
+                   : ub == 3 ? k_relax<0, KIND, 3, kBlockSmall, false> : k_relax<0, KIND, 2, kBlockSmall, false>;
   }
   if (block == kBlockMid) {  // wave claims, one type per lane: U > 1 would spill at 80 VGPRs
     if (tpv != 0 || ub != 1) return nullptr;
-    return k_relax<0, KIND, 1, kBlockMid>;
+    return k_relax<0, KIND, 1, kBlockMid, false>;
   }
   if (block != kBlock) return nullptr;
   switch (tpv) {
-    case 0: return ub == 1 ? k_relax<0, KIND, 1, kBlock> : ub == 3 ? k_relax<0, KIND, 3, kBlock> : k_relax<0, KIND, 2, kBlock>;
-    case 1: return k_relax<1, KIND, 1, kBlock>;
-    case 2: return k_relax<2, KIND, 1, kBlock>;
-    case 4: return k_relax<4, KIND, 1, kBlock>;
-    case 8: return k_relax<8, KIND, 1, kBlock>;
-    case 16: return k_relax<16, KIND, 1, kBlock>;
-    case 32: return k_relax<32, KIND, 1, kBlock>;
-    case 64: return k_relax<64, KIND, 1, kBlock>;
+    case 0: return ub == 1 ? k_relax<0, KIND, 1, kBlock, false>
+                           : ub == 3 ? k_relax<0, KIND, 3, kBlock, false> : k_relax<0, KIND, 2, kBlock, false>;
+    case 1: return k_relax<1, KIND, 1, kBlock, false>;
+    case 2: return k_relax<2, KIND, 1, kBlock, false>;
+    case 4: return k_relax<4, KIND, 1, kBlock, false>;
+    case 8: return k_relax<8, KIND, 1, kBlock, false>;
+    case 16: return k_relax<16, KIND, 1, kBlock, false>;
+    case 32: return k_relax<32, KIND, 1, kBlock, false>;
+    case 64: return k_relax<64, KIND, 1, kBlock, false>;
     default: return nullptr;
   }
 }
@@ -1264,8 +1340,8 @@ RelaxFn relax_fn(int tpv, int ub, int block) {
 }  // namespace
 
 // Kernel variant of one timetable form (defined in relax_<form>.hip).
-RelaxFn relax_fn_compact(int tpv, int ub, int block);
-RelaxFn relax_fn_flat(int tpv, int ub, int block);
-RelaxFn relax_fn_grid(int tpv, int ub, int block);
+RelaxFn relax_fn_compact(int tpv, int ub, int block, bool goal);
+RelaxFn relax_fn_flat(int tpv, int ub, int block, bool goal);
+RelaxFn relax_fn_grid(int tpv, int ub, int block, bool goal);
 
 }  // namespace eat

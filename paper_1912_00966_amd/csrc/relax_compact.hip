@@ -3,6 +3,6 @@
 
 namespace eat {
 
-RelaxFn relax_fn_compact(int tpv, int ub, int block) { return relax_fn<kKindCompact>(tpv, ub, block); }
+RelaxFn relax_fn_compact(int tpv, int ub, int block, bool goal) { return relax_fn<kKindCompact>(tpv, ub, block, goal); }
 
 }  // namespace eat

@@ -3,6 +3,6 @@
 
 namespace eat {
 
-RelaxFn relax_fn_flat(int tpv, int ub, int block) { return relax_fn<kKindFlat>(tpv, ub, block); }
+RelaxFn relax_fn_flat(int tpv, int ub, int block, bool goal) { return relax_fn<kKindFlat>(tpv, ub, block, goal); }
 
 }  // namespace eat

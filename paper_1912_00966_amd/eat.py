@@ -43,14 +43,28 @@ EAT_ORDER_LONGEST_FIRST = 2
 EXPORTS = (
     "eat_layout_build", "eat_layout_build_trips", "eat_layout_free", "eat_layout_info", "eat_layout_view_get",
     "eat_graph_build", "eat_graph_build_trips", "eat_graph_upload", "eat_graph_free", "eat_graph_info", "eat_graph_failures",
-    "eat_query", "eat_batch_create", "eat_batch_run", "eat_batch_wait", "eat_batch_free",
+    "eat_query", "eat_query_goal", "eat_batch_create", "eat_batch_create_goal", "eat_batch_run", "eat_batch_wait",
+    "eat_batch_free", "eat_parents", "eat_profile",
     "eat_batch_options", "eat_batch_tune", "eat_query_batch_static",
     "eat_query_batch", "eat_next_departure", "eat_status_string", "eat_last_error",
     "eat_version", "eat_session_create", "eat_session_admit", "eat_session_step",
     "eat_session_poll", "eat_session_sync", "eat_session_result", "eat_session_copy",
     "eat_session_query_stats",
     "eat_session_release", "eat_session_free",
+    "eat_ap_cover", "eat_esdg_levels", "eat_variant_graph_build", "eat_variant_graph_info", "eat_variant_query",
+    "eat_variant_graph_free",
 )
+
+# the paper's algorithm ladder (eat_variant)
+EAT_VARIANT_CONNECTION = 0
+EAT_VARIANT_CONNECTION_TYPE = 1
+EAT_VARIANT_CONNECTION_TYPE_AP = 2
+EAT_VARIANT_CLUSTER_AP = 3
+EAT_VARIANT_EDGE = 4
+EAT_VARIANT_WARPS = 5
+EAT_VARIANT_ESDG = 6
+VARIANT_NAMES = {0: "connection", 1: "connection-type", 2: "connection-type-AP", 3: "cluster-AP", 4: "edge",
+                 5: "warps", 6: "ESDG"}
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -123,6 +137,34 @@ class SessionOptions(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 4)]
 
 
+class VariantBuildOptions(ctypes.Structure):
+    _fields_ = [("cluster_seconds", ctypes.c_int32), ("esdg", ctypes.c_int32), ("n_threads", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+class VariantInfo(ctypes.Structure):
+    _fields_ = [("n_vertices", ctypes.c_int32), ("n_clusters", ctypes.c_int32), ("n_levels", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("n_conn", ctypes.c_int64), ("n_types", ctypes.c_int64),
+                ("n_edges", ctypes.c_int64), ("n_type_aps", ctypes.c_int64), ("n_cluster_aps", ctypes.c_int64),
+                ("n_esdg_edges", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class VariantOptions(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("warp_size", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("count", ctypes.c_int32), ("max_iterations", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class VariantStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("host_checks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("examined", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class EatError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{message} (status {status})")
@@ -161,6 +203,22 @@ def lib():
     L.eat_batch_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, _i32p, _i32p, _i32p,
                                    ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(RunOptions),
                                    ctypes.POINTER(_vp)]
+    L.eat_query_goal.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp,
+                                 ctypes.POINTER(RunOptions), ctypes.POINTER(QueryStats)]
+    L.eat_batch_create_goal.argtypes = [ctypes.POINTER(_vp), ctypes.c_int32, _i32p, _i32p, _i32p, _i32p,
+                                        ctypes.c_int32, ctypes.POINTER(_vp), ctypes.POINTER(RunOptions),
+                                        ctypes.POINTER(_vp)]
+    L.eat_parents.argtypes = [_vp, ctypes.c_int32, _vp, _vp, _vp]
+    L.eat_profile.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p,
+                              _vp, _vp, ctypes.POINTER(RunOptions)]
+    L.eat_ap_cover.argtypes = [_i32p, ctypes.c_int64, _i32p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    L.eat_esdg_levels.argtypes = [_i32p, _i32p, _i32p, _i32p, ctypes.c_int64, ctypes.c_int32, _i32p, _i32p,
+                                  ctypes.POINTER(ctypes.c_int64)]
+    L.eat_variant_graph_build.argtypes = conn[:6] + [ctypes.POINTER(VariantBuildOptions), ctypes.POINTER(_vp)]
+    L.eat_variant_graph_info.argtypes = [_vp, ctypes.POINTER(VariantInfo)]
+    L.eat_variant_query.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp, ctypes.POINTER(VariantOptions),
+                                    ctypes.POINTER(VariantStats)]
+    L.eat_variant_graph_free.argtypes = [_vp]
     L.eat_batch_run.argtypes = [_vp, _vp]
     L.eat_batch_wait.argtypes = [_vp, ctypes.POINTER(QueryStats)]
     L.eat_batch_free.argtypes = [_vp]
@@ -195,7 +253,7 @@ def lib():
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("eat_layout_free", "eat_graph_free", "eat_batch_free", "eat_status_string",
-                        "eat_last_error", "eat_version", "eat_session_free"):
+                        "eat_last_error", "eat_version", "eat_session_free", "eat_variant_graph_free"):
             f.restype = ctypes.c_int
     _lib = L
     return L
@@ -355,6 +413,44 @@ class Graph:
         st = eat_query(self, s, ts, out, stream=stream, options=options, stats=stats)
         return (out, st) if stats else out
 
+    def query_goal(self, s: int, ts: int, d: int, out=None, stream=None, options=None, stats: bool = False):
+        """Goal-directed query (eat_query_goal): out[d] is the earliest arrival at
+        d; other entries are upper bounds.  Returns out (or (out, stats))."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n_vertices, dtype=torch.int32, device="cuda")
+        st = eat_query_goal(self, s, ts, d, out, stream=stream, options=options, stats=stats)
+        return (out, st) if stats else out
+
+    def parents(self, s: int, arr, out=None, stream=None):
+        """Parent connection of every stop for the answer arr of a query from s
+        (eat_parents): a (V, 3) CUDA int32 tensor of (u, t, lam), -1 where none."""
+        import torch
+        if out is None:
+            out = torch.empty((self.n_vertices, 3), dtype=torch.int32, device="cuda")
+        _check(lib().eat_parents(self.handle, int(s), _dev_ptr(arr, self.n_vertices, "arr"),
+                                 _dev_ptr(out, 3 * self.n_vertices, "out"), _stream_handle(stream)))
+        return out
+
+    def profile(self, s: int, t_lo: int, t_hi: int, stream=None, options=None):
+        """Profile of s over departures in [t_lo, t_hi] (eat_profile): (dep, arr)
+        with dep a numpy int32 array of k departure times and arr a (k, V) CUDA
+        int32 tensor, row i holding per stop the arrival of the Pareto-optimal
+        journey leaving at dep[i] (EAT_INF where none)."""
+        import torch
+        n = np.zeros(1, dtype=np.int32)
+        ro = _run_opts(options)
+        rop = ctypes.byref(ro) if ro is not None else None
+        _check(lib().eat_profile(self.handle, int(s), int(t_lo), int(t_hi), 0, None, _ptr32(n), None,
+                                 _stream_handle(stream), rop))
+        k = int(n[0])
+        dep = np.zeros(max(k, 1), dtype=np.int32)
+        arr = torch.empty((max(k, 1), self.n_vertices), dtype=torch.int32, device="cuda")
+        if k:
+            _check(lib().eat_profile(self.handle, int(s), int(t_lo), int(t_hi), k, _ptr32(dep), _ptr32(n),
+                                     ctypes.c_void_p(arr.data_ptr()), _stream_handle(stream), rop))
+        return dep[:k], arr[:k]
+
     def failures(self) -> int:
         """Plain queries (run without stats) on this graph that hit their round
         limit since it was built (eat_graph_failures)."""
@@ -427,10 +523,37 @@ def eat_query(g: Graph, s: int, ts: int, arr, stream=None, options=None, stats: 
     return st.as_dict() if st is not None else None
 
 
-class Batch:
-    """A prepared batch (eat_batch_create); run() enqueues all its queries in one launch."""
+def eat_query_goal(g: Graph, s: int, ts: int, d: int, arr, stream=None, options=None, stats: bool = False):
+    ptr = _dev_ptr(arr, g.n_vertices, "arr")
+    ro = _run_opts(options)
+    st = QueryStats() if stats else None
+    _check(lib().eat_query_goal(g.handle, int(s), int(ts), int(d), ptr, _stream_handle(stream),
+                                ctypes.byref(ro) if ro is not None else None,
+                                ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
 
-    def __init__(self, graphs: Sequence[Graph], q_graph, q_src, q_ts, outs, options=None):
+
+def journey(par, s: int, d: int):
+    """The journey from s to d read from parents par ((V, 3) array of (u, t,
+    lam), as returned by Graph.parents): a list of connections (u, v, t, lam)
+    in travel order; [] for d == s; None if d has no parent chain to s."""
+    par = np.asarray(par.cpu() if hasattr(par, "cpu") else par).reshape(-1, 3)
+    legs, v = [], int(d)
+    while v != s:
+        u, t, lam = (int(x) for x in par[v])
+        if u < 0 or len(legs) > len(par):
+            return None
+        legs.append((u, v, t, lam))
+        v = u
+    return legs[::-1]
+
+
+class Batch:
+    """A prepared batch (eat_batch_create, or eat_batch_create_goal when q_dst
+    gives destinations, -1 = every stop); run() enqueues all its queries in
+    one launch."""
+
+    def __init__(self, graphs: Sequence[Graph], q_graph, q_src, q_ts, outs, options=None, q_dst=None):
         self.graphs = list(graphs)
         q_graph, q_src, q_ts = _i32(q_graph), _i32(q_src), _i32(q_ts)
         n = len(q_src)
@@ -445,9 +568,16 @@ class Batch:
         ah = (_vp * max(n, 1))(*ptrs)
         ro = _run_opts(options)
         h = _vp()
-        _check(lib().eat_batch_create(gh, len(self.graphs), _ptr32(q_graph), _ptr32(q_src),
-                                      _ptr32(q_ts), n, ah,
-                                      ctypes.byref(ro) if ro is not None else None, ctypes.byref(h)))
+        rop = ctypes.byref(ro) if ro is not None else None
+        if q_dst is not None:
+            q_dst = _i32(q_dst)
+            if len(q_dst) != n:
+                raise ValueError("q_dst must have one entry per query")
+            _check(lib().eat_batch_create_goal(gh, len(self.graphs), _ptr32(q_graph), _ptr32(q_src), _ptr32(q_ts),
+                                               _ptr32(q_dst), n, ah, rop, ctypes.byref(h)))
+        else:
+            _check(lib().eat_batch_create(gh, len(self.graphs), _ptr32(q_graph), _ptr32(q_src),
+                                          _ptr32(q_ts), n, ah, rop, ctypes.byref(h)))
         self._h = h
         self.n = n
         self._outs = outs  # keep the slabs alive as long as the batch
@@ -631,3 +761,74 @@ class Session:
 
 def eat_version() -> int:
     return int(lib().eat_version())
+
+
+# ---------------------------------------------------------------------------
+# The paper's algorithm ladder and its host utilities
+# ---------------------------------------------------------------------------
+def ap_cover(d) -> np.ndarray:
+    """Greedy arithmetic-progression cover (eat_ap_cover) of strictly increasing
+    values: a (k, 3) int32 array of {first, last, difference}."""
+    d = _i32(d)
+    n = ctypes.c_int64()
+    _check(lib().eat_ap_cover(_ptr32(d), len(d), None, 0, ctypes.byref(n)))
+    out = np.zeros((max(int(n.value), 1), 3), dtype=np.int32)
+    _check(lib().eat_ap_cover(_ptr32(d), len(d), _ptr32(out), int(n.value), ctypes.byref(n)))
+    return out[:int(n.value)]
+
+
+def esdg_levels(u, v, t, lam, n_vertices):
+    """ESDG level of every connection as given (eat_esdg_levels): (level array,
+    number of levels, number of dependency edges)."""
+    u, v, t, lam = (_i32(x) for x in (u, v, t, lam))
+    level = np.zeros(max(len(u), 1), dtype=np.int32)
+    nl = ctypes.c_int32()
+    ne = ctypes.c_int64()
+    _check(lib().eat_esdg_levels(_ptr32(u), _ptr32(v), _ptr32(t), _ptr32(lam), len(u), int(n_vertices),
+                                 _ptr32(level), ctypes.byref(nl), ctypes.byref(ne)))
+    return level[:len(u)], int(nl.value), int(ne.value)
+
+
+class VariantGraph:
+    """The arrays of every variant of the paper's ladder on the device
+    (eat_variant_graph_build)."""
+
+    def __init__(self, u, v, t, lam, n_vertices, cluster_seconds=0, esdg=False, n_threads=0):
+        u, v, t, lam = (_i32(x) for x in (u, v, t, lam))
+        o = VariantBuildOptions()
+        o.cluster_seconds = int(cluster_seconds)
+        o.esdg = 1 if esdg else 0
+        o.n_threads = int(n_threads)
+        h = _vp()
+        _check(lib().eat_variant_graph_build(_ptr32(u), _ptr32(v), _ptr32(t), _ptr32(lam), len(u), int(n_vertices),
+                                             ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        gi = VariantInfo()
+        _check(lib().eat_variant_graph_info(self._h, ctypes.byref(gi)))
+        self.info = gi.as_dict()
+        self.n_vertices = gi.n_vertices
+
+    def query(self, s: int, ts: int, variant: int, out=None, warp_size=0, check_every=0, count=False,
+              stream=None, max_iterations=0):
+        """(out, stats): the EAT answer by one variant, with its iteration count."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n_vertices, dtype=torch.int32, device="cuda")
+        o = VariantOptions()
+        o.variant, o.warp_size, o.check_every = int(variant), int(warp_size), int(check_every)
+        o.count, o.max_iterations = 1 if count else 0, int(max_iterations)
+        st = VariantStats()
+        _check(lib().eat_variant_query(self._h, int(s), int(ts), _dev_ptr(out, self.n_vertices, "out"),
+                                       _stream_handle(stream), ctypes.byref(o), ctypes.byref(st)))
+        return out, st.as_dict()
+
+    def free(self):
+        if getattr(self, "_h", None):
+            lib().eat_variant_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
