@@ -266,11 +266,14 @@ typedef struct {
                                  round, the schedule of Section III-B).  The answer is the
                                  same either way; the window trades a few more rounds for
                                  fewer re-expansions of stops whose arrival improves */
-  int32_t threads_per_query;  /* work-group size of one query: 1024 (default), 768 or 512
+  int32_t threads_per_query;  /* work-group size of one query: 1024 (default); 768 or 512
                                  -- two queries share a CU, each with half of its LDS for
-                                 the arrival table (wave claims only: threads_per_vertex =
-                                 0).  Two per CU raise throughput when many queries are in
-                                 flight; 1024 finishes a single long query sooner.  0 = 1024 */
+                                 the arrival table; 384 -- four per CU, a quarter each;
+                                 256 -- six per CU, a sixth each (wave claims only:
+                                 threads_per_vertex = 0; 256, 384 and 768 with one type per
+                                 lane).  More queries per CU raise throughput when many are
+                                 in flight; 1024 finishes a single long query sooner.
+                                 0 = 1024 */
   int32_t query_order;        /* eat_query_order: the order in which a batch's work-groups
                                  take its queries */
   int32_t reserved[3];        /* must be zero */

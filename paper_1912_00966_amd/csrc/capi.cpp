@@ -486,23 +486,25 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   pl->headers = o.headers;
   if (o.time_window < -1) return set_err(EAT_ERR_INVALID_ARGUMENT, "time_window must be >= -1");
   if (o.threads_per_query != 0 && o.threads_per_query != kBlock && o.threads_per_query != kBlockSmall &&
-      o.threads_per_query != kBlockMid)
-    return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query must be 0, 512, 768 or 1024");
+      o.threads_per_query != kBlockMid && o.threads_per_query != kBlockQuarter && o.threads_per_query != kBlockSixth)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query must be 0, 256, 384, 512, 768 or 1024");
   pl->block = o.threads_per_query ? o.threads_per_query : kBlock;
   if (pl->block != kBlock && o.threads_per_vertex != 0)
     return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query 512 or 768 needs threads_per_vertex 0");
-  if (pl->block == kBlockMid && pl->ub != 1)
-    return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query 768 runs one connection type per lane");
+  if ((pl->block == kBlockMid || pl->block == kBlockQuarter || pl->block == kBlockSixth) && pl->ub != 1)
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query 256, 384 and 768 run one connection type per lane");
   pl->window = o.time_window == 0 ? 7200 : (o.time_window < 0 ? 0 : o.time_window);
   if (o.query_order < EAT_ORDER_AUTO || o.query_order > EAT_ORDER_LONGEST_FIRST)
     return set_err(EAT_ERR_INVALID_ARGUMENT, "unknown query order");
   pl->order = o.query_order;
   pl->max_rounds = o.max_rounds;
   pl->bm_words = (max_v + 31) / 32;
-  const bool small = pl->block != kBlock;  // two work-groups per CU
+  const int qpc = queries_per_cu(pl->block);  // work-groups sharing a CU
+  const bool small = qpc > 1;
   // default list capacity: the largest that still leaves room for a
-  // 16,384-slot table (1024 threads) or an 8,192-slot one (512 threads)
-  int fcap = o.frontier_cap ? o.frontier_cap : (small ? 256 : 704);
+  // 16,384-slot table (1024 threads) or an 8,192-slot one (512, 768 threads);
+  // with four or six queries per CU, a 4,096- or 2,048-slot table
+  int fcap = o.frontier_cap ? o.frontier_cap : (qpc >= 4 ? 128 : small ? 256 : 704);
   // a multiple of 64, at least 64: a sweep stages the active items of 64
   // consecutive items at once, which must fit an empty list
   fcap = (fcap + 63) / 64 * 64;
@@ -519,14 +521,14 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   // a frontier never holds more items than there are stops (or table slots)
   const int items = std::max(64, (std::max(max_v, H) + 63) / 64 * 64);
   fcap = std::min(fcap, items);
-  // two 512- or 768-thread work-groups share a CU: each gets half its LDS
-  const size_t budget = small ? lim.lds / 2 - 512 : lim.lds;
+  // work-groups that share a CU split its LDS
+  const size_t budget = small ? lim.lds / (size_t)qpc - 512 : lim.lds;
   // slab mode (no table, or a table that overflowed): one activity bit per
   // stop, in LDS while it fits, else in a region of HBM per work-group
   pl->bits_global = (size_t)pl->bm_words * 4 + lists_lds(fcap) > budget;
   if (pl->bits_global && small)
-    return set_err(EAT_ERR_UNSUPPORTED, "a graph whose activity bitmap does not fit half the LDS runs "
-                                        "1024-thread queries (threads_per_query 0 or 1024)");
+    return set_err(EAT_ERR_UNSUPPORTED, "a graph whose activity bitmap does not fit the LDS share of a "
+                                        "smaller work-group runs 1024-thread queries (threads_per_query 0 or 1024)");
   pl->bits_stride = (pl->bm_words + 63) / 64 * 64;
   const size_t slab_lds = (pl->bits_global ? 0 : (size_t)pl->bm_words * 4) + lists_lds(fcap);
   auto need = [&](int h) { return std::max(table_lds(h, fcap), slab_lds); };

@@ -95,9 +95,16 @@ struct RunArgs {
   const int32_t *targets;    // device array (batch only)
 };
 
-constexpr int kBlock = 1024;      // threads per query (work-group), default
-constexpr int kBlockSmall = 512;  // the alternatives: two queries per CU ...
-constexpr int kBlockMid = 768;    // ... with 8 or 12 waves each
+constexpr int kBlock = 1024;        // threads per query (work-group), default
+constexpr int kBlockSmall = 512;    // the alternatives: two queries per CU ...
+constexpr int kBlockMid = 768;      // ... with 8 or 12 waves each,
+constexpr int kBlockQuarter = 384;  // four queries per CU with 6 waves each,
+constexpr int kBlockSixth = 256;    // six queries per CU with 4 waves each
+// Queries (work-groups) of a block size that share one CU, each with that
+// share of the LDS.
+constexpr int queries_per_cu(int block) {
+  return block == kBlock ? 1 : block == kBlockQuarter ? 4 : block == kBlockSixth ? 6 : 2;
+}
 constexpr int kMaxBuckets = 32;
 constexpr int kCounterWords = 4 + kMaxBuckets;
 

@@ -1111,10 +1111,12 @@ __device__ __forceinline__ void slab_query(const RunArgs &a, const GraphG &G, gp
   if (mine) atomicAdd(&sh.reached, mine);
 }
 
-// 768-thread work-groups share a CU two at a time (24 waves, 6 per SIMD),
-// which needs at most 80 VGPRs: asked of the compiler here.
+// 768-thread work-groups share a CU two at a time, 384-thread ones four and
+// 256-thread ones six at a time: 24 waves, 6 per SIMD, which needs at most
+// 80 VGPRs: asked of the compiler here.
 template <int TPV, int KIND, int U, int B, bool GOAL>
-__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(B == kBlockMid ? 6 : 1))) void k_relax(RunArgs a) {
+__global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(
+    B == kBlockMid || B == kBlockQuarter || B == kBlockSixth ? 6 : 1))) void k_relax(RunArgs a) {
   extern __shared__ __align__(16) uint32_t lds[];
   __shared__ Shared sh;
 
@@ -1309,9 +1311,15 @@ template <int KIND>
 RelaxFn relax_fn(int tpv, int ub, int block, bool goal) {
   if (goal) {
     if (tpv != 0 || ub != 1) return nullptr;
-    return block == kBlockSmall ? k_relax<0, KIND, 1, kBlockSmall, true>
-         : block == kBlockMid   ? k_relax<0, KIND, 1, kBlockMid, true>
-         : block == kBlock      ? k_relax<0, KIND, 1, kBlock, true> : nullptr;
+    return block == kBlockSmall   ? k_relax<0, KIND, 1, kBlockSmall, true>
+         : block == kBlockMid     ? k_relax<0, KIND, 1, kBlockMid, true>
+         : block == kBlockQuarter ? k_relax<0, KIND, 1, kBlockQuarter, true>
+         : block == kBlockSixth   ? k_relax<0, KIND, 1, kBlockSixth, true>
+         : block == kBlock        ? k_relax<0, KIND, 1, kBlock, true> : nullptr;
+  }
+  if (block == kBlockQuarter || block == kBlockSixth) {  // wave claims, one type per lane (80 VGPRs)
+    if (tpv != 0 || ub != 1) return nullptr;
+    return block == kBlockQuarter ? k_relax<0, KIND, 1, kBlockQuarter, false> : k_relax<0, KIND, 1, kBlockSixth, false>;
   }
   if (block == kBlockSmall) {  // wave claims only
     if (tpv != 0) return nullptr;

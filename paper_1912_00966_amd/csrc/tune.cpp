@@ -100,14 +100,15 @@ eat_run_options cand(int threads, int ub, int window, int tpv = 0, int mode = EA
   return o;
 }
 
-// The candidates: work-group size (one query per 1024-thread work-group, or
-// two per CU at 768 / 512 threads), connection types in flight per lane (a
+// The candidates: work-group size (one query per 1024-thread work-group, two
+// per CU at 768 / 512 threads, four at 384, six at 256), connection types in flight per lane (a
 // wave evaluates 64 x that many (type, cluster) lookups at once), virtual
 // warps of 16 / 32 lanes per active stop, the arrival window of a round, the
 // topology-driven schedule, and the compact header form.
 std::vector<eat_run_options> candidates() {
   return {cand(1024, 1, 7200), cand(1024, 1, 3600), cand(1024, 1, -1), cand(1024, 2, 7200),
           cand(768, 1, 7200),  cand(768, 1, 3600),  cand(512, 1, 7200), cand(512, 2, 7200),
+          cand(384, 1, 7200),  cand(384, 1, 3600),  cand(256, 1, 7200),
           cand(1024, 1, 7200, 16), cand(1024, 1, 7200, 32),
           cand(1024, 1, 7200, 0, EAT_MODE_TOPOLOGY), cand(1024, 1, 7200, 0, EAT_MODE_AUTO, EAT_HEADERS_COMPACT)};
 }

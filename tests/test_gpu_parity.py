@@ -239,22 +239,23 @@ def test_time_windows_are_exact(window, tpv):
             assert np.array_equal(got, exp[i]), (i, opts)
 
 
-@pytest.mark.parametrize("threads", [512, 768])
+@pytest.mark.parametrize("threads", [512, 768, 384, 256])
 @pytest.mark.parametrize("opts", [{}, {"table_cap": 64}, {"time_window": -1}, {"types_per_lane": 2},
                                   {"headers": eat.EAT_HEADERS_COMPACT}, {"mode": eat.EAT_MODE_TOPOLOGY},
                                   {"frontier_cap": 64}])
 def test_two_queries_per_cu_are_exact(threads, opts):
-    """Two queries per CU (512- or 768-thread work-groups, half the LDS each)
-    give the same answers, also when the smaller table overflows."""
+    """Several queries per CU (512- or 768-thread work-groups with half the LDS
+    each, 384 with a quarter, 256 with a sixth) give the same answers, also
+    when the smaller table overflows."""
     tt, q = _workload("city-1k")
     exp = _expected("city-1k")
     g = _graph("city-1k", "hybrid")
     _say(f"{threads} threads {opts}")
-    if threads == 768 and opts.get("types_per_lane", 1) > 1:
-        # 768-thread queries run at 80 VGPRs: only one type per lane fits
+    if threads != 512 and opts.get("types_per_lane", 1) > 1:
+        # 256-, 384- and 768-thread queries run at 80 VGPRs: only one type per lane fits
         out = torch.empty(g.n_vertices, dtype=torch.int32, device="cuda")
         with pytest.raises(eat.EatError) as ei:
-            eat.eat_query(g, int(q.s[0]), int(q.ts[0]), out, options=dict(opts, threads_per_query=768))
+            eat.eat_query(g, int(q.s[0]), int(q.ts[0]), out, options=dict(opts, threads_per_query=threads))
         assert ei.value.status == eat.EAT_ERR_INVALID_ARGUMENT
         return
     for i, (s, ts) in enumerate(zip(q.s, q.ts)):
@@ -267,7 +268,7 @@ def test_512_threads_need_wave_claims():
     g = _graph("city-1k", "hybrid")
     out = torch.empty(g.n_vertices, dtype=torch.int32, device="cuda")
     for bad in ({"threads_per_query": 512, "threads_per_vertex": 16}, {"threads_per_query": 768, "threads_per_vertex": 4},
-                {"threads_per_query": 256}):
+                {"threads_per_query": 384, "threads_per_vertex": 8}, {"threads_per_query": 640}):
         with pytest.raises(eat.EatError) as ei:
             eat.eat_query(g, 0, 0, out, options=bad)
         assert ei.value.status == eat.EAT_ERR_INVALID_ARGUMENT
@@ -319,6 +320,8 @@ def test_batch_city_1k_equals_oracle(layout):
 @pytest.mark.parametrize("layout,headers,threads", [("hybrid", eat.EAT_HEADERS_GRID, 1024),
                                                     ("hybrid", eat.EAT_HEADERS_GRID, 512),
                                                     ("hybrid", eat.EAT_HEADERS_GRID, 768),
+                                                    ("hybrid", eat.EAT_HEADERS_GRID, 384),
+                                                    ("hybrid", eat.EAT_HEADERS_GRID, 256),
                                                     ("hybrid", eat.EAT_HEADERS_COMPACT, 1024),
                                                     ("flat", eat.EAT_HEADERS_AUTO, 512)])
 def test_batch_city_50k_all_256_queries_bit_exact(layout, headers, threads):
@@ -349,7 +352,8 @@ def test_batch_city_50k_all_256_queries_bit_exact(layout, headers, threads):
 
 @pytest.mark.parametrize("opts", [{}, {"time_window": -1}, {"threads_per_vertex": 16}, {"table_cap": -1},
                                   {"threads_per_query": 512}, {"threads_per_query": 768},
-                                  {"threads_per_query": 768, "table_cap": -1}, {"types_per_lane": 2}])
+                                  {"threads_per_query": 768, "table_cap": -1}, {"types_per_lane": 2},
+                                  {"threads_per_query": 384}, {"threads_per_query": 256}])
 def test_small_lists_overflow_into_sweeps_city_50k(opts):
     """64-entry frontier lists (the smallest): rounds whose pushes overflow the
     list sweep the activity flags in chunks of up to 64 items instead; every
