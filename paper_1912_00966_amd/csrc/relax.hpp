@@ -758,6 +758,7 @@ struct Shared {
   int32_t nmin[3];              // smallest arrival pushed in round r: nmin[r % 3]
   int32_t cur[3];               // wave-claim cursor of round r: cur[r % 3]
   int32_t wcur, resume;         // sweep: next group to claim, first group of the next chunk
+  int32_t first, start;         // sweep: the chunk's first group, its first list entry
   unsigned long long cx[3];     // round r: low half entries pushed, high half X entries (per sweep chunk)
   unsigned long long acc[5];
 };
@@ -978,17 +979,23 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
       // Chunks of up to fcap items: each wave claims groups of 64 items from
       // a shared cursor and stages a group's active items only if all of them
       // fit (no relaxation runs while staging); the next chunk resumes at the
-      // first group that did not fit.
+      // first group that did not fit.  The chunk's first group always fits: it
+      // owns list entries [64 - its count, 64), the others are booked from 64
+      // on, so every chunk stages it and the sweep ends after at most one
+      // chunk per group, whatever the order in which the waves book.
       if (tid == 0) sh.wcur = 0;
       for (;;) {
         if (tid == 0) {
-          sh.cnt = 0;
+          sh.cnt = 64;
+          sh.start = 64;
+          sh.first = sh.wcur;
           sh.cur[r3] = 0;
           reinterpret_cast<int32_t *>(&sh.cx[r3])[1] = 0;  // X entries of the chunk
           sh.resume = ngroups;
         }
         __syncthreads();
         if (sh.wcur >= ngroups) break;  // uniform: read after the barrier
+        const int32_t g0 = sh.first;
         for (;;) {
           int32_t g = 0;
           if (lane == 0) g = atomicAdd(&sh.wcur, 1);
@@ -1000,7 +1007,10 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
           if (!m) continue;
           const int32_t pc = (int32_t)__popcll(m);
           int32_t pos = 0;
-          if (lane == 0) {
+          if (g == g0) {
+            pos = 64 - pc;
+            if (lane == 0) sh.start = pos;
+          } else if (lane == 0) {
             pos = lds_ld(&sh.cnt);
             bool fits = false;
             while (pos + pc <= a.fcap) {
@@ -1026,9 +1036,12 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
           }
         }
         __syncthreads();
-        const int32_t cnt = sh.cnt;
+        const int32_t cnt = sh.cnt, st = sh.start;
         if (tid == 0) sh.wcur = min(sh.wcur, sh.resume);  // read by all after the next barrier
-        if (cnt) expand_list<TPV, KIND, U, B>(G, S, cur, cnt, false, thr, P, X, &sh.cur[r3], c);
+        if (cnt > st) {
+          const FList chunk{cur.item + st, cur.beg + st, cur.cnt + st};
+          expand_list<TPV, KIND, U, B>(G, S, chunk, cnt - st, false, thr, P, X, &sh.cur[r3], c);
+        }
         __syncthreads();
       }
     }
