@@ -454,7 +454,7 @@ def serving_record(args, log, rates, requests, checks):
     tts = synth.serving_cities(reading=args.reading)
     graphs = [eat.graph_from_timetable(t) for t in tts]
     log(f"[serve] cities {[t.n_vertices for t in tts]} ready in {time.time() - t0:.0f}s")
-    sess = eat.Session(graphs, pool_bytes=1 << 30, n_streams=2)
+    sess = eat.Session(graphs, pool_bytes=1 << 30, n_streams=args.served_streams)
     n_thr = host_threads()
     csa = {}
     rows = []
@@ -495,6 +495,7 @@ def serving_record(args, log, rates, requests, checks):
         rows.append(row)
     sess.free()
     return {"graphs": [t.n_vertices for t in tts], "rates": rows, "bit_exact": bool(exact),
+            "streams": args.served_streams,
             "check": "connection scan on the 10k and 50k cities, certificate on the 500k city, "
                      "a few also against the query alone"}
 
@@ -664,6 +665,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="mixed workload: skip the served record")
     ap.add_argument("--served-rates", default="10000,50000", help="served record: Poisson rates (queries/s)")
     ap.add_argument("--served-requests", type=int, default=20000, help="served record: requests per rate")
+    ap.add_argument("--served-streams", type=int, default=2,
+                    help="serving: launches in flight at once (session streams)")
     ap.add_argument("--served-checks", type=int, default=64,
                     help="served record: answers per graph and rate checked against the oracle")
     ap.add_argument("--dump-stats", default="", metavar="PATH",
