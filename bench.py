@@ -665,7 +665,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="mixed workload: skip the served record")
     ap.add_argument("--served-rates", default="10000,50000", help="served record: Poisson rates (queries/s)")
     ap.add_argument("--served-requests", type=int, default=20000, help="served record: requests per rate")
-    ap.add_argument("--served-streams", type=int, default=2,
+    ap.add_argument("--served-streams", type=int, default=4,
                     help="serving: launches in flight at once (session streams)")
     ap.add_argument("--served-checks", type=int, default=64,
                     help="served record: answers per graph and rate checked against the oracle")
