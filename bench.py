@@ -604,13 +604,116 @@ def run_ablation(args, log):
         widths.append({"cluster_seconds": cw, "cluster_ap_ms": round(ms_v, 4),
                        "kernel_ms": None if ms_k is None else round(ms_k, 4)})
         log(f"[ablation] width {widths[-1]}")
+    # query variants (Section I): goal-directed batches, journeys, profiles
+    qv = query_variants_record(tt, s_, ts_, exp, g, out)
+    exact &= qv.pop("bit_exact")
+    log(f"[ablation] query variants {qv}")
+    # sub-trip shortcuts (Sections II-G, IV-B) on a city served by bus lines
+    sc = shortcuts_record(log)
+    exact &= sc.pop("bit_exact")
     print(json.dumps({"metric": "paper algorithm ladder: ms per EAT query (one query at a time)",
                       "workload": f"{name} ({args.reading} reading)", "queries": nq, "connections": int(C),
                       "serial_scan_ms": round(serial_ms, 4), "variants": rows, "virtual_warps": warps,
                       "kernel": {"ms_per_query": round(ms_plain, 4), "speedup_vs_serial": round(serial_ms / ms_plain, 2),
                                  "threads_per_vertex": tpv, "batched_qps": round(batched_qps, 1)},
-                      "cluster_widths": widths, "bit_exact": bool(exact),
+                      "cluster_widths": widths, "query_variants": qv, "shortcuts": sc, "bit_exact": bool(exact),
                       "device": torch.cuda.get_device_name()}), flush=True)
+
+
+def query_variants_record(tt, s_, ts_, exp, g, out):
+    """Goal-directed batch (destination: the reached stop of median arrival)
+    against the same batch answering every stop; eat_parents and eat_profile
+    timings; every result against the oracle."""
+    import torch
+
+    import oracle
+    from paper_1912_00966_amd import eat
+
+    nq, V = len(s_), tt.n_vertices
+    INF = oracle.INF
+    d = np.empty(nq, np.int32)
+    for i in range(nq):
+        r = np.flatnonzero(exp[i] != INF)
+        d[i] = r[np.argsort(exp[i][r])[len(r) // 2]]
+    slab = torch.empty((nq, V), dtype=torch.int32, device="cuda")
+    views = [slab[i] for i in range(nq)]
+    rec, exact = {}, True
+    for name, kw in (("full", {}), ("goal", {"q_dst": d})):
+        b = eat.Batch([g], np.zeros(nq, np.int32), s_, ts_, views, **kw)
+        b.run()
+        st = b.wait(stats=True)
+        got = slab.cpu().numpy()
+        if name == "goal":
+            exact &= all(got[i][d[i]] == exp[i][d[i]] for i in range(nq))
+        else:
+            exact &= bool(np.array_equal(got, np.stack(exp)))
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(5):
+            b.run()
+        b.wait()
+        rec[name] = {"qps": round(5 * nq / (time.perf_counter() - a), 1),
+                     "rounds_mean": round(float(np.mean([x["rounds"] for x in st])), 2),
+                     "type_evals_mean": round(float(np.mean([x["type_evals"] for x in st])), 1)}
+        b.free()
+    # journeys: parents of one answer
+    par = torch.empty((V, 3), dtype=torch.int32, device="cuda")
+    eat.eat_query(g, int(s_[0]), int(ts_[0]), out)
+    g.parents(int(s_[0]), out, out=par)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    for _ in range(10):
+        g.parents(int(s_[0]), out, out=par)
+    torch.cuda.synchronize()
+    rec["parents_ms"] = round((time.perf_counter() - a) * 100, 4)
+    pu, pt, pl = oracle.parents(tt.u, tt.v, tt.t, tt.lam, V, int(s_[0]), out.cpu().numpy())
+    exact &= bool(np.array_equal(par.cpu().numpy(), np.stack([pu, pt, pl], 1)))
+    # profile of one source over two hours of the morning
+    a = time.perf_counter()
+    dep, parr = g.profile(int(s_[0]), 6 * 3600, 8 * 3600)
+    rec["profile_ms"] = round((time.perf_counter() - a) * 1e3, 3)
+    rec["profile_departures"] = int(len(dep))
+    csa = oracle.Csa(tt.u, tt.v, tt.t, tt.lam, V)
+    dep_o, arr_o = csa.profile(int(s_[0]), 6 * 3600, 8 * 3600)
+    exact &= bool(np.array_equal(dep, dep_o) and np.array_equal(parr.cpu().numpy(), arr_o))
+    rec["bit_exact"] = bool(exact)
+    return rec
+
+
+def shortcuts_record(log):
+    """The 10,000-stop city served by bus lines, 256 queries in one launch,
+    without and with sub-trip shortcuts (sqrt of the mean trip length):
+    rounds, queries/s, every answer against the oracle on the original
+    connections."""
+    import torch
+
+    import oracle
+    from paper_1912_00966_amd import eat, synth
+
+    tt = synth.lines_city(10_000)
+    q = synth.queries(tt.n_vertices, 256, 10601)
+    exp = oracle.Csa(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices).query_many(q.s, q.ts)
+    slab = torch.empty((len(q), tt.n_vertices), dtype=torch.int32, device="cuda")
+    rec, exact = {}, True
+    for name, rule in (("plain", None), ("shortcuts", 0)):
+        g = eat.graph_from_timetable(tt, subtrip_len=rule)
+        b = eat.Batch([g], np.zeros(len(q), np.int32), q.s, q.ts, [slab[i] for i in range(len(q))])
+        b.run()
+        st = b.wait(stats=True)
+        exact &= bool(np.array_equal(slab.cpu().numpy(), exp))
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(10):
+            b.run()
+        b.wait()
+        rec[name] = {"connections": int(g.info.n_conn), "qps": round(10 * len(q) / (time.perf_counter() - a), 1),
+                     "rounds_mean": round(float(np.mean([x["rounds"] for x in st])), 2),
+                     "rounds_max": int(max(x["rounds"] for x in st))}
+        b.free()
+        g.free()
+    log(f"[ablation] shortcuts {rec}")
+    rec["bit_exact"] = bool(exact)
+    return rec
 
 
 def run_serving(args, log):
