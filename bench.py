@@ -61,7 +61,7 @@ HEADERS = {"auto": 0, "grid": 1, "compact": 2}  # eat_headers values
 # Overlapping consecutive batches pays when a batch is shorter than its slowest
 # query (few queries per CU); a batch that fills the chip for its whole launch
 # only loses L2 locality to it.  Measured on MI355X.
-DEFAULT_STREAMS = {"city-1k": 4, "city-50k": 4, "region-500k": 2, "mixed": 2}
+DEFAULT_STREAMS = {"city-1k": 4, "city-50k": 4, "region-500k": 2, "mixed": 3}
 # Threads per query: 768 puts two queries of 12 waves on a CU (more queries in
 # flight, the heavy ones still with many waves), 1024 finishes one long query
 # sooner and keeps the whole LDS for its table (region-500k).
@@ -72,7 +72,7 @@ def launch_key(o):
     """The effective launch options of a batch (eat_batch_options), as text."""
     return ",".join(str(x) for x in (o["threads_per_query"] or 1024, o["types_per_lane"] or 1,
                                      o["threads_per_vertex"], o["time_window"] or 7200, o["mode"], o["headers"],
-                                     o["table_cap"], o["frontier_cap"]))
+                                     o["table_cap"], o["frontier_cap"], o["query_order"]))
 
 
 def profile_traffic_for(args, options):
@@ -137,7 +137,7 @@ def _explicit_options(args):
     """True when a launch option was given on the command line."""
     return not (args.layout == "hybrid" and args.table == 0 and args.headers == "auto" and args.window == 0
                 and args.tpv == 0 and args.types_per_lane == 0 and args.threads == 0 and args.fcap == 0
-                and args.mode == "auto")
+                and args.mode == "auto" and args.order == 0)
 
 
 def _opts(args):
@@ -146,7 +146,8 @@ def _opts(args):
         threads = 1024  # virtual warps run in 1024-thread work-groups
     return {"threads_per_vertex": args.tpv, "types_per_lane": args.types_per_lane,
             "time_window": args.window, "table_cap": args.table, "mode": MODES[args.mode],
-            "headers": HEADERS[args.headers], "threads_per_query": threads, "frontier_cap": args.fcap}
+            "headers": HEADERS[args.headers], "threads_per_query": threads, "frontier_cap": args.fcap,
+            "query_order": args.order}
 
 
 def calibrate_copy(torch, mib, log):
@@ -268,10 +269,11 @@ def run_batched(args, log):
         del tslab
         torch.cuda.synchronize()
         tuned = {"best": best, "candidates": [[o["threads_per_query"], o["types_per_lane"], o["threads_per_vertex"],
-                                               o["time_window"], o["mode"], o["headers"], round(ms, 4)]
-                                              for o, ms in results],
+                                               o["time_window"], o["mode"], o["headers"], o["query_order"],
+                                               round(ms, 4)] for o, ms in results],
                  "candidate_fields": ["threads_per_query", "types_per_lane", "threads_per_vertex", "time_window",
-                                      "mode", "headers", "ms_per_run"], "tune_s": round(time.time() - t0, 2)}
+                                      "mode", "headers", "query_order", "ms_per_run"],
+                 "tune_s": round(time.time() - t0, 2)}
         log(f"[bench] autotuned in {tuned['tune_s']}s: {best}")
         opts = None
     slabs = [Slabs(torch, Vq, qg) for _ in range(S)]
@@ -755,6 +757,8 @@ def main():
                     help="threads per query (work-group size); 0 = per workload (%s)"
                          % ", ".join(f"{k} {v}" for k, v in DEFAULT_THREADS.items()))
     ap.add_argument("--fcap", type=int, default=0, help="frontier list entries (0 = default)")
+    ap.add_argument("--order", type=int, default=0, choices=(0, 1, 2, 3),
+                    help="query order of a batch: 0 auto, 1 locality, 2 longest first, 3 banded")
     ap.add_argument("--graph", action="store_true",
                     help="capture each stream's batch run into a HIP graph and replay it in the timed steps")
     ap.add_argument("--copy-mib", type=int, default=1024,

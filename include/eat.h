@@ -241,7 +241,11 @@ typedef enum {
    * time, earliest first: a query leaving early reaches far more stops (the
    * timetable thins out during the day), so the longest queries start first
    * and the launch does not end on one long query started last */
-  EAT_ORDER_LONGEST_FIRST = 2
+  EAT_ORDER_LONGEST_FIRST = 2,
+  /* the same buckets, each split by departure time into four bands of equal
+   * size, earliest band first, each band in the locality order: most of the
+   * longest-first tail and most of the locality */
+  EAT_ORDER_BANDED = 3
 } eat_query_order;
 
 typedef struct {

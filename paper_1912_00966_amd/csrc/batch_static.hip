@@ -126,7 +126,7 @@ extern "C" eat_status eat_query_batch_static(const eat_graph *const *graphs, int
   const int slots = lim.cus * per_cu;
   std::sort(qs, qs + n_q, [&](const QueryDev &a, const QueryDev &b) { return eat::query_before(graphs, a, b); });
   const int32_t nb = eat::bucket_offsets(n_q, std::min(lim.xccs, eat::kMaxBuckets), g_stage.buckets);
-  if (eat::use_longest_first(pl.order, n_q, slots)) eat::longest_first_in_buckets(qs, g_stage.buckets, nb);
+  eat::order_in_buckets(graphs, qs, g_stage.buckets, nb, eat::order_bands(pl.order, n_q, slots));
   for (int32_t i = 0; i < n_graphs; ++i) g_stage.graphs[i] = graphs[i]->desc;
 
   hipStream_t hs = static_cast<hipStream_t>(stream);

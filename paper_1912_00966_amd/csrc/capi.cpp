@@ -494,7 +494,7 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   if ((pl->block == kBlockMid || pl->block == kBlockQuarter || pl->block == kBlockSixth) && pl->ub != 1)
     return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query 256, 384 and 768 run one connection type per lane");
   pl->window = o.time_window == 0 ? 7200 : (o.time_window < 0 ? 0 : o.time_window);
-  if (o.query_order < EAT_ORDER_AUTO || o.query_order > EAT_ORDER_LONGEST_FIRST)
+  if (o.query_order < EAT_ORDER_AUTO || o.query_order > EAT_ORDER_BANDED)
     return set_err(EAT_ERR_INVALID_ARGUMENT, "unknown query order");
   pl->order = o.query_order;
   pl->max_rounds = o.max_rounds;
@@ -563,25 +563,35 @@ int32_t bucket_offsets(int64_t n, int n_buckets, int32_t *off) {
   return nb;
 }
 
-void longest_first_in_buckets(QueryDev *qs, const int32_t *off, int32_t nb) {
-  for (int32_t b = 0; b < nb; ++b)
-    std::sort(qs + off[b], qs + off[b + 1], [](const QueryDev &x, const QueryDev &y) {
+void order_in_buckets(const eat_graph *const *graphs, QueryDev *qs, const int32_t *off, int32_t nb, int bands) {
+  if (bands < 0) return;
+  for (int32_t b = 0; b < nb; ++b) {
+    QueryDev *q0 = qs + off[b];
+    const int64_t n = off[b + 1] - off[b];
+    std::sort(q0, q0 + n, [](const QueryDev &x, const QueryDev &y) {
       return x.ts != y.ts ? x.ts < y.ts : x.index < y.index;
     });
+    for (int k = 0; k < bands; ++k)  // inside a band of departure times: the locality order
+      std::sort(q0 + n * k / bands, q0 + n * (k + 1) / bands,
+                [&](const QueryDev &x, const QueryDev &y) { return query_before(graphs, x, y); });
+  }
 }
 
-bool use_longest_first(int order, int32_t n_q, int64_t slots) {
-  return order == EAT_ORDER_LONGEST_FIRST || (order == EAT_ORDER_AUTO && (int64_t)n_q > slots);
+int order_bands(int order, int32_t n_q, int64_t slots) {
+  if (order == EAT_ORDER_LOCALITY) return -1;
+  if (order == EAT_ORDER_LONGEST_FIRST) return 0;
+  if (order == EAT_ORDER_BANDED) return 4;
+  return (int64_t)n_q > slots ? 0 : -1;  // auto
 }
 
 void order_queries(const std::vector<const eat_graph *> &graphs, std::vector<QueryDev> &qs,
-                   int n_buckets, std::vector<int32_t> &off, bool longest_first) {
+                   int n_buckets, std::vector<int32_t> &off, int bands) {
   const eat_graph *const *g = graphs.data();
   std::sort(qs.begin(), qs.end(), [&](const QueryDev &a, const QueryDev &b) { return query_before(g, a, b); });
   off.assign((size_t)std::max(1, n_buckets) + 1, 0);
   const int32_t nb = bucket_offsets((int64_t)qs.size(), n_buckets, off.data());
   off.resize((size_t)nb + 1);
-  if (longest_first) longest_first_in_buckets(qs.data(), off.data(), nb);
+  order_in_buckets(g, qs.data(), off.data(), nb, bands);
 }
 
 void apply_plan(const Plan &pl, RunArgs *a) {
@@ -743,7 +753,7 @@ static eat_status batch_create(const eat_graph *const *graphs, int32_t n_graphs,
   const int slots = lim.cus * per_cu;  // work-groups in flight
   std::vector<int32_t> boff;
   eat::order_queries(std::vector<const eat_graph *>(graphs, graphs + n_graphs), qs,
-                     std::min(lim.xccs, eat::kMaxBuckets), boff, eat::use_longest_first(pl.order, n_q, slots));
+                     std::min(lim.xccs, eat::kMaxBuckets), boff, eat::order_bands(pl.order, n_q, slots));
   const int nb = (int)boff.size() - 1;
 
   eat_batch *b = new (std::nothrow) eat_batch();

@@ -109,14 +109,16 @@ int32_t bucket_offsets(int64_t n, int n_buckets, int32_t *off);
 // position of the source (nearby sources touch nearby data), and splits them
 // into n_buckets contiguous buckets of nearly equal size; off receives
 // n_buckets + 1 offsets.
-// With longest_first, each bucket's queries are then ordered by departure
-// time, earliest first (see EAT_ORDER_LONGEST_FIRST).
+// Then each bucket's queries are reordered as order_in_buckets says.
 void order_queries(const std::vector<const eat_graph *> &graphs, std::vector<QueryDev> &qs,
-                   int n_buckets, std::vector<int32_t> &off, bool longest_first);
-// Departure-time order inside each bucket of qs[0..n) (offsets off[0..nb]).
-void longest_first_in_buckets(QueryDev *qs, const int32_t *off, int32_t nb);
-// Whether a launch of n_q queries on `slots` work-groups in flight takes them
-// longest first (resolves EAT_ORDER_AUTO).
-bool use_longest_first(int order, int32_t n_q, int64_t slots);
+                   int n_buckets, std::vector<int32_t> &off, int bands);
+// Inside each bucket of qs (offsets off[0..nb]): bands < 0 keeps the locality
+// order; bands = 0 orders by departure time, earliest first; bands > 0 splits
+// the departure-time order into that many bands of equal size, earliest band
+// first, each band in the locality order.
+void order_in_buckets(const eat_graph *const *graphs, QueryDev *qs, const int32_t *off, int32_t nb, int bands);
+// The bands argument of order_in_buckets for a launch of n_q queries on
+// `slots` work-groups in flight (resolves EAT_ORDER_AUTO).
+int order_bands(int order, int32_t n_q, int64_t slots);
 
 }  // namespace eat

@@ -1249,7 +1249,8 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(
         for (int32_t p = tid; p < H; p += B) {
           const unsigned long long e = T.kv[p];
           const uint32_t key = (uint32_t)e;
-          if (key != NO_KEY) arr[key & ~IDLE] = (int32_t)(e >> 32);
+          // nontemporal like the fill: the reached stops' lines are not read again
+          if (key != NO_KEY) __builtin_nontemporal_store((int32_t)(e >> 32), arr + (key & ~IDLE));
         }
         if (tid == 0) sh.reached = sh.count;
         done = true;

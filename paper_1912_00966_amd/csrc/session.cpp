@@ -375,7 +375,7 @@ extern "C" eat_status eat_session_step(eat_session *S, int32_t *n_launched) {
     qs[(size_t)i] = QueryDev{sl.graph, sl.s, sl.ts, i, S->d_pool + sl.off};
   }
   std::vector<int32_t> boff;
-  eat::order_queries(S->graphs, qs, S->n_buckets, boff, eat::use_longest_first(S->plan.order, n, S->grid_cap));
+  eat::order_queries(S->graphs, qs, S->n_buckets, boff, eat::order_bands(S->plan.order, n, S->grid_cap));
   std::copy(qs.begin(), qs.end(), b.h_q);
   std::copy(boff.begin(), boff.end(), b.h_b);
   HIP_TRY(hipMemcpyAsync(b.d_q, b.h_q, sizeof(QueryDev) * (size_t)n, hipMemcpyHostToDevice, b.stream));

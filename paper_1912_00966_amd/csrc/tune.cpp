@@ -89,8 +89,9 @@ void record(const std::string &key, const eat_run_options &o) {
 }
 
 eat_run_options cand(int threads, int ub, int window, int tpv = 0, int mode = EAT_MODE_AUTO,
-                     int headers = EAT_HEADERS_AUTO) {
+                     int headers = EAT_HEADERS_AUTO, int order = EAT_ORDER_AUTO) {
   eat_run_options o{};
+  o.query_order = order;
   o.threads_per_query = threads;
   o.types_per_lane = ub;
   o.time_window = window;
@@ -101,14 +102,20 @@ eat_run_options cand(int threads, int ub, int window, int tpv = 0, int mode = EA
 }
 
 // The candidates: work-group size (one query per 1024-thread work-group, two
-// per CU at 768 / 512 threads, four at 384, six at 256), connection types in flight per lane (a
-// wave evaluates 64 x that many (type, cluster) lookups at once), virtual
-// warps of 16 / 32 lanes per active stop, the arrival window of a round, the
-// topology-driven schedule, and the compact header form.
+// per CU at 768 / 512 threads, four at 384, six at 256), connection types in
+// flight per lane (a wave evaluates 64 x that many (type, cluster) lookups at
+// once), virtual warps of 16 / 32 lanes per active stop, the arrival window of
+// a round, the topology-driven schedule, the compact header form, and the
+// order in which the work-groups take the queries (locality, departure-time
+// bands; timed over the caller's streams, where a launch's tail overlaps the
+// next launch).
 std::vector<eat_run_options> candidates() {
   return {cand(1024, 1, 7200), cand(1024, 1, 3600), cand(1024, 1, -1), cand(1024, 2, 7200),
           cand(768, 1, 7200),  cand(768, 1, 3600),  cand(512, 1, 7200), cand(512, 2, 7200),
           cand(384, 1, 7200),  cand(384, 1, 3600),  cand(256, 1, 7200),
+          cand(768, 1, 7200, 0, EAT_MODE_AUTO, EAT_HEADERS_AUTO, EAT_ORDER_LOCALITY),
+          cand(768, 1, 7200, 0, EAT_MODE_AUTO, EAT_HEADERS_AUTO, EAT_ORDER_BANDED),
+          cand(1024, 1, 7200, 0, EAT_MODE_AUTO, EAT_HEADERS_AUTO, EAT_ORDER_LOCALITY),
           cand(1024, 1, 7200, 16), cand(1024, 1, 7200, 32),
           cand(1024, 1, 7200, 0, EAT_MODE_TOPOLOGY), cand(1024, 1, 7200, 0, EAT_MODE_AUTO, EAT_HEADERS_COMPACT)};
 }

@@ -38,6 +38,7 @@ EAT_HEADERS_COMPACT = 2
 EAT_ORDER_AUTO = 0
 EAT_ORDER_LOCALITY = 1
 EAT_ORDER_LONGEST_FIRST = 2
+EAT_ORDER_BANDED = 3
 
 # every function include/eat.h declares
 EXPORTS = (
