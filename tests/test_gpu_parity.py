@@ -437,6 +437,48 @@ def test_batch_equals_single_queries_and_mixed_graphs():
         assert np.array_equal(alone, outs[k])
 
 
+
+@pytest.mark.parametrize("order", [eat.EAT_ORDER_AUTO, eat.EAT_ORDER_LOCALITY, eat.EAT_ORDER_LONGEST_FIRST,
+                                   eat.EAT_ORDER_BANDED])
+def test_query_orders_change_nothing_but_the_schedule(order):
+    """The order in which work-groups take a batch's queries is a schedule
+    only: on two graphs with more queries than work-groups in flight (1,200 on
+    a 1k-stop city, 300 on a 5k-stop one, shuffled), every answer equals the
+    scan's and every query's statistics land at its own index."""
+    tt1, _ = _workload("city-1k")
+    g1 = _graph("city-1k", "hybrid")
+    tt2 = synth.scaled_city(5000, seed=402)
+    g2 = eat.graph_from_timetable(tt2)
+    qa = synth.queries(tt1.n_vertices, 1200, 901)
+    qb = synth.queries(tt2.n_vertices, 300, 902)
+    qg = np.r_[np.zeros(len(qa.s), np.int32), np.ones(len(qb.s), np.int32)]
+    qs = np.r_[qa.s, qb.s]
+    qt = np.r_[qa.ts, qb.ts]
+    perm = np.random.default_rng(order).permutation(len(qg))
+    qg, qs, qt = qg[perm], qs[perm], qt[perm]
+    _say(f"order {order}: {len(qg)} queries over two graphs")
+    outs, st = _batch([g1, g2], qg, qs, qt, query_order=order, threads_per_query=768)
+    c1 = _csa("city-1k")
+    c2 = oracle.Csa(tt2.u, tt2.v, tt2.t, tt2.lam, tt2.n_vertices)
+    for k in range(len(qg)):
+        exp = (c1 if qg[k] == 0 else c2).query(int(qs[k]), int(qt[k]))
+        assert np.array_equal(outs[k], exp), (order, k)
+        assert st[k]["status"] == 0
+        if st[k]["spilled"] == 0:  # the on-chip table counts the stops it holds
+            assert st[k]["reached"] == int(np.count_nonzero(exp != oracle.INF)), (order, k)
+
+
+def test_unknown_query_order_is_refused():
+    tt, q = _workload("city-1k")
+    g = _graph("city-1k", "hybrid")
+    out = torch.full((tt.n_vertices,), -7, dtype=torch.int32, device="cuda")
+    for bad in (-1, 4):
+        with pytest.raises(eat.EatError) as ei:
+            eat.eat_query_batch([g], np.zeros(1, np.int32), q.s[:1], q.ts[:1], [out], options={"query_order": bad})
+        assert ei.value.status == eat.EAT_ERR_INVALID_ARGUMENT
+    assert torch.all(out == -7)
+
+
 # ------------------------------------------------------------- edge cases
 
 def test_racing_candidates_keep_the_minimum():
