@@ -281,7 +281,9 @@ def run_batched(args, log):
     # the current stream and S - 1 more (with the runtime's 4 hardware queues,
     # streams beyond that share queues)
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(S - 1)]
-    for w in range(max(args.warmup, 1)):
+    # every stream's batch runs at least once before the timed steps (its first
+    # run pays one-time costs: the slabs' first touch, the stream's queue)
+    for w in range(max(args.warmup, S)):
         batches[w % S].run(streams[w % S])
     torch.cuda.synchronize()
     batches[0].run(streams[0])

@@ -522,7 +522,7 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   const int items = std::max(64, (std::max(max_v, H) + 63) / 64 * 64);
   fcap = std::min(fcap, items);
   // work-groups that share a CU split its LDS
-  const size_t budget = small ? lim.lds / (size_t)qpc - 512 : lim.lds;
+  const size_t budget = (small ? lim.lds / (size_t)qpc : lim.lds) - kStaticLds;
   // slab mode (no table, or a table that overflowed): one activity bit per
   // stop, in LDS while it fits, else in a region of HBM per work-group
   pl->bits_global = (size_t)pl->bm_words * 4 + lists_lds(fcap) > budget;
@@ -534,14 +534,15 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
   auto need = [&](int h) { return std::max(table_lds(h, fcap), slab_lds); };
   while (table_auto && H >= 64 && need(H) > budget) H >>= 1;
   if (H < 64) H = 0;
-  if (H && need(H) > lim.lds) return set_err(EAT_ERR_UNSUPPORTED, "table_cap too large for the device's LDS");
+  if (H && need(H) + kStaticLds > lim.lds)
+    return set_err(EAT_ERR_UNSUPPORTED, "table_cap too large for the device's LDS");
   pl->table_cap = H;
   pl->ns_per_tick = lim.ns_per_tick;
   pl->table_bits = 0;
   while (H && (1 << pl->table_bits) < H) ++pl->table_bits;
   pl->fcap = fcap;
   pl->lds = H ? need(H) : slab_lds;
-  if (pl->lds > lim.lds)
+  if (pl->lds + kStaticLds > lim.lds)
     return set_err(EAT_ERR_UNSUPPORTED, "frontier lists too large for the device's LDS (" +
                                             std::to_string(pl->lds) + " bytes needed, " +
                                             std::to_string(lim.lds) + " available)");

@@ -55,7 +55,11 @@ using RelaxFn = void (*)(RunArgs);
 namespace {
 
 constexpr int32_t INF = EAT_INF;
-constexpr int kClaim = 4;  // frontier entries a wave claims at a time
+constexpr int kClaim = 4;  // frontier entries a wave claims at a time (rounds of many types)
+// A round's connection types, numbered in list order, are cut into windows of
+// 64; a wave relaxes whole windows.  Rounds of up to kWin windows take this
+// path; larger ones fall back to claims of kClaim entries.
+constexpr int kWin = 128;
 
 // Pointers into device (global) memory.  The graph descriptor and the query
 // records hold plain pointers; the kernels read through these so that every
@@ -388,13 +392,13 @@ struct FList {
 };
 
 // The stops a round expands (wave-claim expansion): {first type, type count,
-// arrival time, item} per entry, read by a claiming wave in one 16-byte load.
+// arrival time, offset of the first type in the round's type numbering} per
+// entry, read by a wave in one 16-byte load.
 using XList = int4 *;
 
-// Pushes into the next round's list.  The list's entry count is the low half
-// of a 64-bit LDS word whose high half counts the round's X entries, so the
-// take pass books both with one atomic.  The smallest arrival a lane pushes is
-// kept in a register and reduced once per round (wave_min).
+// Pushes into the next round's list: the list's entry count is the low half
+// of a 64-bit LDS word, one atomic per wave.  The smallest arrival a lane
+// pushes is kept in a register and reduced once per round (wave_min).
 struct ListPush {
   FList nxt;
   int32_t fcap;
@@ -432,6 +436,18 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
   v = min(v, __builtin_amdgcn_update_dpp(INF, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
   v = min(v, __builtin_amdgcn_update_dpp(INF, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
   return __builtin_amdgcn_readlane(v, 63);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave, every lane active: the
+// same DPP steps, adding where wave_min takes the minimum.
+__device__ __forceinline__ int32_t wave_incl_sum(int32_t v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
 }
 
 __device__ __forceinline__ int32_t lds_ld(const int32_t *p) {
@@ -759,9 +775,16 @@ struct Shared {
   int32_t cur[3];               // wave-claim cursor of round r: cur[r % 3]
   int32_t wcur, resume;         // sweep: next group to claim, first group of the next chunk
   int32_t first, start;         // sweep: the chunk's first group, its first list entry
-  unsigned long long cx[3];     // round r: low half entries pushed, high half X entries (per sweep chunk)
+  unsigned long long cx[3];     // round r: low half entries pushed to the next list
+  unsigned long long xt[3];     // round r (per sweep chunk): low half X entries, high half their types
   unsigned long long acc[5];
+  // windows of 64 types: bit i of wstart[w] is set if an X entry's types start
+  // at type 64 w + i; wentry[w] is the X entry holding type 64 w.  A wave
+  // clears the bits of each window it relaxes, so they are zero between rounds.
+  unsigned long long wstart[kWin];
+  int32_t wentry[kWin];
 };
+static_assert(sizeof(Shared) <= kStaticLds, "the plan reserves kStaticLds bytes of LDS for Shared");
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
@@ -771,15 +794,19 @@ __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane
 // them.  An expanded entry is made idle (with `clear`; a sweep has done it
 // already) before its connection types are relaxed, so an improvement that
 // lands later pushes it again.
-// TPV == 0: wave claims -- each wave takes 4 * U entries at a time and spreads
-//   their connection types over its lanes, U types per lane in flight (a
-//   load-balanced expansion without a block-wide scan).
+// TPV == 0: the take pass lists the expanded entries in X, numbering their
+//   connection types consecutively; wave w then relaxes the windows of 64
+//   types w, w + waves, ... (U windows per step), so a round of T types costs
+//   every wave at most ceil(T / (64 waves)) steps whatever its stops' degrees.
+//   A round of more than kWin windows falls back to wave claims: each wave
+//   takes 4 * U entries at a time from a cursor and spreads their types over
+//   its lanes.
 // TPV > 0: virtual warps (Section IV-B) -- groups of TPV lanes, one stop per
 //   group, lane i of a group takes the stop's types i, i + TPV, ...
 template <int TPV, int KIND, int U, int B, class Store>
 __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, const FList &cur, int32_t n,
-                                            bool clear, int32_t thr, ListPush &P, const XList X,
-                                            int32_t *cursor, Ctr &c) {
+                                            bool clear, int32_t thr, ListPush &P, const XList X, Shared &sh,
+                                            int r3, Ctr &c) {
   // Takes entry e (e < n), reading its arrival x: true if it is expanded
   // this round (with its type range in beg, cnt); defer = pushed to the next
   // list instead.  No relaxation runs during the take.
@@ -813,43 +840,105 @@ __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, con
   };
   const int lane = __lane_id();
   if constexpr (TPV == 0) {
-    // Take pass: every thread takes list entries; deferred ones go to the
-    // next list, the others to X, both booked with one atomic per wave.
+    unsigned long long *const xt = &sh.xt[r3];
+    // Take pass: every thread takes list entries.  Deferred ones go to the
+    // next list (one atomic per wave); expanded ones with connection types go
+    // to X with the offset of their first type (one more atomic per wave books
+    // the X entries and the types together, so X order is type order), and
+    // mark their window starts.
     for (int32_t e0 = 0; e0 < n; e0 += B) {
       const int32_t e = e0 + (int32_t)threadIdx.x;
       bool defer = false, go = false;
       int32_t item = 0, beg = 0, cnt = 0, x = INF;
       if (e < n) go = take(e, item, beg, cnt, x, defer);
+      go = go && cnt > 0;  // a stop without connection types has nothing to relax
       const uint64_t md = __ballot(defer), mg = __ballot(go);
-      if (md | mg) {
+      if (md) {
         if (defer) P.lmin = min(P.lmin, x);
-        const int leader = __ffsll((unsigned long long)(md | mg)) - 1;
-        unsigned long long old = 0;
-        if (lane == leader)
-          old = atomicAdd(P.cx, (unsigned long long)__popcll(md) | ((unsigned long long)__popcll(mg) << 32));
-        const int32_t lo = __builtin_amdgcn_readlane((int32_t)(uint32_t)old, leader);
-        const int32_t hi = __builtin_amdgcn_readlane((int32_t)(uint32_t)(old >> 32), leader);
+        const int leader = __ffsll((unsigned long long)md) - 1;
+        uint32_t lo = 0;
+        if (lane == leader) lo = (uint32_t)atomicAdd(P.cx, (unsigned long long)__popcll(md));
+        lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)lo, leader);
         if (defer && P.append) {
-          const int32_t slot = lo + (int32_t)__popcll(md & lanes_below(lane));
+          const int32_t slot = (int32_t)lo + (int32_t)__popcll(md & lanes_below(lane));
           if (slot < P.fcap) {
             P.nxt.item[slot] = item;
             P.nxt.beg[slot] = beg;
             P.nxt.cnt[slot] = cnt;
           }
         }
-        if (go) X[hi + (int32_t)__popcll(mg & lanes_below(lane))] = make_int4(beg, cnt, x, item);
+      }
+      if (mg) {  // every lane active: the scan reads all of them
+        const int32_t mine = go ? cnt : 0;
+        const int32_t incl = wave_incl_sum(mine);
+        const int32_t tot = __builtin_amdgcn_readlane(incl, 63);
+        const int leader = __ffsll((unsigned long long)mg) - 1;
+        unsigned long long old = 0;
+        if (lane == leader)
+          old = atomicAdd(xt, (unsigned long long)__popcll(mg) | ((unsigned long long)(uint32_t)tot << 32));
+        const int32_t xb = __builtin_amdgcn_readlane((int32_t)(uint32_t)old, leader);
+        const int32_t tb = __builtin_amdgcn_readlane((int32_t)(uint32_t)(old >> 32), leader);
+        if (go) {
+          const int32_t slot = xb + (int32_t)__popcll(mg & lanes_below(lane));
+          const int32_t toff = tb + incl - mine;
+          X[slot] = make_int4(beg, cnt, x, toff);
+          if ((toff >> 6) < kWin) atomicOr(&sh.wstart[toff >> 6], 1ull << (toff & 63));
+          // the windows whose first type is one of this entry's
+          for (int32_t w = (toff + 63) >> 6; w < kWin && (w << 6) < toff + cnt; ++w) sh.wentry[w] = slot;
+        }
       }
     }
-    __syncthreads();  // X complete
-    const int32_t nx = lds_ld(reinterpret_cast<int32_t *>(P.cx) + 1);
+    __syncthreads();  // X and the windows complete
+    const unsigned long long xv = __hip_atomic_load(xt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const int32_t nx = (int32_t)(uint32_t)xv, T = (int32_t)(uint32_t)(xv >> 32);
+    const int32_t nw = (T + 63) >> 6;
+    constexpr int kWaves = B / 64;
+    const int32_t wave = (int32_t)(threadIdx.x >> 6);
+    if (nw <= kWin) {
+      // Windows: lane i of window w relaxes type k = 64 w + i, of the X entry
+      // that holds it: wentry[w] plus the entries starting in (64 w, k].
+      for (int32_t w0 = wave * U; w0 < nw; w0 += kWaves * U) {
+        int64_t jj[U];
+        int32_t tb[U], tn[U], xx[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int32_t w = w0 + u;
+          const int32_t wc = w < nw ? w : nw - 1;
+          const unsigned long long starts = sh.wstart[wc];
+          const int32_t first = sh.wentry[wc];
+          const unsigned long long upto = lane == 63 ? ~0ull : (2ull << lane) - 1ull;
+          int32_t ei = first + (int32_t)__popcll(starts & ~1ull & upto);
+          const int32_t k = (w << 6) + lane;
+          ok[u] = w < nw && k < T && ei >= 0 && ei < nx;
+          const int4 t = X[ok[u] ? ei : 0];
+          const int32_t d = k - t.w;  // the type's place in its stop's range
+          ok[u] = ok[u] && d >= 0 && d < t.y;
+          tb[u] = ok[u] ? t.x : 0;
+          tn[u] = ok[u] ? t.y : 0;
+          jj[u] = ok[u] ? (int64_t)t.x + d : 0;
+          xx[u] = ok[u] ? t.z : 0;
+        }
+        // the windows' start bits have been read by every lane: clear them
+        if (lane == 0) {
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if (w0 + u < nw) sh.wstart[w0 + u] = 0ull;
+        }
+        relax_batch<KIND, U>(G, S, jj, tb, tn, xx, ok, P, c);
+      }
+      return;
+    }
+    // More than kWin windows: no wave reads the start bits; clear the ones set.
+    for (int32_t i = (int32_t)threadIdx.x; i < kWin; i += B) sh.wstart[i] = 0ull;
     // Wave claims: wave w first takes entries [w kC, w kC + kC) of X, then
     // further groups of kC from a shared cursor (fetched one claim ahead), and
     // spreads their connection types over its 64 lanes (a prefix sum of their
     // counts in scalar registers), U types per lane in flight, until X is used
     // up.  No block-wide scan and no barrier inside.
+    int32_t *const cursor = &sh.cur[r3];
     constexpr int kC = kClaim * U;
-    constexpr int kWaves = B / 64;
-    int32_t base = (int32_t)(threadIdx.x >> 6) * kC;
+    int32_t base = wave * kC;
     while (base < nx) {
       int32_t ahead = 0;
       if (lane == 0) ahead = atomicAdd(cursor, kC);
@@ -879,7 +968,7 @@ __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, con
         for (int u = 0; u < U; ++u) {
           const int32_t k = k0 + lane + 64 * u;
           ok[u] = k < total;
-          // the last entry whose offset is <= k (entries of no types are passed over)
+          // the last entry whose offset is <= k
           int32_t bi = sb[0], oi = 0, xi = sx[0], ni = sn[0];
 #pragma unroll
           for (int t = 1; t < kC; ++t) {
@@ -951,6 +1040,7 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
   int32_t base = x0;  // smallest arrival pushed for the round ("before round 0": the first item)
   if (tid < 3) {
     sh.cx[tid] = 0ull;
+    sh.xt[tid] = 0ull;
     sh.cur[tid] = 0;
     sh.nmin[tid] = tid == 2 ? x0 : INF;  // "pushed before round 0": the first item
   }
@@ -965,6 +1055,7 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
     // rounds - 2, before the barrier that ended round rounds - 1: safe to reset
     if (tid == 0) {
       sh.cx[(rounds + 1) % 3] = 0ull;
+      sh.xt[(rounds + 1) % 3] = 0ull;
       sh.nmin[(rounds + 1) % 3] = INF;
       sh.cur[(rounds + 1) % 3] = 0;
     }
@@ -973,7 +1064,7 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
     const int32_t thr = (a.window <= 0 || base >= INF - a.window) ? INF : base + a.window;
     ListPush P{nxt, a.fcap, !topo, &sh.cx[r3], INF};
     if (!sweep) {
-      expand_list<TPV, KIND, U, B>(G, S, cur, nf, true, thr, P, X, &sh.cur[r3], c);
+      expand_list<TPV, KIND, U, B>(G, S, cur, nf, true, thr, P, X, sh, r3, c);
     } else {
       ++qs.sweeps;
       // Chunks of up to fcap items: each wave claims groups of 64 items from
@@ -990,7 +1081,7 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
           sh.start = 64;
           sh.first = sh.wcur;
           sh.cur[r3] = 0;
-          reinterpret_cast<int32_t *>(&sh.cx[r3])[1] = 0;  // X entries of the chunk
+          sh.xt[r3] = 0ull;  // X entries of the chunk
           sh.resume = ngroups;
         }
         __syncthreads();
@@ -1040,7 +1131,7 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
         if (tid == 0) sh.wcur = min(sh.wcur, sh.resume);  // read by all after the next barrier
         if (cnt > st) {
           const FList chunk{cur.item + st, cur.beg + st, cur.cnt + st};
-          expand_list<TPV, KIND, U, B>(G, S, chunk, cnt - st, false, thr, P, X, &sh.cur[r3], c);
+          expand_list<TPV, KIND, U, B>(G, S, chunk, cnt - st, false, thr, P, X, sh, r3, c);
         }
         __syncthreads();
       }
@@ -1160,6 +1251,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(
       sh.q = q;
     }
     if (tid < 5) sh.acc[tid] = 0ull;
+    if (tid < kWin) sh.wstart[tid] = 0ull;
     if (tid == 0) {
       sh.count = 0;
       sh.over = 0;
