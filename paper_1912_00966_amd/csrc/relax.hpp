@@ -60,6 +60,8 @@ constexpr int kClaim = 4;  // frontier entries a wave claims at a time (rounds o
 // 64; a wave relaxes whole windows.  Rounds of up to kWin windows take this
 // path; larger ones fall back to claims of kClaim entries.
 constexpr int kWin = 128;
+// Chunks of the slab fill a lane issues per step a wave waits for others.
+constexpr int32_t kFillPerStep = 8;
 
 // Pointers into device (global) memory.  The graph descriptor and the query
 // records hold plain pointers; the kernels read through these so that every
@@ -783,10 +785,46 @@ struct Shared {
   // clears the bits of each window it relaxes, so they are zero between rounds.
   unsigned long long wstart[kWin];
   int32_t wentry[kWin];
+  // the infinity fill of the result slab still to issue: 16-byte chunks
+  // [fill_next, fill_n4) of fill_p (table queries; see fill_idle)
+  int4 *fill_p;
+  int32_t fill_n4, fill_next;
 };
 static_assert(sizeof(Shared) <= kStaticLds, "the plan reserves kStaticLds bytes of LDS for Shared");
 
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// The slab's infinity fill of a table query is issued in pieces by waves that
+// would otherwise wait at the end of a round: a wave's reads wait for every
+// store it issued before them (one in-order counter), so a fill issued all at
+// once up front would hold up the query's first reads.  k chunks of 16 bytes
+// per lane, nontemporal (the slab's lines are not read again).
+__device__ __forceinline__ void fill_issue(Shared &sh, int32_t k) {
+  const int32_t n4 = sh.fill_n4;
+  if (lds_ld(&sh.fill_next) >= n4) return;
+  const int lane = __lane_id();
+  int32_t base = 0;
+  if (lane == 0) base = atomicAdd(&sh.fill_next, 64 * k);
+  base = __builtin_amdgcn_readlane(base, 0);
+  gp<v4i> a4 = (gp<v4i>)sh.fill_p;
+  const v4i inf4 = {INF, INF, INF, INF};
+  for (int32_t j = 0; j < k; ++j) {
+    const int32_t i = base + 64 * j + lane;
+    if (i < n4) __builtin_nontemporal_store(inf4, a4 + i);
+  }
+}
+
+// The rest of the deferred fill, by the whole work-group (after a barrier
+// that ended the rounds, so fill_next is final).
+template <int B>
+__device__ __forceinline__ void fill_rest(Shared &sh) {
+  const int32_t n4 = sh.fill_n4;
+  gp<v4i> a4 = (gp<v4i>)sh.fill_p;
+  const v4i inf4 = {INF, INF, INF, INF};
+  for (int32_t i = sh.fill_next + (int32_t)threadIdx.x; i < n4; i += B) __builtin_nontemporal_store(inf4, a4 + i);
+}
 
 // Expand the entries of list[0..n) whose arrival is below thr; the others
 // are deferred: they go to the next list unexpanded, still active (made
@@ -927,6 +965,11 @@ __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, con
         }
         relax_batch<KIND, U>(G, S, jj, tb, tn, xx, ok, P, c);
       }
+      // a wave with fewer steps than wave 0 issues part of the fill meanwhile
+      constexpr int32_t kPer = kWaves * U;
+      const int32_t most = (nw + kPer - 1) / kPer;
+      const int32_t mine = nw > wave * U ? (nw - 1 - wave * U) / kPer + 1 : 0;
+      if (most > mine) fill_issue(sh, min(kFillPerStep * (most - mine), 2 * kFillPerStep));
       return;
     }
     // More than kWin windows: no wave reads the start bits; clear the ones set.
@@ -1188,7 +1231,10 @@ __device__ __forceinline__ void slab_query(const RunArgs &a, const GraphG &G, gp
   const int32_t VW = (V + 31) >> 5;
   const FList l0{l, l + F, l + 2 * F}, l1{l + 3 * F, l + 4 * F, l + 5 * F};
   for (int32_t i = tid; i < VW; i += B) bits_st(bits, i, 0u);
-  if (tid == 0) sh.over = 0;
+  if (tid == 0) {
+    sh.over = 0;
+    sh.fill_n4 = 0;  // the fill is complete: the slab now holds the arrivals
+  }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (tid == 0) {
@@ -1283,19 +1329,34 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(
     QState qs;
     Ctr c;
 
-    // ---- Initialize (Algorithm 2): the slab gets infinity everywhere.  The
-    // stores drain while the on-chip relaxation runs; they are nontemporal
-    // (streamed past the caches), so the slab does not evict the graph's
-    // lines that the relaxation reads (4.5 % faster on the mixed batch).
-    if ((reinterpret_cast<uintptr_t>(arr) & 15u) == 0) {
-      typedef int v4i __attribute__((ext_vector_type(4)));
-      gp<v4i> a4 = (gp<v4i>)arr;
-      const int32_t n4 = V >> 2;
-      const v4i inf4 = {INF, INF, INF, INF};
-      for (int32_t i = tid; i < n4; i += B) __builtin_nontemporal_store(inf4, a4 + i);
-      for (int32_t i = (n4 << 2) + tid; i < V; i += B) arr[i] = INF;
+    // ---- Initialize (Algorithm 2): the slab gets infinity everywhere, with
+    // nontemporal stores (streamed past the caches, so the slab does not evict
+    // the graph's lines that the relaxation reads).  A table query's fill is
+    // issued while its rounds run (fill_issue), the rest after them; a slab
+    // query needs it first.
+    const bool aligned = (reinterpret_cast<uintptr_t>(arr) & 15u) == 0;
+    if (aligned && a.table_cap > 0) {
+      for (int32_t i = ((V >> 2) << 2) + tid; i < V; i += B) arr[i] = INF;
+      if (tid == 0) {
+        sh.fill_p = reinterpret_cast<int4 *>(arr);
+        sh.fill_n4 = V >> 2;
+        sh.fill_next = 0;
+      }
     } else {
-      for (int32_t i = tid; i < V; i += B) arr[i] = INF;
+      if (aligned) {
+        gp<v4i> a4 = (gp<v4i>)arr;
+        const int32_t n4 = V >> 2;
+        const v4i inf4 = {INF, INF, INF, INF};
+        for (int32_t i = tid; i < n4; i += B) __builtin_nontemporal_store(inf4, a4 + i);
+        for (int32_t i = (n4 << 2) + tid; i < V; i += B) arr[i] = INF;
+      } else {
+        for (int32_t i = tid; i < V; i += B) arr[i] = INF;
+      }
+      if (tid == 0) {
+        sh.fill_p = nullptr;
+        sh.fill_n4 = 0;
+        sh.fill_next = 0;
+      }
     }
 
     bool done = false;
@@ -1335,6 +1396,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(
       } else {
         ok = run_rounds<TPV, KIND, U, B>(a, G, T, H, l0, l1, X, topo, max_rounds, Q.ts, sh, qs, c);
       }
+      fill_rest<B>(sh);  // before the final values, or before slab mode after an overflow
       if (ok) {
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the infinity fill has landed
         __syncthreads();
@@ -1350,7 +1412,8 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(
     }
     if (!done) {
       // ---- arrivals in the result slab (no table, or the table overflowed) ----------
-      // An overflowed table attempt never wrote the slab: it still holds infinity.
+      // An overflowed table attempt never wrote the slab: it holds infinity once
+      // the fill issued above has landed (slab_query waits for it).
       // The bitmap in HBM (it does not fit the LDS) is compiled into the
       // 1024-thread kernels only; the host runs such graphs with those.
       bool in_hbm = false;
