@@ -59,9 +59,10 @@ def algorithmic_bytes(stats, n_vertices):
 MODES = {"auto": 0, "topology": 2}  # eat_mode values
 HEADERS = {"auto": 0, "grid": 1, "compact": 2}  # eat_headers values
 # Overlapping consecutive batches pays when a batch is shorter than its slowest
-# query (few queries per CU); a batch that fills the chip for its whole launch
-# only loses L2 locality to it.  Measured on MI355X.
-DEFAULT_STREAMS = {"city-1k": 4, "city-50k": 4, "region-500k": 2, "mixed": 3}
+# query (few queries per CU), and for the mixed batch, whose launch ends on a
+# tail of long queries that the next launch fills.  Four streams use the
+# runtime's four hardware queues.  Measured on MI355X.
+DEFAULT_STREAMS = {"city-1k": 4, "city-50k": 4, "region-500k": 2, "mixed": 4}
 # Threads per query: 768 puts two queries of 12 waves on a CU (more queries in
 # flight, the heavy ones still with many waves), 1024 finishes one long query
 # sooner and keeps the whole LDS for its table (region-500k).
