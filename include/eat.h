@@ -250,7 +250,7 @@ typedef enum {
 
 typedef struct {
   int32_t threads_per_vertex; /* lanes sharing one active stop's types (virtual warps,
-                                 Section IV-B): 1,2,4,..,64; 0 = wave claims (below) */
+                                 Section IV-B): 1,2,4,..,64; 0 = type windows (below) */
   int32_t mode;               /* eat_mode */
   int32_t max_rounds;         /* round limit per query; 0 = n_vertices + 2 without a time
                                  window, 8 * n_vertices + 64 with one */
@@ -258,10 +258,12 @@ typedef struct {
                                  multiple of 64; 0 = auto */
   int32_t table_cap;          /* on-chip arrival-table slots (power of two); 0 = auto,
                                  -1 = keep arrivals in the result slab (HBM) only */
-  int32_t types_per_lane;     /* wave claims: each wave takes 4 * types_per_lane listed
-                                 stops at a time and spreads their connection types over its
-                                 64 lanes, types_per_lane types per lane in flight; 1..3,
-                                 0 = 1 */
+  int32_t types_per_lane;     /* threads_per_vertex = 0: a round's connection types are
+                                 numbered in list order and cut into windows of 64; each wave
+                                 relaxes types_per_lane windows per step, one type of each per
+                                 lane (rounds of more than 8,192 types: each wave takes
+                                 4 * types_per_lane listed stops at a time and spreads their
+                                 types over its lanes); 1..3, 0 = 1 */
   int32_t headers;            /* eat_headers: which form of the hybrid headers to read */
   int32_t time_window;        /* frontier rounds expand only the listed stops whose arrival
                                  is below (smallest arrival pushed for the round) + this
@@ -273,7 +275,7 @@ typedef struct {
   int32_t threads_per_query;  /* work-group size of one query: 1024 (default); 768 or 512
                                  -- two queries share a CU, each with half of its LDS for
                                  the arrival table; 384 -- four per CU, a quarter each;
-                                 256 -- six per CU, a sixth each (wave claims only:
+                                 256 -- six per CU, a sixth each (type windows only:
                                  threads_per_vertex = 0; 256, 384 and 768 with one type per
                                  lane).  More queries per CU raise throughput when many are
                                  in flight; 1024 finishes a single long query sooner.
@@ -299,7 +301,12 @@ typedef struct {
   int64_t elapsed_ns;    /* device wall-clock time from the query's start to its end */
 } eat_query_stats;
 
-/* One query (s, ts) on g.  arr: device, >= n_vertices int32, caller-owned;
+/* One query (s, ts) on g: the earliest arrival time at every stop over
+ * time-respecting paths that leave s at or after ts (the problem of Sections I
+ * and I-A), by the relaxation of Algorithms 2 (initialize), 3 (relax by atomic
+ * minimum, Section III-C) and 5-6 (next departure of a connection type,
+ * Sections II-B..II-D), iterated over the active stops (Section III-B) until
+ * no arrival improves.  arr: device, >= n_vertices int32, caller-owned;
  * it receives the earliest arrival times.  Asynchronous on stream when stats
  * is NULL; with stats (host pointer) the call waits for the stream, fills it
  * and returns EAT_ERR_NOT_CONVERGED if the round limit was hit.
@@ -316,7 +323,7 @@ eat_status eat_query(const eat_graph *g, int32_t s, int32_t ts, int32_t *arr,
  * the relaxation keeps only what can still improve the arrival at d -- a stop
  * reached no earlier than the best arrival at d found so far is neither
  * written nor expanded -- and ends when every listed stop is at or past it.
- * Runs the wave-claim kernels with one connection type per lane
+ * Runs the type-window kernels with one connection type per lane
  * (EAT_ERR_UNSUPPORTED if ro asks for threads_per_vertex > 0). */
 eat_status eat_query_goal(const eat_graph *g, int32_t s, int32_t ts, int32_t d, int32_t *arr,
                           void *stream, const eat_run_options *ro, eat_query_stats *stats);
@@ -370,7 +377,9 @@ eat_status eat_query_batch_static(const eat_graph *const *graphs, int32_t n_grap
  * options the tuned record (eat_batch_tune) or the defaults. */
 eat_status eat_batch_options(const eat_batch *b, eat_run_options *out);
 
-/* create + run + wait + free.  Returns after the batch has finished. */
+/* Many queries at once, each answered as by eat_query (Sections I and I-A;
+ * Algorithms 2, 3, 5, 6): create + run + wait + free.  Returns after the
+ * batch has finished. */
 eat_status eat_query_batch(const eat_graph *const *graphs, int32_t n_graphs,
                            const int32_t *q_graph, const int32_t *q_src,
                            const int32_t *q_ts, int32_t n_q, int32_t *const *arr,

@@ -13,7 +13,7 @@ Knobs the candidates cover (all exact; they change only speed):
   threads_per_query   1024, or 768 / 512 (two queries per CU)
   types_per_lane      connection types each lane keeps in flight: a wave has
                       64 x that many (type, cluster) lookups in flight
-  threads_per_vertex  0 = wave claims, or 16 / 32 lanes per active stop
+  threads_per_vertex  0 = type windows, or 16 / 32 lanes per active stop
                       (virtual warps: threads per edge)
   time_window         arrival window of a round (seconds; -1 = none)
   mode                frontier-driven rounds, or a topology sweep every round

@@ -613,11 +613,11 @@ void apply_plan(const Plan &pl, RunArgs *a) {
 // ---------------------------------------------------------------------------
 // single query
 // ---------------------------------------------------------------------------
-// Goal-directed queries run the wave-claim kernels with one connection type
+// Goal-directed queries run the type-window kernels with one connection type
 // per lane.
 static eat_status goal_plan(Plan *pl) {
   if (pl->tpv != 0)
-    return set_err(EAT_ERR_UNSUPPORTED, "goal-directed queries run with threads_per_vertex 0 (wave claims)");
+    return set_err(EAT_ERR_UNSUPPORTED, "goal-directed queries run with threads_per_vertex 0 (type windows)");
   pl->ub = 1;
   return EAT_OK;
 }

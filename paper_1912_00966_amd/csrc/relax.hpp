@@ -393,7 +393,7 @@ struct FList {
   int32_t *cnt;
 };
 
-// The stops a round expands (wave-claim expansion): {first type, type count,
+// The stops a round expands (type windows): {first type, type count,
 // arrival time, offset of the first type in the round's type numbering} per
 // entry, read by a wave in one 16-byte load.
 using XList = int4 *;
@@ -1476,9 +1476,9 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(
 }
 
 
-// TPV = 0: wave-claim expansion with ub connection types in flight per lane
+// TPV = 0: type windows with ub connection types in flight per lane
 // (1..3); TPV > 0: virtual warps of TPV lanes.  Goal-directed queries (goal)
-// run the wave-claim kernels with one type per lane.
+// run the type-window kernels with one type per lane.
 template <int KIND>
 RelaxFn relax_fn(int tpv, int ub, int block, bool goal) {
   if (goal) {
