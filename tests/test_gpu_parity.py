@@ -503,6 +503,52 @@ def _check_tt(tt, queries, layout="hybrid", cw=0, **opt):
         assert np.array_equal(got, c.query(s, ts)), (s, ts)
 
 
+def _hub_timetable(hub_types, seed):
+    """Stop 0 with `hub_types` connection types (one per head stop 1..hub_types,
+    three departures each), behind it a sparse random network over all stops,
+    so one round holds the hub's types and later rounds are ordinary."""
+    rng = np.random.default_rng(seed)
+    V = hub_types + 3000
+    heads = np.arange(1, hub_types + 1, dtype=np.int32)
+    u = [np.zeros(3 * hub_types, np.int32)]
+    v = [np.repeat(heads, 3)]
+    t = [np.tile(np.array([3600, 5400, 9000], np.int32), hub_types) + rng.integers(0, 600, 3 * hub_types)]
+    lam = [np.repeat(rng.integers(60, 3000, hub_types), 3)]
+    m = 8 * V
+    u.append(rng.integers(1, V, m))
+    v.append(rng.integers(0, V, m))
+    t.append(rng.integers(3600, 80000, m))
+    lam.append(rng.integers(30, 1800, m))
+    cat = lambda xs: np.concatenate(xs).astype(np.int32)
+    u, v, t, lam = cat(u), cat(v), cat(t), cat(lam)
+    keep = u != v
+    return synth.Timetable(f"hub{hub_types}", V, u[keep], v[keep], t[keep], lam[keep], 0, 0, 0)
+
+
+@pytest.mark.parametrize("hub_types", [5000, 9000])
+def test_high_degree_stop(hub_types):
+    """A stop with thousands of connection types: one entry whose types span
+    up to 79 windows of 64 (5,000 types), and a round of more than 128 windows
+    (9,000 types), which the kernels relax by claims of whole entries instead;
+    with tables that hold the round and tables that overflow into the slab."""
+    tt = _hub_timetable(hub_types, 11 + hub_types)
+    c = oracle.Csa(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices)
+    g = eat.eat_graph_build(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices)
+    src = np.array([0, 0, 0, 17, 1234], np.int32)
+    ts = np.array([0, 5000, 8000, 3000, 3600], np.int32)
+    exp = [c.query(int(s_), int(t_)) for s_, t_ in zip(src, ts)]
+    for opts in ({}, {"threads_per_query": 768}, {"threads_per_query": 384}, {"threads_per_query": 256},
+                 {"types_per_lane": 2}, {"types_per_lane": 3}, {"table_cap": -1}, {"time_window": -1},
+                 {"threads_per_query": 768, "frontier_cap": 64}):
+        _say(f"hub {hub_types}: {opts}")
+        outs, st = _batch([g], np.zeros(len(src), np.int32), src, ts, **opts)
+        for i in range(len(src)):
+            assert st[i]["status"] == 0
+            assert np.array_equal(outs[i], exp[i]), (opts, i)
+    got, _ = _query(g, 0, 0)
+    assert np.array_equal(got, exp[0])
+
+
 def test_edge_cases():
     _say("edge cases")
     rng = np.random.default_rng(5)
