@@ -91,10 +91,17 @@ KERNEL_SOURCES = ("relax.hpp", "relax_grid.hip", "kernels.hip", "device.hpp")
 
 
 def kernel_source_digest():
+    """SHA-256 of the kernel sources with their comments and blank lines
+    removed: a change of code changes it, a change of comments does not."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_1912_00966_amd", "csrc", name), "rb").read())
+        text = open(os.path.join(ROOT, "paper_1912_00966_amd", "csrc", name), encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+        h.update(code.encode())
     return h.hexdigest()
 
 

@@ -833,9 +833,11 @@ __device__ __forceinline__ void fill_rest(Shared &sh) {
 // already) before its connection types are relaxed, so an improvement that
 // lands later pushes it again.
 // TPV == 0: the take pass lists the expanded entries in X, numbering their
-//   connection types consecutively; wave w then relaxes the windows of 64
-//   types w, w + waves, ... (U windows per step), so a round of T types costs
-//   every wave at most ceil(T / (64 waves)) steps whatever its stops' degrees.
+//   connection types consecutively; the windows of 64 types are dealt to the
+//   waves U at a time (wave w: windows wU .. wU + U - 1, then the U windows
+//   U waves further on, ...), one step per U windows, so a round of T types
+//   costs every wave at most ceil(T / (64 U waves)) steps whatever its stops'
+//   degrees.
 //   A round of more than kWin windows falls back to wave claims: each wave
 //   takes 4 * U entries at a time from a cursor and spreads their types over
 //   its lanes.
