@@ -170,16 +170,20 @@ eat_status eat_layout_view_get(const eat_layout *layout, eat_layout_view *out);
 typedef struct eat_graph eat_graph;
 
 /* Preprocesses (as eat_layout_build) and uploads to the current HIP device.
- * The graph is immutable afterwards; queries on several streams may share it. */
+ * The uploads and the device-side header-grid build run on stream (NULL = the
+ * null stream), and the call returns once that stream has finished them: work
+ * on other streams (queries on other graphs) is not waited for.  The graph is
+ * immutable afterwards; queries on several streams may share it. */
 eat_status eat_graph_build(const int32_t *u, const int32_t *v, const int32_t *t,
                            const int32_t *lam, int64_t n_conn, int32_t n_vertices,
-                           const eat_build_options *opt, eat_graph **out);
+                           const eat_build_options *opt, void *stream, eat_graph **out);
 /* eat_layout_build_trips + eat_graph_upload. */
 eat_status eat_graph_build_trips(const int32_t *u, const int32_t *v, const int32_t *t,
                                  const int32_t *lam, const int32_t *trip, int64_t n_conn,
-                                 int32_t n_vertices, const eat_build_options *opt, eat_graph **out);
-/* Uploads an existing host layout (the layout may be freed afterwards).  Of
- * opt (nullable) only header_grid is used.
+                                 int32_t n_vertices, const eat_build_options *opt, void *stream,
+                                 eat_graph **out);
+/* Uploads an existing host layout (the layout may be freed afterwards) on
+ * stream, as eat_graph_build.  Of opt (nullable) only header_grid is used.
  *
  * Header grid (hybrid layout, device side).  Besides the compact headers, the
  * device holds one 16-byte entry per (type, cluster) -- empty clusters
@@ -204,7 +208,8 @@ eat_status eat_graph_build_trips(const int32_t *u, const int32_t *v, const int32
  * cluster read consecutive entries.  Costs 16 * n_types * n_clusters bytes of
  * HBM; built only when n_types * n_clusters < 2^31 and the pool holds fewer
  * than 2^30 words. */
-eat_status eat_graph_upload(const eat_layout *layout, const eat_build_options *opt, eat_graph **out);
+eat_status eat_graph_upload(const eat_layout *layout, const eat_build_options *opt, void *stream,
+                            eat_graph **out);
 void eat_graph_free(eat_graph *g); /* NULL-safe; waits for the device */
 eat_status eat_graph_info(const eat_graph *g, eat_graph_info_t *out);
 /* *count receives the number of eat_query calls on g, made without stats,

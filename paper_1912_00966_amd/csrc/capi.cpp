@@ -251,7 +251,8 @@ GraphBytes graph_bytes(const eat_layout &L, bool with_grid) {
 
 }  // namespace
 
-extern "C" eat_status eat_graph_upload(const eat_layout *L, const eat_build_options *opt, eat_graph **out) {
+extern "C" eat_status eat_graph_upload(const eat_layout *L, const eat_build_options *opt, void *stream,
+                                       eat_graph **out) {
   if (!L || !out) return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL argument");
   *out = nullptr;
   const int32_t header_grid = opt ? opt->header_grid : 0;
@@ -310,16 +311,18 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, const eat_build_opti
   g->info.device_bytes = (int64_t)b.total;
   g->info.n_grid_entries = with_grid ? T * (int64_t)L->n_clusters : 0;
 
+  const hipStream_t hs = static_cast<hipStream_t>(stream);
+  // host staging of the type records; it lives until the stream has finished
+  std::vector<int32_t> ty2, side, tail;
   auto up = [&](const void *dst, const void *src, size_t bytes) -> hipError_t {
     if (bytes == 0) return hipSuccess;
-    return hipMemcpy(const_cast<void *>(dst), src, bytes, hipMemcpyHostToDevice);
+    return hipMemcpyAsync(const_cast<void *>(dst), src, bytes, hipMemcpyHostToDevice, hs);
   };
   hipError_t ue = hipSuccess;
   if (ue == hipSuccess) ue = up(g->desc.vt, L->vt.data(), L->vt.size() * 4);
   if (ue == hipSuccess && T > 0) {
     // 32-byte type records; with the grid also the 16-byte side records and
     // the tail stop of every type
-    std::vector<int32_t> ty2, side, tail;
     try {
       ty2.resize((size_t)T * 8);
       if (with_grid) {
@@ -361,13 +364,13 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, const eat_build_opti
   }
   if (ue == hipSuccess && hybrid) {
     ue = up(g->desc.hdr, L->hdr.data(), (size_t)L->n_headers * 8);
-    if (ue == hipSuccess) ue = hipMemset(const_cast<int2 *>(g->desc.hdr) + L->n_headers, 0, 8);
+    if (ue == hipSuccess) ue = hipMemsetAsync(const_cast<int2 *>(g->desc.hdr) + L->n_headers, 0, 8, hs);
   }
   if (ue == hipSuccess) ue = up(g->desc.pool, L->pool.data(), L->pool.size() * 4);
   if (ue == hipSuccess) ue = up(g->d_desc, &g->desc, sizeof(GraphDev));
-  if (ue == hipSuccess) ue = hipMemset(g->d_failed, 0, sizeof(int32_t));
-  if (ue == hipSuccess && with_grid) ue = eat::launch_build_grid(g->desc, nullptr);
-  if (ue == hipSuccess) ue = hipDeviceSynchronize();
+  if (ue == hipSuccess) ue = hipMemsetAsync(g->d_failed, 0, sizeof(int32_t), hs);
+  if (ue == hipSuccess && with_grid) ue = eat::launch_build_grid(g->desc, hs);
+  if (ue == hipSuccess) ue = hipStreamSynchronize(hs);
   if (ue != hipSuccess) {
     (void)hipFree(g->d_buf);
     delete g;
@@ -379,26 +382,27 @@ extern "C" eat_status eat_graph_upload(const eat_layout *L, const eat_build_opti
 
 extern "C" eat_status eat_graph_build(const int32_t *u, const int32_t *v, const int32_t *t,
                                       const int32_t *lam, int64_t n_conn, int32_t n_vertices,
-                                      const eat_build_options *opt, eat_graph **out) {
+                                      const eat_build_options *opt, void *stream, eat_graph **out) {
   if (!out) return set_err(EAT_ERR_INVALID_ARGUMENT, "out is NULL");
   *out = nullptr;
   eat_layout *L = nullptr;
   eat_status s = eat_layout_build(u, v, t, lam, n_conn, n_vertices, opt, &L);
   if (s != EAT_OK) return s;
-  s = eat_graph_upload(L, opt, out);
+  s = eat_graph_upload(L, opt, stream, out);
   eat_layout_free(L);
   return s;
 }
 
 extern "C" eat_status eat_graph_build_trips(const int32_t *u, const int32_t *v, const int32_t *t,
                                             const int32_t *lam, const int32_t *trip, int64_t n_conn,
-                                            int32_t n_vertices, const eat_build_options *opt, eat_graph **out) {
+                                            int32_t n_vertices, const eat_build_options *opt, void *stream,
+                                            eat_graph **out) {
   if (!out) return set_err(EAT_ERR_INVALID_ARGUMENT, "out is NULL");
   *out = nullptr;
   eat_layout *L = nullptr;
   eat_status s = eat_layout_build_trips(u, v, t, lam, trip, n_conn, n_vertices, opt, &L);
   if (s != EAT_OK) return s;
-  s = eat_graph_upload(L, opt, out);
+  s = eat_graph_upload(L, opt, stream, out);
   eat_layout_free(L);
   return s;
 }

@@ -188,13 +188,13 @@ def lib():
     L.eat_layout_build.argtypes = conn + [ctypes.POINTER(_vp)]
     conn_trips = [_i32p, _i32p, _i32p, _i32p, _i32p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(BuildOptions)]
     L.eat_layout_build_trips.argtypes = conn_trips + [ctypes.POINTER(_vp)]
-    L.eat_graph_build_trips.argtypes = conn_trips + [ctypes.POINTER(_vp)]
+    L.eat_graph_build_trips.argtypes = conn_trips + [_vp, ctypes.POINTER(_vp)]
     L.eat_layout_free.argtypes = [_vp]
     L.eat_layout_free.restype = None
     L.eat_layout_info.argtypes = [_vp, ctypes.POINTER(GraphInfo)]
     L.eat_layout_view_get.argtypes = [_vp, ctypes.POINTER(LayoutView)]
-    L.eat_graph_build.argtypes = conn + [ctypes.POINTER(_vp)]
-    L.eat_graph_upload.argtypes = [_vp, ctypes.POINTER(BuildOptions), ctypes.POINTER(_vp)]
+    L.eat_graph_build.argtypes = conn + [_vp, ctypes.POINTER(_vp)]
+    L.eat_graph_upload.argtypes = [_vp, ctypes.POINTER(BuildOptions), _vp, ctypes.POINTER(_vp)]
     L.eat_graph_free.argtypes = [_vp]
     L.eat_graph_free.restype = None
     L.eat_graph_info.argtypes = [_vp, ctypes.POINTER(GraphInfo)]
@@ -472,32 +472,33 @@ class Graph:
 
 
 def eat_graph_build(u, v, t, lam, n_vertices, layout=EAT_LAYOUT_HYBRID, cluster_seconds=0,
-                    n_threads=0, header_grid=0) -> Graph:
-    """header_grid: 0 = also build the device header grid (hybrid), -1 = compact headers only."""
+                    n_threads=0, header_grid=0, stream=None) -> Graph:
+    """header_grid: 0 = also build the device header grid (hybrid), -1 = compact headers only.
+    The upload runs on `stream` (default: torch's current stream)."""
     u, v, t, lam = (_i32(x) for x in (u, v, t, lam))
     h = _vp()
     o = _build_opts(layout, cluster_seconds, n_threads, header_grid)
     _check(lib().eat_graph_build(_ptr32(u), _ptr32(v), _ptr32(t), _ptr32(lam), len(u),
-                                 int(n_vertices), ctypes.byref(o), ctypes.byref(h)))
+                                 int(n_vertices), ctypes.byref(o), _stream_handle(stream), ctypes.byref(h)))
     return Graph(h)
 
 
 def eat_graph_build_trips(u, v, t, lam, trip, n_vertices, subtrip_len=0, layout=EAT_LAYOUT_HYBRID,
-                          cluster_seconds=0, n_threads=0, header_grid=0) -> Graph:
+                          cluster_seconds=0, n_threads=0, header_grid=0, stream=None) -> Graph:
     """Device graph with sub-trip shortcuts (see eat_layout_build_trips)."""
     u, v, t, lam, trip = (_i32(x) for x in (u, v, t, lam, trip))
     h = _vp()
     o = _build_opts(layout, cluster_seconds, n_threads, header_grid, subtrip_len)
     _check(lib().eat_graph_build_trips(_ptr32(u), _ptr32(v), _ptr32(t), _ptr32(lam), _ptr32(trip), len(u),
-                                       int(n_vertices), ctypes.byref(o), ctypes.byref(h)))
+                                       int(n_vertices), ctypes.byref(o), _stream_handle(stream), ctypes.byref(h)))
     return Graph(h)
 
 
-def eat_graph_upload(layout: Layout, header_grid: int = 0) -> Graph:
+def eat_graph_upload(layout: Layout, header_grid: int = 0, stream=None) -> Graph:
     h = _vp()
     o = BuildOptions()
     o.header_grid = int(header_grid)
-    _check(lib().eat_graph_upload(layout._h, ctypes.byref(o), ctypes.byref(h)))
+    _check(lib().eat_graph_upload(layout._h, ctypes.byref(o), _stream_handle(stream), ctypes.byref(h)))
     return Graph(h)
 
 

@@ -416,6 +416,29 @@ def test_batch_run_replays_from_a_captured_hip_graph():
     b.free()
 
 
+def test_graph_built_on_a_stream_while_another_stream_runs():
+    """eat_graph_build on a stream of its own (uploads, the grid build and the
+    final wait on that stream) while a batch on another graph runs on a second
+    stream: both answers equal the scan's."""
+    tt, q = _workload("city-1k")
+    g1 = _graph("city-1k", "hybrid")
+    busy = torch.cuda.Stream()
+    slab = torch.full((len(q), tt.n_vertices), -7, dtype=torch.int32, device="cuda")
+    b = eat.Batch([g1], np.zeros(len(q), np.int32), q.s, q.ts, [slab[i] for i in range(len(q))])
+    b.run(busy)
+    tt2 = synth.scaled_city(5000, seed=403)
+    side = torch.cuda.Stream()
+    g2 = eat.eat_graph_build(tt2.u, tt2.v, tt2.t, tt2.lam, tt2.n_vertices, stream=side)
+    q2 = synth.queries(tt2.n_vertices, 8, 778)
+    c2 = oracle.Csa(tt2.u, tt2.v, tt2.t, tt2.lam, tt2.n_vertices)
+    for i in range(len(q2.s)):
+        got, _ = _query(g2, int(q2.s[i]), int(q2.ts[i]))
+        assert np.array_equal(got, c2.query(int(q2.s[i]), int(q2.ts[i]))), i
+    b.wait()
+    assert np.array_equal(slab.cpu().numpy(), _expected("city-1k"))
+    b.free()
+
+
 def test_batch_equals_single_queries_and_mixed_graphs():
     """Alone == batched, with two graphs of different size in one launch."""
     tt1, q1 = _workload("city-1k")
