@@ -281,7 +281,8 @@ typedef struct {
                                  -- two queries share a CU, each with half of its LDS for
                                  the arrival table; 384 -- four per CU, a quarter each;
                                  256 -- six per CU, a sixth each (type windows only:
-                                 threads_per_vertex = 0; 256, 384 and 768 with one type per
+                                 threads_per_vertex = 0; graphs of up to 65,536 stops,
+                                 EAT_ERR_UNSUPPORTED above; 256, 384 and 768 with one type per
                                  lane).  More queries per CU raise throughput when many are
                                  in flight; 1024 finishes a single long query sooner.
                                  0 = 1024 */
