@@ -105,8 +105,6 @@ constexpr int kBlockSixth = 256;    // six queries per CU with 4 waves each
 constexpr int queries_per_cu(int block) {
   return block == kBlock ? 1 : block == kBlockQuarter ? 4 : block == kBlockSixth ? 6 : 2;
 }
-// Largest graph (stops) that 384- and 256-thread queries accept.
-constexpr int32_t kSmallBlockMaxV = 65536;
 // LDS a relaxation work-group holds besides the dynamic part the plan sizes
 // (its counters and the start bits of the type windows).
 constexpr size_t kStaticLds = 2048;
