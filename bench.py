@@ -479,13 +479,21 @@ def serving_record(args, log, rates, requests, checks):
             if seen[r.graph] < checks:
                 want.add(r.id)
                 seen[r.graph] += 1
-        got = {}
+        # the checked answers are copied on a side stream into buffers made
+        # beforehand, so that checking never stalls the serving loop (the
+        # session orders a slot's reuse after such a copy)
+        side = torch.cuda.Stream()
+        bufs = {r.id: torch.empty(graphs[r.graph].n_vertices, dtype=torch.int32, device="cuda")
+                for r in reqs if r.id in want}
+        torch.cuda.synchronize()
 
         def keep(r, slot):
             if r.id in want:
-                got[r.id] = sess.result(slot).cpu().numpy()
+                sess.result(slot, out=bufs[r.id], stream=side)
 
         rep = serve.serve(sess, reqs, on_done=keep, min_batch=64, max_delay_s=50e-6)
+        side.synchronize()
+        got = {i: b.cpu().numpy() for i, b in bufs.items() if i in want}
         with ThreadPoolExecutor(n_thr) as ex:
             for gi, t in enumerate(tts):
                 mine = [reqs[i] for i in sorted(got) if reqs[i].graph == gi]
@@ -749,11 +757,11 @@ def main():
                     help="mixed (eight cities, 4,096 queries; default), city-1k, city-50k, region-500k")
     ap.add_argument("--layout", default="hybrid", choices=["hybrid", "flat"])
     ap.add_argument("--reading", default="S", choices=["S", "F"])
-    ap.add_argument("--tpv", type=int, default=0, help="threads per active stop (0 = wave claims)")
+    ap.add_argument("--tpv", type=int, default=0, help="threads per active stop (0 = type windows)")
     ap.add_argument("--window", type=int, default=0,
                     help="arrival window of a round in seconds (0 = auto, -1 = none)")
     ap.add_argument("--types-per-lane", type=int, default=0,
-                    help="wave claims: connection types in flight per lane (0 = auto)")
+                    help="type windows: connection types in flight per lane (0 = auto)")
     ap.add_argument("--table", type=int, default=0,
                     help="on-chip arrival-table slots (0 = auto, -1 = arrivals in HBM only)")
     ap.add_argument("--mode", default="auto", choices=sorted(MODES),
