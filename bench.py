@@ -462,6 +462,7 @@ def serving_record(args, log, rates, requests, checks):
     import oracle
     from paper_1912_00966_amd import eat, serve, synth
 
+    native = args.serve_loop == "native"
     t0 = time.time()
     tts = synth.serving_cities(reading=args.reading)
     graphs = [eat.graph_from_timetable(t) for t in tts]
@@ -486,12 +487,22 @@ def serving_record(args, log, rates, requests, checks):
         bufs = {r.id: torch.empty(graphs[r.graph].n_vertices, dtype=torch.int32, device="cuda")
                 for r in reqs if r.id in want}
         torch.cuda.synchronize()
+        if native:
+            order = sorted(reqs, key=lambda r: r.arrival)
+            lat, nrep = sess.serve([r.graph for r in order], [r.s for r in order], [r.ts for r in order],
+                                   [r.arrival for r in order], min_batch=64, max_delay_s=50e-6,
+                                   copy_dst=[bufs.get(r.id) for r in order], copy_stream=side)
+            span = nrep["wall_s"] - (order[0].arrival if order else 0.0)
+            rep = serve.ServeReport(n=len(order), wall_s=nrep["wall_s"], qps=len(order) / span,
+                                    latency_s=lat, steps=nrep["steps"],
+                                    mean_step_queries=nrep["launched"] / max(1, nrep["steps"]),
+                                    busy_waits=nrep["busy_waits"])
+        else:
+            def keep(r, slot):
+                if r.id in want:
+                    sess.result(slot, out=bufs[r.id], stream=side)
 
-        def keep(r, slot):
-            if r.id in want:
-                sess.result(slot, out=bufs[r.id], stream=side)
-
-        rep = serve.serve(sess, reqs, on_done=keep, min_batch=64, max_delay_s=50e-6)
+            rep = serve.serve(sess, reqs, on_done=keep, min_batch=64, max_delay_s=50e-6)
         side.synchronize()
         got = {i: b.cpu().numpy() for i, b in bufs.items() if i in want}
         with ThreadPoolExecutor(n_thr) as ex:
@@ -515,7 +526,7 @@ def serving_record(args, log, rates, requests, checks):
         rows.append(row)
     sess.free()
     return {"graphs": [t.n_vertices for t in tts], "rates": rows, "bit_exact": bool(exact),
-            "streams": args.served_streams,
+            "streams": args.served_streams, "loop": "eat_session_serve (native)" if native else "serve.py",
             "check": "connection scan on the 10k and 50k cities, certificate on the 500k city, "
                      "a few also against the query alone"}
 
@@ -790,6 +801,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="mixed workload: skip the served record")
     ap.add_argument("--served-rates", default="10000,50000", help="served record: Poisson rates (queries/s)")
     ap.add_argument("--served-requests", type=int, default=20000, help="served record: requests per rate")
+    ap.add_argument("--serve-loop", default="native", choices=["native", "python"],
+                    help="serving: the request loop in native code (eat_session_serve) or serve.py")
     ap.add_argument("--served-streams", type=int, default=4,
                     help="serving: launches in flight at once (session streams)")
     ap.add_argument("--served-checks", type=int, default=64,

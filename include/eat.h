@@ -507,8 +507,10 @@ eat_status eat_session_create(const eat_graph *const *graphs, int32_t n_graphs,
 eat_status eat_session_admit(eat_session *sess, int32_t graph, int32_t s, int32_t ts,
                              int32_t *slot);
 /* Launches the queries admitted since the last step (up to max_step_queries;
- * the rest wait for the next step).  If every stream is busy it waits for the
- * oldest launch to finish.  *n_launched (nullable) receives the count. */
+ * the rest wait for the next step).  Never waits: if every launch slot (one
+ * per stream) is still in flight it launches nothing and returns
+ * EAT_ERR_BUSY, so the caller can poll and admit meanwhile.  *n_launched
+ * (nullable) receives the count. */
 eat_status eat_session_step(eat_session *sess, int32_t *n_launched);
 /* Writes up to cap finished slot ids into done (host array); *n receives the
  * count.  Never blocks. */
@@ -526,6 +528,34 @@ eat_status eat_session_copy(eat_session *sess, int32_t slot, int32_t *dst, void 
 eat_status eat_session_query_stats(eat_session *sess, int32_t slot, eat_query_stats *out);
 /* Frees a finished (or admitted but not yet launched) slot. */
 eat_status eat_session_release(eat_session *sess, int32_t slot);
+
+typedef struct {
+  int64_t steps;       /* launches made */
+  int64_t launched;    /* queries launched (= n) */
+  int64_t busy_waits;  /* admissions deferred because the pool was full */
+  double wall_s;       /* from the call until the last query finished */
+} eat_serve_report;
+
+/* Drives the session through an open-loop request stream on the calling
+ * thread: request i arrives arrival_s[i] seconds after the call starts
+ * (non-decreasing), asking (src[i], ts[i]) on graphs[graph[i]].  Requests are
+ * admitted first come, first served while slot memory lasts; the admitted
+ * queries are launched in one step when no launched query is unfinished, when
+ * min_batch (>= 1) of them wait, or when the oldest has waited max_delay_s;
+ * every finished query is reported, its result copied to copy_dst[i] on
+ * copy_stream when copy_dst (nullable) and copy_dst[i] are not NULL (device
+ * memory, >= n_vertices int32; the slot's reuse waits for the copy), and its
+ * slot released.  latency_s[i] (host array) receives the time from its arrival
+ * to the poll that saw it finished.  All host arrays have n entries.  The
+ * requests are checked before the first one is admitted
+ * (EAT_ERR_INVALID_ARGUMENT); the session must hold no admitted or unfinished
+ * query when called.  rep (nullable) receives the counts.  This is the
+ * request loop of a server, in native code: Section I's queries, answered by
+ * eat_session_step launches. */
+eat_status eat_session_serve(eat_session *sess, int32_t n, const int32_t *graph, const int32_t *src,
+                             const int32_t *ts, const double *arrival_s, int32_t min_batch,
+                             double max_delay_s, int32_t *const *copy_dst, void *copy_stream,
+                             double *latency_s, eat_serve_report *rep);
 void eat_session_free(eat_session *sess); /* NULL-safe; waits for the device */
 
 /* ---------------------------------------------------------------------------

@@ -18,11 +18,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstring>
 #include <deque>
 #include <map>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "device.hpp"
@@ -485,3 +487,99 @@ extern "C" eat_status eat_session_release(eat_session *S, int32_t slot) {
 }
 
 extern "C" void eat_session_free(eat_session *S) { destroy(S); }
+
+// ---------------------------------------------------------------------------
+// The request loop of a server, natively: open-loop arrivals, first-come
+// admission, steps by the batching policy, completions polled, copied and
+// released.
+// ---------------------------------------------------------------------------
+extern "C" eat_status eat_session_serve(eat_session *S, int32_t n, const int32_t *graph, const int32_t *src,
+                                        const int32_t *ts, const double *arrival_s, int32_t min_batch,
+                                        double max_delay_s, int32_t *const *copy_dst, void *copy_stream,
+                                        double *latency_s, eat_serve_report *rep) {
+  if (!S) return set_err(EAT_ERR_INVALID_ARGUMENT, "session is NULL");
+  if (n < 0 || min_batch < 1 || !(max_delay_s >= 0.0))
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "n >= 0, min_batch >= 1 and max_delay_s >= 0 are required");
+  if (n > 0 && (!graph || !src || !ts || !arrival_s || !latency_s))
+    return set_err(EAT_ERR_INVALID_ARGUMENT, "NULL request array");
+  for (const Slot &sl : S->slots)
+    if (sl.state == kAdmitted || sl.state == kLaunched)
+      return set_err(EAT_ERR_INVALID_ARGUMENT, "the session holds admitted or unfinished queries");
+  for (int32_t i = 0; i < n; ++i) {
+    if (graph[i] < 0 || graph[i] >= (int32_t)S->graphs.size())
+      return set_err(EAT_ERR_INVALID_ARGUMENT, "request " + std::to_string(i) + ": bad graph index");
+    if (src[i] < 0 || src[i] >= S->graphs[(size_t)graph[i]]->info.n_vertices || ts[i] < 0)
+      return set_err(EAT_ERR_INVALID_ARGUMENT, "request " + std::to_string(i) + ": bad source or time");
+    if (!(arrival_s[i] >= 0.0) || (i > 0 && arrival_s[i] < arrival_s[i - 1]))
+      return set_err(EAT_ERR_INVALID_ARGUMENT, "arrival_s must be >= 0 and non-decreasing");
+  }
+  using Clock = std::chrono::steady_clock;
+  const Clock::time_point t0 = Clock::now();
+  auto now_s = [&]() { return std::chrono::duration<double>(Clock::now() - t0).count(); };
+  std::deque<int32_t> waiting;                      // arrived, not admitted
+  std::deque<std::pair<int32_t, double>> pending;   // admitted, not launched: (slot, admit time)
+  std::vector<int32_t> req_of(S->slots.size(), -1);  // slot -> request
+  std::vector<int32_t> fin(1024);
+  int64_t unfinished = 0, steps = 0, launched = 0, busy = 0;
+  int32_t done = 0, next = 0;
+  while (done < n) {
+    const double now = now_s();
+    while (next < n && arrival_s[next] <= now) waiting.push_back(next++);
+    while (!waiting.empty()) {
+      const int32_t r = waiting.front();
+      int32_t slot = -1;
+      const eat_status st = eat_session_admit(S, graph[r], src[r], ts[r], &slot);
+      if (st == EAT_ERR_BUSY) {
+        ++busy;
+        break;
+      }
+      if (st != EAT_OK) return st;
+      waiting.pop_front();
+      if ((size_t)slot >= req_of.size()) req_of.resize((size_t)slot + 1, -1);
+      req_of[(size_t)slot] = r;
+      pending.emplace_back(slot, now);
+    }
+    if (!pending.empty() &&
+        (unfinished == 0 || (int32_t)pending.size() >= min_batch || now - pending.front().second >= max_delay_s)) {
+      int32_t k = 0;
+      const eat_status st = eat_session_step(S, &k);
+      if (st != EAT_OK && st != EAT_ERR_BUSY) return st;
+      if (st == EAT_OK && k > 0) {  // the oldest k admitted queries
+        pending.erase(pending.begin(), pending.begin() + k);
+        unfinished += k;
+        launched += k;
+        ++steps;
+      }
+    }
+    int32_t nf = 0;
+    eat_status st = eat_session_poll(S, fin.data(), (int32_t)fin.size(), &nf);
+    if (st != EAT_OK) return st;
+    if (nf > 0) {
+      const double t_done = now_s();
+      for (int32_t j = 0; j < nf; ++j) {
+        const int32_t slot = fin[(size_t)j];
+        const int32_t r = req_of[(size_t)slot];
+        req_of[(size_t)slot] = -1;
+        latency_s[r] = t_done - arrival_s[r];
+        if (copy_dst && copy_dst[r]) {
+          st = eat_session_copy(S, slot, copy_dst[r], copy_stream);
+          if (st != EAT_OK) return st;
+        }
+        st = eat_session_release(S, slot);
+        if (st != EAT_OK) return st;
+        --unfinished;
+        ++done;
+      }
+    } else if (unfinished == 0 && pending.empty() && waiting.empty() && next < n) {
+      const double gap = arrival_s[next] - now_s();  // idle until the next arrival
+      if (gap > 200e-6) std::this_thread::sleep_for(std::chrono::duration<double>(gap - 100e-6));
+    }
+  }
+  if (rep) {
+    rep->steps = steps;
+    rep->launched = launched;
+    rep->busy_waits = busy;
+    rep->wall_s = now_s();
+  }
+  return EAT_OK;
+}

@@ -51,7 +51,7 @@ EXPORTS = (
     "eat_version", "eat_session_create", "eat_session_admit", "eat_session_step",
     "eat_session_poll", "eat_session_sync", "eat_session_result", "eat_session_copy",
     "eat_session_query_stats",
-    "eat_session_release", "eat_session_free",
+    "eat_session_release", "eat_session_free", "eat_session_serve",
     "eat_ap_cover", "eat_esdg_levels", "eat_variant_graph_build", "eat_variant_graph_info", "eat_variant_query",
     "eat_variant_graph_free",
 )
@@ -119,6 +119,14 @@ class QueryStats(ctypes.Structure):
                 ("activations", ctypes.c_int64), ("type_evals", ctypes.c_int64),
                 ("header_loads", ctypes.c_int64), ("pool_loads", ctypes.c_int64),
                 ("improvements", ctypes.c_int64), ("elapsed_ns", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ServeReport(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("launched", ctypes.c_int64), ("busy_waits", ctypes.c_int64),
+                ("wall_s", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -249,6 +257,9 @@ def lib():
     L.eat_session_copy.argtypes = [_vp, ctypes.c_int32, _vp, _vp]
     L.eat_session_query_stats.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(QueryStats)]
     L.eat_session_release.argtypes = [_vp, ctypes.c_int32]
+    _f64p = ctypes.POINTER(ctypes.c_double)
+    L.eat_session_serve.argtypes = [_vp, ctypes.c_int32, _i32p, _i32p, _i32p, _f64p, ctypes.c_int32,
+                                    ctypes.c_double, ctypes.POINTER(_vp), _vp, _f64p, ctypes.POINTER(ServeReport)]
     L.eat_session_free.argtypes = [_vp]
     L.eat_session_free.restype = None
     for name in EXPORTS:
@@ -748,6 +759,32 @@ class Session:
 
     def release(self, slot: int):
         _check(lib().eat_session_release(self._h, int(slot)))
+
+    def serve(self, graph, src, ts, arrival_s, min_batch: int = 64, max_delay_s: float = 50e-6,
+              copy_dst=None, copy_stream=None):
+        """eat_session_serve: the whole open-loop request stream in native code.
+        copy_dst: None, or a list with a CUDA int32 tensor (or None) per
+        request.  Returns (latency in seconds per request, report dict)."""
+        graph, src, ts = (_i32(x) for x in (graph, src, ts))
+        arrival = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        n = len(graph)
+        if not (len(src) == len(ts) == len(arrival) == n):
+            raise ValueError("request arrays differ in length")
+        lat = np.zeros(n, np.float64)
+        f64 = ctypes.POINTER(ctypes.c_double)
+        dst = None
+        if copy_dst is not None:
+            if len(copy_dst) != n:
+                raise ValueError("copy_dst needs one entry per request")
+            dst = (_vp * n)(*[None if d is None else
+                              _dev_ptr(d, self.graphs[int(graph[i])].n_vertices, "copy_dst")
+                              for i, d in enumerate(copy_dst)])
+        rep = ServeReport()
+        _check(lib().eat_session_serve(self._h, n, _ptr32(graph), _ptr32(src), _ptr32(ts),
+                                       arrival.ctypes.data_as(f64), int(min_batch), float(max_delay_s),
+                                       dst, _stream_handle(copy_stream) if dst is not None else None,
+                                       lat.ctypes.data_as(f64), ctypes.byref(rep)))
+        return lat, rep.as_dict()
 
     def free(self):
         if getattr(self, "_h", None):

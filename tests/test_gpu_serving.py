@@ -199,3 +199,54 @@ def test_steps_are_refused_not_blocked_when_every_launch_is_in_flight():
     for s_, (src, t) in zip(slots[:8], zip(q.s, q.ts)):
         assert np.array_equal(sess.result(s_).cpu().numpy(), exp.query(int(src), int(t)))
     sess.free()
+
+
+@pytest.mark.parametrize("pool_bytes,rate,n_streams", [(0, 50_000, 4), (64 * 1024, 400_000, 3)],
+                         ids=["roomy-pool", "tiny-pool"])
+def test_native_request_loop_serves_every_request_exactly(pool_bytes, rate, n_streams):
+    """eat_session_serve runs the open-loop stream in native code: every
+    request's copied answer equals the scan's, every latency is positive, and a
+    pool with room for about three 5k-stop slots still serves them all."""
+    tts, graphs = _two_graphs()
+    sess = eat.Session(graphs, pool_bytes=pool_bytes, n_streams=n_streams)
+    reqs = serve.poisson_requests(rate, 300, [g.n_vertices for g in graphs], seed=17)
+    reqs = sorted(reqs, key=lambda r: r.arrival)
+    gi = np.array([r.graph for r in reqs], np.int32)
+    dst = [torch.full((graphs[int(g)].n_vertices,), -7, dtype=torch.int32, device="cuda") for g in gi]
+    side = torch.cuda.Stream()
+    print(f"native loop: {len(reqs)} requests at {rate} qps", flush=True)
+    lat, rep = sess.serve(gi, [r.s for r in reqs], [r.ts for r in reqs], [r.arrival for r in reqs],
+                          min_batch=16, max_delay_s=20e-6, copy_dst=dst, copy_stream=side)
+    side.synchronize()
+    assert rep["launched"] == len(reqs) and rep["steps"] >= 1
+    assert np.all(lat > 0)
+    csa = [oracle.Csa(t.u, t.v, t.t, t.lam, t.n_vertices) for t in tts]
+    for k, r in enumerate(reqs):
+        assert np.array_equal(dst[k].cpu().numpy(), csa[r.graph].query(r.s, r.ts)), k
+    # the session is empty again: a second stream of requests runs on it
+    lat2, rep2 = sess.serve(gi[:20], [r.s for r in reqs[:20]], [r.ts for r in reqs[:20]],
+                            [r.arrival for r in reqs[:20]])
+    assert rep2["launched"] == 20 and np.all(lat2 > 0)
+    sess.free()
+
+
+def test_native_request_loop_checks_its_requests():
+    tts, graphs = _two_graphs()
+    sess = eat.Session(graphs, n_streams=2)
+    V0 = graphs[0].n_vertices
+    cases = [([0, 0], [1, 2], [0, 0], [0.001, 0.0]),   # arrivals out of order
+             ([0, 2], [1, 2], [0, 0], [0.0, 0.001]),   # no graph 2
+             ([0], [V0], [0], [0.0]),                  # source out of range
+             ([0], [1], [-5], [0.0])]                  # negative departure time
+    for g, s, t, a in cases:
+        with pytest.raises(eat.EatError) as ei:
+            sess.serve(g, s, t, a)
+        assert ei.value.status == eat.EAT_ERR_INVALID_ARGUMENT
+    slot = sess.admit(0, 1, 0)  # an admitted query left in the session
+    with pytest.raises(eat.EatError) as ei:
+        sess.serve([0], [1], [0], [0.0])
+    assert ei.value.status == eat.EAT_ERR_INVALID_ARGUMENT
+    sess.release(slot)
+    lat, rep = sess.serve([0], [1], [0], [0.0])
+    assert rep["launched"] == 1
+    sess.free()
