@@ -136,8 +136,8 @@ def cpu_model():
 
 
 def host_threads():
-    """Threads for the oracle: the cores this process may use, at most 16 (the
-    GPU machine's CPU share)."""
+    """Threads for the oracle: the cores this process may use, at most 16 (a
+    GPU's share of the host's cores on an 8-GPU node)."""
     return max(1, min(len(os.sched_getaffinity(0)), 16))
 
 

@@ -47,7 +47,7 @@ typedef enum {
   EAT_ERR_DEVICE = 3,           /* a HIP call failed, or no usable GPU */
   EAT_ERR_NOT_CONVERGED = 4,    /* a query hit its round limit */
   EAT_ERR_BUSY = 5,             /* no free result slot (serving sessions) */
-  EAT_ERR_UNSUPPORTED = 6       /* valid input outside this build's limits */
+  EAT_ERR_UNSUPPORTED = 6       /* valid input outside the library's limits */
 } eat_status;
 
 typedef enum {
