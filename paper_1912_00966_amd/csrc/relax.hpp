@@ -19,10 +19,11 @@
 // Per query:
 //   arrivals   an open-addressing hash table in LDS of the stops the query has
 //              touched: one 64-bit word per slot {arrival, idle flag, stop}.
-//              The caller's result slab in HBM (Algorithm 2 fills it with
-//              infinity, arr[s] = ts) receives the final values; if the table
-//              overflows, the query runs again with its arrivals in the slab,
-//              updated with global atomic minimum (Algorithm 3, Section III-C).
+//              The caller's result slab in HBM (Algorithm 2: infinity
+//              everywhere, arr[s] = ts; the fill is issued in pieces while the
+//              rounds run) receives the final values; if the table overflows,
+//              the query runs again with its arrivals in the slab, updated with
+//              global atomic minimum (Algorithm 3, Section III-C).
 //   activity   the slot's flag (one LDS bit per stop in slab mode): "improved
 //              since it was last expanded" (the active/nextactive flags of
 //              Section III-B).  Setting it also de-duplicates pushes.
@@ -30,9 +31,10 @@
 //              frontier does not fit, the next round sweeps the flags instead
 //              (the topology-driven scan of the paper, 64 items at a time).
 //   Each round takes the listed stops (those past the round's arrival window
-//   wait for a later round), then the waves claim them a few at a time and
-//   spread their connection types over their 64 lanes (or, with TPV > 0, a
-//   group of TPV lanes per stop: the virtual warps of Section IV-B).  A type
+//   wait for a later round) and numbers their connection types; the waves then
+//   relax windows of 64 consecutive types, one type per lane, dealt to them in
+//   turn (or, with TPV > 0, a group of TPV lanes per stop: the virtual warps
+//   of Section IV-B).  A type
 //   (u, v, lam) gives the earliest departure t_c >= arr[u] (Section II-B) via
 //   the cluster lookup of Section II-D and the progression closed form of
 //   Algorithm 6; arr[v] drops to t_c + lam if that is earlier.
