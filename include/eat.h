@@ -548,7 +548,8 @@ typedef struct {
  * slot released.  latency_s[i] (host array) receives the time from its arrival
  * to the poll that saw it finished.  All host arrays have n entries.  The
  * requests are checked before the first one is admitted
- * (EAT_ERR_INVALID_ARGUMENT); the session must hold no admitted or unfinished
+ * (EAT_ERR_INVALID_ARGUMENT, also for a graph whose result slot is larger
+ * than the whole pool); the session must hold no admitted or unfinished
  * query when called.  rep (nullable) receives the counts.  This is the
  * request loop of a server, in native code: Section I's queries, answered by
  * eat_session_step launches. */

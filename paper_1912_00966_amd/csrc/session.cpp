@@ -508,8 +508,12 @@ extern "C" eat_status eat_session_serve(eat_session *S, int32_t n, const int32_t
   for (int32_t i = 0; i < n; ++i) {
     if (graph[i] < 0 || graph[i] >= (int32_t)S->graphs.size())
       return set_err(EAT_ERR_INVALID_ARGUMENT, "request " + std::to_string(i) + ": bad graph index");
-    if (src[i] < 0 || src[i] >= S->graphs[(size_t)graph[i]]->info.n_vertices || ts[i] < 0)
+    const int32_t V = S->graphs[(size_t)graph[i]]->info.n_vertices;
+    if (src[i] < 0 || src[i] >= V || ts[i] < 0)
       return set_err(EAT_ERR_INVALID_ARGUMENT, "request " + std::to_string(i) + ": bad source or time");
+    // a slot larger than the whole pool could never be admitted
+    if (((int64_t)V + kSlotAlignWords - 1) / kSlotAlignWords * kSlotAlignWords > S->pool_words)
+      return set_err(EAT_ERR_INVALID_ARGUMENT, "request " + std::to_string(i) + ": its result slot exceeds the pool");
     if (!(arrival_s[i] >= 0.0) || (i > 0 && arrival_s[i] < arrival_s[i - 1]))
       return set_err(EAT_ERR_INVALID_ARGUMENT, "arrival_s must be >= 0 and non-decreasing");
   }

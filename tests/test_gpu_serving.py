@@ -242,6 +242,11 @@ def test_native_request_loop_checks_its_requests():
         with pytest.raises(eat.EatError) as ei:
             sess.serve(g, s, t, a)
         assert ei.value.status == eat.EAT_ERR_INVALID_ARGUMENT
+    small = eat.Session(graphs, pool_bytes=8 * 1024, n_streams=1)  # no room for a 5k-stop slot
+    with pytest.raises(eat.EatError) as ei:
+        small.serve([1], [1], [0], [0.0])
+    assert ei.value.status == eat.EAT_ERR_INVALID_ARGUMENT
+    small.free()
     slot = sess.admit(0, 1, 0)  # an admitted query left in the session
     with pytest.raises(eat.EatError) as ei:
         sess.serve([0], [1], [0], [0.0])
