@@ -73,8 +73,10 @@ def poisson_requests(rate_qps: float, n: int, graph_sizes: Sequence[int], seed: 
 def serve(session, requests: Sequence[Request],
           on_done: Optional[Callable[[Request, int], None]] = None,
           min_batch: int = 64, max_delay_s: float = 50e-6,
-          clock: Callable[[], float] = time.perf_counter) -> ServeReport:
-    """Runs the open-loop request stream to completion; returns latencies."""
+          clock: Callable[[], float] = time.perf_counter, stuck_s: float = 1.0) -> ServeReport:
+    """Runs the open-loop request stream to completion; returns latencies.
+    Raises RuntimeError when a request cannot be admitted for stuck_s seconds
+    while nothing is in flight (its result slot can never fit the pool)."""
     reqs = sorted(requests, key=lambda r: r.arrival)
     n = len(reqs)
     latency = np.zeros(n)
@@ -88,6 +90,7 @@ def serve(session, requests: Sequence[Request],
     done = 0
     i = 0
     t0 = clock()
+    blocked_since = None  # when admission began failing with nothing in flight
     while done < n:
         now = clock() - t0
         while i < n and reqs[i].arrival <= now:
@@ -99,7 +102,15 @@ def serve(session, requests: Sequence[Request],
             slot = session.admit(r.graph, r.s, r.ts)
             if slot is None:
                 busy += 1
+                if inflight:
+                    blocked_since = None
+                elif blocked_since is None:
+                    blocked_since = now
+                elif now - blocked_since > stuck_s:
+                    raise RuntimeError(f"request {r.id} cannot be admitted with nothing in flight: "
+                                       "its result slot does not fit the session's pool")
                 break
+            blocked_since = None
             waiting.popleft()
             inflight[slot] = r
             pending.append((slot, now))

@@ -134,3 +134,19 @@ def test_refused_steps_are_retried_and_every_request_completes():
     assert fake.refused > 0
     assert sum(fake.launches) == 400 and rep.steps == len(fake.launches)
     assert not fake.used
+
+
+def test_a_request_that_can_never_be_admitted_raises():
+    class NeverFits(FakeSession):
+        def admit(self, g, s, ts):
+            return None if g == 1 else super().admit(g, s, ts)
+
+    reqs = [serve.Request(id=0, graph=0, s=1, ts=0, arrival=0.0),
+            serve.Request(id=1, graph=1, s=1, ts=0, arrival=0.0)]
+    ticks = iter(range(10**6))
+    try:
+        serve.serve(NeverFits(capacity=4), reqs, clock=lambda: next(ticks) * 1e-3, stuck_s=0.05)
+    except RuntimeError as e:
+        assert "request 1" in str(e)
+    else:
+        raise AssertionError("serve() returned although request 1 can never be admitted")
