@@ -493,10 +493,10 @@ extern "C" void eat_session_free(eat_session *S) { destroy(S); }
 // admission, steps by the batching policy, completions polled, copied and
 // released.
 // ---------------------------------------------------------------------------
-extern "C" eat_status eat_session_serve(eat_session *S, int32_t n, const int32_t *graph, const int32_t *src,
-                                        const int32_t *ts, const double *arrival_s, int32_t min_batch,
-                                        double max_delay_s, int32_t *const *copy_dst, void *copy_stream,
-                                        double *latency_s, eat_serve_report *rep) {
+static eat_status serve_loop(eat_session *S, int32_t n, const int32_t *graph, const int32_t *src,
+                             const int32_t *ts, const double *arrival_s, int32_t min_batch, double max_delay_s,
+                             int32_t *const *copy_dst, void *copy_stream, double *latency_s,
+                             eat_serve_report *rep) {
   if (!S) return set_err(EAT_ERR_INVALID_ARGUMENT, "session is NULL");
   if (n < 0 || min_batch < 1 || !(max_delay_s >= 0.0))
     return set_err(EAT_ERR_INVALID_ARGUMENT, "n >= 0, min_batch >= 1 and max_delay_s >= 0 are required");
@@ -586,4 +586,16 @@ extern "C" eat_status eat_session_serve(eat_session *S, int32_t n, const int32_t
     rep->wall_s = now_s();
   }
   return EAT_OK;
+}
+
+extern "C" eat_status eat_session_serve(eat_session *S, int32_t n, const int32_t *graph, const int32_t *src,
+                                        const int32_t *ts, const double *arrival_s, int32_t min_batch,
+                                        double max_delay_s, int32_t *const *copy_dst, void *copy_stream,
+                                        double *latency_s, eat_serve_report *rep) {
+  try {
+    return serve_loop(S, n, graph, src, ts, arrival_s, min_batch, max_delay_s, copy_dst, copy_stream, latency_s,
+                      rep);
+  } catch (const std::bad_alloc &) {  // nothing throws across the C ABI
+    return set_err(EAT_ERR_OUT_OF_MEMORY, "host allocation failed in the request loop");
+  }
 }
