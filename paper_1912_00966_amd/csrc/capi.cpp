@@ -832,7 +832,12 @@ extern "C" eat_status eat_batch_create(const eat_graph *const *graphs, int32_t n
                                        const int32_t *q_graph, const int32_t *q_src,
                                        const int32_t *q_ts, int32_t n_q, int32_t *const *arr,
                                        const eat_run_options *ro, eat_batch **out) {
-  return batch_create(graphs, n_graphs, q_graph, q_src, q_ts, nullptr, n_q, arr, ro, out);
+  try {
+    return batch_create(graphs, n_graphs, q_graph, q_src, q_ts, nullptr, n_q, arr, ro, out);
+  } catch (const std::bad_alloc &) {  // nothing throws across the C ABI
+    if (out) *out = nullptr;
+    return set_err(EAT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
 }
 
 extern "C" eat_status eat_batch_create_goal(const eat_graph *const *graphs, int32_t n_graphs,
@@ -843,7 +848,12 @@ extern "C" eat_status eat_batch_create_goal(const eat_graph *const *graphs, int3
     if (out) *out = nullptr;
     return set_err(EAT_ERR_INVALID_ARGUMENT, "q_dst is NULL");
   }
-  return batch_create(graphs, n_graphs, q_graph, q_src, q_ts, q_dst, n_q, arr, ro, out);
+  try {
+    return batch_create(graphs, n_graphs, q_graph, q_src, q_ts, q_dst, n_q, arr, ro, out);
+  } catch (const std::bad_alloc &) {
+    if (out) *out = nullptr;
+    return set_err(EAT_ERR_OUT_OF_MEMORY, "host allocation failed");
+  }
 }
 
 extern "C" eat_status eat_batch_options(const eat_batch *b, eat_run_options *out) {

@@ -345,7 +345,17 @@ extern "C" eat_status eat_session_admit(eat_session *S, int32_t graph, int32_t s
   return EAT_OK;
 }
 
+static eat_status step_impl(eat_session *S, int32_t *n_launched);
+
 extern "C" eat_status eat_session_step(eat_session *S, int32_t *n_launched) {
+  try {
+    return step_impl(S, n_launched);
+  } catch (const std::bad_alloc &) {  // nothing throws across the C ABI
+    return set_err(EAT_ERR_OUT_OF_MEMORY, "host allocation failed in a step");
+  }
+}
+
+static eat_status step_impl(eat_session *S, int32_t *n_launched) {
   if (!S) return set_err(EAT_ERR_INVALID_ARGUMENT, "session is NULL");
   if (n_launched) *n_launched = 0;
   if (S->admitted.empty()) return EAT_OK;
