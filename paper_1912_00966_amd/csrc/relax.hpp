@@ -458,6 +458,11 @@ __device__ __forceinline__ int32_t lds_ld(const int32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// A value every lane of the wave holds alike (read after a barrier, or
+// derived from such values), moved to a scalar register: loops and branches
+// on it become scalar, and addresses built from it use scalar bases.
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // ---------------------------------------------------------------------------
 // Where a query keeps its arrival times.  An "item" names one stop's entry.
 // Each item carries an activity flag: set when the item's arrival improves
@@ -932,10 +937,10 @@ __device__ __forceinline__ void expand_list(const GraphG &G, const Store &S, con
     }
     __syncthreads();  // X and the windows complete
     const unsigned long long xv = __hip_atomic_load(xt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    const int32_t nx = (int32_t)(uint32_t)xv, T = (int32_t)(uint32_t)(xv >> 32);
+    const int32_t nx = uniform((int32_t)(uint32_t)xv), T = uniform((int32_t)(uint32_t)(xv >> 32));
     const int32_t nw = (T + 63) >> 6;
     constexpr int kWaves = B / 64;
-    const int32_t wave = (int32_t)(threadIdx.x >> 6);
+    const int32_t wave = uniform((int32_t)(threadIdx.x >> 6));
     if (nw <= kWin) {
       // Windows: lane i of window w relaxes type k = 64 w + i, of the X entry
       // that holds it: wentry[w] plus the entries starting in (64 w, k].
@@ -1132,8 +1137,12 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
           sh.resume = ngroups;
         }
         __syncthreads();
-        if (sh.wcur >= ngroups) break;  // uniform: read after the barrier
-        const int32_t g0 = sh.first;
+        // The chunk's first group, from before the barrier.  (Not the cursor
+        // itself: a wave that reaches its claims first moves it, and a wave
+        // that read it later could leave the sweep while the others stage a
+        // chunk, so that the waves' barriers would no longer pair up.)
+        const int32_t g0 = uniform(sh.first);
+        if (g0 >= ngroups) break;
         for (;;) {
           int32_t g = 0;
           if (lane == 0) g = atomicAdd(&sh.wcur, 1);
@@ -1174,7 +1183,7 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
           }
         }
         __syncthreads();
-        const int32_t cnt = sh.cnt, st = sh.start;
+        const int32_t cnt = uniform(sh.cnt), st = uniform(sh.start);
         if (tid == 0) sh.wcur = min(sh.wcur, sh.resume);  // read by all after the next barrier
         if (cnt > st) {
           const FList chunk{cur.item + st, cur.beg + st, cur.cnt + st};
@@ -1188,10 +1197,10 @@ __device__ __forceinline__ bool run_rounds(const RunArgs &a, const GraphG &G, co
     if (lane == 0 && wm != INF) atomicMin(&sh.nmin[r3], wm);
     __syncthreads();  // all pushes of the round are in
     // independent reads, one LDS round trip
-    const int32_t over = lds_ld(&sh.over);
-    const bool full = S.full();
-    const int32_t nnv = lds_ld(reinterpret_cast<int32_t *>(&sh.cx[r3]));
-    base = lds_ld(&sh.nmin[r3]);
+    const int32_t over = uniform(lds_ld(&sh.over));
+    const bool full = uniform(S.full() ? 1 : 0) != 0;
+    const int32_t nnv = uniform(lds_ld(reinterpret_cast<int32_t *>(&sh.cx[r3])));
+    base = uniform(lds_ld(&sh.nmin[r3]));
     if (over != 0 || full) {
       qs.rounds += rounds + 1;
       return false;
@@ -1308,7 +1317,7 @@ __global__ __launch_bounds__(B) __attribute__((amdgpu_waves_per_eu(
       sh.reached = 0;
     }
     __syncthreads();
-    const int32_t q = sh.q;
+    const int32_t q = uniform(sh.q);
     if (q >= a.nq) {
       // The last work-group to leave re-arms the shared counters for the next
       // launch of the same batch, so a run is a single kernel launch.
