@@ -281,10 +281,11 @@ typedef struct {
                                  -- two queries share a CU, each with half of its LDS for
                                  the arrival table; 384 -- four per CU, a quarter each;
                                  256 -- six per CU, a sixth each (type windows only:
-                                 threads_per_vertex = 0; graphs of up to 65,536 stops,
-                                 EAT_ERR_UNSUPPORTED above; 256, 384 and 768 with one type per
-                                 lane).  More queries per CU raise throughput when many are
-                                 in flight; 1024 finishes a single long query sooner.
+                                 threads_per_vertex = 0; 256, 384 and 768 with one type per
+                                 lane; a graph whose activity bitmap, one bit per stop, does
+                                 not fit the LDS share: EAT_ERR_UNSUPPORTED, 1024 runs it).
+                                 More queries per CU raise throughput when many are in
+                                 flight; 1024 finishes a single long query sooner.
                                  0 = 1024 */
   int32_t query_order;        /* eat_query_order: the order in which a batch's work-groups
                                  take its queries */

@@ -497,12 +497,6 @@ eat_status make_plan(const eat_run_options *ro, int32_t max_v, int device, Plan 
     return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query 512 or 768 needs threads_per_vertex 0");
   if ((pl->block == kBlockMid || pl->block == kBlockQuarter || pl->block == kBlockSixth) && pl->ub != 1)
     return set_err(EAT_ERR_INVALID_ARGUMENT, "threads_per_query 256, 384 and 768 run one connection type per lane");
-  // Four and six queries per CU run graphs of up to kSmallBlockMaxV stops: two
-  // runs of 384-thread queries on larger graphs faulted the GPU, and the cause
-  // has not been found.
-  if ((pl->block == kBlockQuarter || pl->block == kBlockSixth) && max_v > kSmallBlockMaxV)
-    return set_err(EAT_ERR_UNSUPPORTED, "threads_per_query 256 and 384 run graphs of up to " +
-                                            std::to_string(kSmallBlockMaxV) + " stops");
   pl->window = o.time_window == 0 ? 7200 : (o.time_window < 0 ? 0 : o.time_window);
   if (o.query_order < EAT_ORDER_AUTO || o.query_order > EAT_ORDER_BANDED)
     return set_err(EAT_ERR_INVALID_ARGUMENT, "unknown query order");

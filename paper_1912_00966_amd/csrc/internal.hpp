@@ -49,8 +49,6 @@ eat_status hip_err(hipError_t e, const char *what);
   } while (0)
 
 constexpr size_t kAlign = 256;
-// Largest graph (stops) that 384- and 256-thread queries accept.
-constexpr int32_t kSmallBlockMaxV = 65536;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct DeviceLimits {

@@ -117,6 +117,47 @@ def test_mixed_batch_4096_queries_one_launch():
 
 
 @functools.lru_cache(maxsize=None)
+def _mixed_city(i):
+    """City i of the mixed batch (its generator seed) and 128 of its queries."""
+    n = synth.MIXED_BATCH_SIZES[i]
+    tt = synth.scaled_city(n, 401 + i)
+    q = synth.queries(n, 512, 10401 + i)
+    return tt, q.s[:128], q.ts[:128], eat.graph_from_timetable(tt)
+
+
+@functools.lru_cache(maxsize=None)
+def _mixed_city_scan(i):
+    tt, s, ts, _ = _mixed_city(i)
+    csa = oracle.Csa(tt.u, tt.v, tt.t, tt.lam, tt.n_vertices)
+    n_thr = max(1, min(len(os.sched_getaffinity(0)), 16))
+    with ThreadPoolExecutor(n_thr) as ex:
+        exp = list(ex.map(lambda k: csa.query(int(s[k]), int(ts[k])), range(len(s))))
+    csa.close()
+    return exp
+
+
+@pytest.mark.parametrize("fcap", [0, 64])
+@pytest.mark.parametrize("th,city", [(384, 6), (256, 5)])
+def test_small_work_groups_on_large_cities(th, city, fcap):
+    """Four and six queries per CU (384 and 256 threads) on the mixed batch's
+    200,000- and 100,000-stop cities, 128 queries in one launch, with default
+    lists and with lists of 64 entries (most rounds then sweep the table in
+    chunks): every answer equals the scan's."""
+    tt, s, ts, g = _mixed_city(city)
+    _say(f"{tt.n_vertices} stops, {th} threads, frontier_cap {fcap}")
+    outs = [torch.full((tt.n_vertices,), -7, dtype=torch.int32, device="cuda") for _ in range(len(s))]
+    st = eat.eat_query_batch([g], np.zeros(len(s), np.int32), s, ts, outs, stats=True,
+                             options={"threads_per_query": th, "frontier_cap": fcap})
+    torch.cuda.synchronize()
+    assert all(x["status"] == 0 for x in st)
+    if fcap:
+        assert sum(x["sweep_rounds"] for x in st) > 0
+    exp = _mixed_city_scan(city)
+    for k in range(len(s)):
+        assert np.array_equal(outs[k].cpu().numpy(), exp[k]), (k, int(s[k]), int(ts[k]))
+
+
+@functools.lru_cache(maxsize=None)
 def _lines_1500k():
     """1.5M stops served by 12,000 bus lines (about 23M connections): the stop
     bitmap (188 KB) does not fit the LDS, so slab-mode activity bits live in

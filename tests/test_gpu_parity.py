@@ -274,15 +274,20 @@ def test_512_threads_need_wave_claims():
         assert ei.value.status == eat.EAT_ERR_INVALID_ARGUMENT
 
 
-def test_small_work_groups_refuse_graphs_above_their_limit():
-    """384- and 256-thread queries take graphs of up to 65,536 stops; a larger
-    graph is refused before any launch (arr untouched), alone and in a batch
-    with a small graph; 768 threads run it."""
-    n = 70000
-    big = eat.eat_graph_build(np.array([0, 1]), np.array([1, 2]), np.array([10, 20]), np.array([5, 5]), n)
+def test_small_work_groups_and_the_lds_bitmap_limit():
+    """384- and 256-thread queries run a 70,000-stop graph; a 300,000-stop one,
+    whose activity bitmap does not fit their share of the LDS, is refused
+    before any launch (arr untouched), alone and in a batch with a small
+    graph; 768 threads run it."""
     small = _graph("city-1k", "hybrid")
-    out = torch.full((n,), -7, dtype=torch.int32, device="cuda")
     out_small = torch.full((small.n_vertices,), -7, dtype=torch.int32, device="cuda")
+    mid = eat.eat_graph_build(np.array([0, 1]), np.array([1, 2]), np.array([10, 20]), np.array([5, 5]), 70000)
+    for th in (384, 256):
+        got, _ = _query(mid, 0, 0, threads_per_query=th)
+        assert got[:3].tolist() == [0, 15, 25] and np.all(got[3:] == oracle.INF)
+    n = 300000
+    big = eat.eat_graph_build(np.array([0, 1]), np.array([1, 2]), np.array([10, 20]), np.array([5, 5]), n)
+    out = torch.full((n,), -7, dtype=torch.int32, device="cuda")
     for th in (384, 256):
         with pytest.raises(eat.EatError) as ei:
             eat.eat_query(big, 0, 0, out, options={"threads_per_query": th})
