@@ -382,11 +382,16 @@ def test_batch_city_50k_all_256_queries_bit_exact(layout, headers, threads):
                                   {"threads_per_query": 768, "table_cap": -1}, {"types_per_lane": 2},
                                   {"threads_per_query": 384}, {"threads_per_query": 256},
                                   {"mode": eat.EAT_MODE_TOPOLOGY}, {"mode": eat.EAT_MODE_TOPOLOGY, "time_window": 1800},
-                                  {"mode": eat.EAT_MODE_TOPOLOGY, "threads_per_query": 384, "table_cap": -1}])
+                                  {"mode": eat.EAT_MODE_TOPOLOGY, "threads_per_query": 384, "table_cap": -1},
+                                  {"mode": eat.EAT_MODE_TOPOLOGY, "threads_per_query": 768},
+                                  {"mode": eat.EAT_MODE_TOPOLOGY, "threads_per_query": 256},
+                                  {"mode": eat.EAT_MODE_TOPOLOGY, "threads_per_query": 512, "table_cap": -1}])
 def test_small_lists_overflow_into_sweeps_city_50k(opts):
     """64-entry frontier lists (the smallest): rounds whose pushes overflow the
     list sweep the activity flags in chunks of up to 64 items instead; every
-    answer stays exact, with arrivals in the table or in the slab."""
+    answer stays exact, with arrivals in the table or in the slab.  The
+    topology cases sweep every round, so every work-group size starts many
+    chunks close to the end of its group cursor."""
     tt, q = _workload("city-50k")
     g = _graph("city-50k", "hybrid")
     exp = _expected("city-50k")
